@@ -1,0 +1,307 @@
+"""Pins of the CPU oracle against things other than itself (paper closed
+forms, mpmath, numerical quadrature, FFT brute force, exact invariants).
+
+Each test names the passage of arXiv 2102.02989 it checks.
+"""
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import synth
+from fft_bruteforce import j3c_fft
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------- Boys
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 5, 7, 9, 12])
+def test_boys_vs_mpmath(m):
+    """F_m(T) = gamma(m+1/2, T) / (2 T^{m+1/2}) (lower incomplete gamma)."""
+    mpmath.mp.dps = 40
+    for T in [0.0, 1e-12, 1e-6, 0.3, 1.0, 7.5, 25.0, 39.99, 40.01, 55.0, 120.0, 900.0]:
+        if T == 0.0:
+            ref = mpmath.mpf(1) / (2 * m + 1)
+        else:
+            ref = mpmath.gammainc(m + 0.5, 0, T) / (2 * mpmath.mpf(T) ** (m + 0.5))
+        got = oracle.boys(m, T)
+        assert abs(got - float(ref)) <= 2e-15 * abs(float(ref)), (m, T, got, float(ref))
+
+
+# ---------------------------------------------------- isolated integrals
+def _ss_s_closed(kind, omega, gc, C, ga, A, gb, B):
+    """Closed form of (s|w|ss) for unnormalised 1s primitives (Eqs. S3-S9,
+    prefactor pi^3/(a_P p)^{3/2}; the printed (pi/4)^3 prefactor does not
+    match quadrature).  The caller sets mpmath's working precision."""
+    A, B, C = (mpmath.matrix([mpmath.mpf(x) for x in v]) for v in (A, B, C))
+    ga, gb, gc, omega = (mpmath.mpf(x) for x in (ga, gb, gc, omega))
+    p = ga + gb
+    P = (ga * A + gb * B) / p
+    ab2 = sum((A[i] - B[i]) ** 2 for i in range(3))
+    R = mpmath.sqrt(sum((P[i] - C[i]) ** 2 for i in range(3)))
+    eta1 = mpmath.sqrt(gc * p / (gc + p))
+    eta2 = 1 / mpmath.sqrt(1 / eta1 ** 2 + 1 / omega ** 2)
+
+    def g(eta):
+        if R < mpmath.mpf("1e-30"):
+            return 2 * eta / mpmath.sqrt(mpmath.pi)
+        return mpmath.erf(eta * R) / R
+
+    pref = mpmath.pi ** 3 / (gc * p) ** mpmath.mpf(1.5) * mpmath.exp(-ga * gb / p * ab2)
+    val = {oracle.COUL: g(eta1), oracle.ERF: g(eta2), oracle.ERFC: g(eta1) - g(eta2)}[kind]
+    return pref * val
+
+
+@pytest.mark.parametrize("kind", [oracle.COUL, oracle.ERF, oracle.ERFC])
+def test_ss_s_closed_form(kind):
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        gc, ga, gb = np.exp(rng.uniform(np.log(0.05), np.log(30.0), 3))
+        omega = float(np.exp(rng.uniform(np.log(0.05), np.log(3.0))))
+        A, B, C = rng.normal(size=(3, 3)) * rng.uniform(0.0, 4.0)
+        got = oracle.prim3c(kind, omega, 0, gc, C, 0, ga, A, 0, gb, B)[0, 0, 0]
+        ref = float(_ss_s_closed(kind, omega, gc, C, ga, A, gb, B))
+        # erfc = Coulomb - erf is formed as a difference: error relative to
+        # the Coulomb magnitude
+        scale = max(1.0, abs(float(_ss_s_closed(oracle.COUL, omega, gc, C, ga, A, gb, B))))
+        assert abs(got - ref) <= 2e-14 * scale, (got, ref)
+    # coincident centres: R -> 0 limit
+    z = np.zeros(3)
+    got = oracle.prim3c(kind, 0.4, 0, 0.7, z, 0, 0.9, z, 0, 1.3, z)[0, 0, 0]
+    ref = float(_ss_s_closed(kind, 0.4, 0.7, z, 0.9, z, 1.3, z))
+    assert abs(got - ref) <= 1e-14 * abs(ref)
+
+
+def test_closed_form_vs_qspace_quadrature():
+    """The corrected s-type prefactor pi^3/(a_P p)^{3/2} (Eq. S4 as printed
+    carries (pi/4)^3) agrees with the isolated integral evaluated as a 1-D
+    radial q-space quadrature: (1/2pi^2) int dq 4pi * w~(q) * sin(qR)/(qR) * Fc Fab."""
+    gc, ga, gb, omega = 0.7, 0.6, 0.7, 0.4
+    A = np.array([0.0, 0.0, 0.0]); B = np.array([0.0, 0.0, 0.0]); C = np.array([1.9, 0.0, 0.0])
+    p = ga + gb
+    R = 1.9
+    pref = (math.pi / gc) ** 1.5 * (math.pi / p) ** 1.5
+
+    def integrand(q, attenuated):
+        w = 4 * math.pi / q ** 2 if q > 0 else 0.0
+        if attenuated:
+            w *= 1 - math.exp(-q * q / (4 * omega ** 2))
+        s = math.sin(q * R) / (q * R) if q > 0 else 1.0
+        return q * q / (2 * math.pi ** 2) * w * s * math.exp(-q * q / (4 * gc) - q * q / (4 * p))
+
+    for kind, att in [(oracle.COUL, False), (oracle.ERFC, True)]:
+        quad = pref * integrate.quad(lambda q: integrand(q, att), 0, 80, limit=400, epsabs=1e-15, epsrel=1e-14)[0]
+        got = oracle.prim3c(kind, omega, 0, gc, C, 0, ga, A, 0, gb, B)[0, 0, 0]
+        assert abs(got - quad) <= 1e-12 * abs(quad), (kind, got, quad)
+
+
+def _deriv_coefs(n, alpha):
+    """(x-A)^n g = sum_j c_j d^j/dA^j g for a Gaussian g ~ exp(-alpha (x-A)^2):
+    (x-A)^{n+1} g = (1/2alpha) [d/dA ((x-A)^n g) + n (x-A)^{n-1} g]."""
+    F = [{0: mpmath.mpf(1)}]
+    for k in range(n):
+        nxt = {}
+        for j, c in F[k].items():
+            nxt[j + 1] = nxt.get(j + 1, 0) + c / (2 * alpha)
+        if k >= 1:
+            for j, c in F[k - 1].items():
+                nxt[j] = nxt.get(j, 0) + k * c / (2 * alpha)
+        F.append(nxt)
+    return F[n]
+
+
+def _cart(l):
+    return [(lx, ly, l - lx - ly) for lx in range(l, -1, -1) for ly in range(l - lx, -1, -1)]
+
+
+CLASSES = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (2, 1, 1), (2, 0, 2), (0, 2, 3), (2, 2, 0), (1, 2, 2),
+           (2, 2, 3)]
+
+
+@pytest.mark.parametrize("la,lb,lc", CLASSES)
+def test_higher_l_vs_center_derivatives(la, lb, lc):
+    """Cartesian blocks = centre derivatives of the s-type closed form
+    (x-A)^n e^{-a(x-A)^2} generated from d/dA_x; derivatives by mpmath at 40
+    digits.  Checks the oracle's Obara-Saika recurrences for every class of
+    the benchmark bases (l_AO <= 2, l_aux <= 3) and the erfc operator."""
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(100 + 10 * la + 3 * lb + lc)
+    ga, gb, gc = 0.9, 0.55, 1.3
+    omega = 0.45
+    A = rng.normal(size=3) * 0.8
+    B = rng.normal(size=3) * 0.8
+    C = rng.normal(size=3) * 0.8 + np.array([1.0, 0.5, -0.4])
+    blk = oracle.prim3c(oracle.ERFC, omega, lc, gc, C, la, ga, A, lb, gb, B)
+    scale = np.abs(blk).max()
+
+    def f(*x):
+        return _ss_s_closed(oracle.ERFC, omega, gc, x[6:9], ga, x[0:3], gb, x[3:6])
+
+    x0 = [mpmath.mpf(v) for v in list(A) + list(B) + list(C)]
+    comps = [(ic, ia, ib) for ic in range(len(_cart(lc))) for ia in range(len(_cart(la)))
+             for ib in range(len(_cart(lb)))]
+    nsel = 3 if la + lb + lc >= 6 else 8
+    if len(comps) > nsel:
+        idx = rng.choice(len(comps), nsel, replace=False)
+        comps = [comps[i] for i in idx] + [comps[-1]]
+    for ic, ia, ib in comps:
+        pa, pb, pc = _cart(la)[ia], _cart(lb)[ib], _cart(lc)[ic]
+        coef_lists = [_deriv_coefs(pa[d], mpmath.mpf(ga)) for d in range(3)] + \
+                     [_deriv_coefs(pb[d], mpmath.mpf(gb)) for d in range(3)] + \
+                     [_deriv_coefs(pc[d], mpmath.mpf(gc)) for d in range(3)]
+        total = mpmath.mpf(0)
+
+        def rec(i, orders, c):
+            nonlocal total
+            if i == 9:
+                total += c * mpmath.diff(f, x0, tuple(orders))
+                return
+            for j, cj in coef_lists[i].items():
+                rec(i + 1, orders + [j], c * cj)
+
+        rec(0, [], mpmath.mpf(1))
+        ref = float(total)
+        assert abs(blk[ic, ia, ib] - ref) <= 1e-12 * max(scale, 1e-3), (ic, ia, ib, blk[ic, ia, ib], ref)
+
+
+# ------------------------------------------------------ Fourier transforms
+def test_fourier_transforms_vs_quadrature():
+    """Aux and pair transforms (used in Eqs. M10, M11) and overlaps (Eq. M13c)
+    against 1-D numerical quadrature of each Cartesian factor."""
+    rng = np.random.default_rng(3)
+
+    def q1(f):
+        re = integrate.quad(lambda x: f(x).real, -40, 40, limit=400, epsabs=1e-15)[0]
+        im = integrate.quad(lambda x: f(x).imag, -40, 40, limit=400, epsabs=1e-15)[0]
+        return re + 1j * im
+
+    for l in [0, 1, 2, 3]:
+        g = float(rng.uniform(0.3, 3.0))
+        C = rng.normal(size=3)
+        q = rng.normal(size=3) * 2.0
+        for comp, pw in enumerate(_cart(l)):
+            ref = 1.0 + 0j
+            for d in range(3):
+                ref *= q1(lambda x: (x - C[d]) ** pw[d] * np.exp(-g * (x - C[d]) ** 2 - 1j * q[d] * x))
+            got = oracle.prim_ft(l, comp, g, C, q)
+            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+    for la, lb in [(0, 0), (1, 0), (1, 2), (2, 2)]:
+        ga, gb = rng.uniform(0.3, 3.0, 2)
+        A, B = rng.normal(size=(2, 3))
+        q = rng.normal(size=3) * 1.5
+        for ia, pa in enumerate(_cart(la)):
+            for ib, pb in enumerate(_cart(lb)):
+                ref = 1.0 + 0j
+                ovl = 1.0
+                for d in range(3):
+                    fx = lambda x, d=d: ((x - A[d]) ** pa[d] * (x - B[d]) ** pb[d] *
+                                         np.exp(-ga * (x - A[d]) ** 2 - gb * (x - B[d]) ** 2))
+                    ref *= q1(lambda x, fx=fx, d=d: fx(x) * np.exp(-1j * q[d] * x))
+                    ovl *= q1(lambda x, fx=fx: fx(x) + 0j).real
+                got = oracle.pair_ft(la, ia, ga, A, lb, ib, gb, B, q)
+                assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+                assert abs(oracle.overlap(la, ia, ga, A, lb, ib, gb, B) - ovl) <= 1e-12 * max(1.0, abs(ovl))
+
+
+# ------------------------------------------------------ periodic, absolute
+def test_periodic_gamma_vs_fft_bruteforce():
+    """Full G=0-removed j3c (SR - G0 + LR, Eqs. M10-M13) at Gamma against a
+    real-space-grid FFT evaluation that uses no analytic integral, on a
+    triclinic 2-atom cell with s/p/d AO and s/p/d/f aux shells."""
+    p = synth.tiny_problem(kmesh=(1, 1, 1), omega=0.7)
+    ref = j3c_fft(p, ngrid=28)
+    got = oracle.j3c(p, cut=1e-17)
+    assert np.abs(got - ref).max() <= 1e-9, np.abs(got - ref).max()
+
+
+@pytest.mark.slow
+def test_periodic_kmesh_vs_fft_bruteforce():
+    """As above on a 2x1x1 mesh, all ordered k-pairs: pins the Bloch phase
+    convention (Eq. M1 -> e^{+ik2.n} in Eq. M11), the q = G + k12 set and the
+    k1 = k2 restriction of the G=0 term."""
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.9)
+    ref = j3c_fft(p, ngrid=26, all_pairs=True)
+    got = oracle.j3c(p, all_pairs=True, cut=1e-17)
+    assert np.abs(got - ref).max() <= 1e-9, np.abs(got - ref).max()
+
+
+# ------------------------------------------------------ invariants
+def test_omega_independence_gamma():
+    """SR + LR - G0 does not depend on the range-separation parameter
+    (Eq. M9 splits 1/r exactly; Eqs. M10 and M12 evaluate the two parts)."""
+    p = synth.config1()
+    sel = [0, 4, 6, 7, 13]  # s, p, d aux on both atoms
+    V1 = oracle.j3c(p, omega=0.25, aux_shells=sel)
+    V2 = oracle.j3c(p, omega=0.5, aux_shells=sel)
+    assert np.abs(V1 - V2).max() <= 1e-10, np.abs(V1 - V2).max()
+    assert np.abs(V1).max() > 0.1
+
+
+def test_omega_independence_kmesh_and_hermiticity():
+    """omega-independence with k1 != k2 (the LR phase sign and the G=0 term
+    only on k1 = k2), Hermiticity V^{k2k1}_{P nu mu} = conj V^{k1k2}_{P mu nu},
+    and a real, mu<->nu symmetric Gamma block (Eq. M6, M1)."""
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.8, diffuse=False)
+    V1 = oracle.j3c(p, omega=0.8, all_pairs=True)
+    V2 = oracle.j3c(p, omega=1.2, all_pairs=True)
+    assert np.abs(V1 - V2).max() <= 1e-10, np.abs(V1 - V2).max()
+    nk = 2
+    Vk = V1.reshape(nk, nk, *V1.shape[1:])
+    herm = np.abs(Vk - np.conj(Vk.transpose(1, 0, 2, 4, 3))).max()
+    assert herm <= 1e-12, herm
+    g = Vk[0, 0]
+    assert np.abs(g.imag).max() <= 1e-13
+    assert np.abs(g - g.transpose(0, 2, 1)).max() <= 1e-12
+
+
+def test_lattice_translation_phase():
+    """Moving atom 1 by a lattice vector L multiplies the block by
+    e^{+ik1.L} (AO mu on it), e^{-ik2.L} (AO nu on it), e^{+ik12.L} (aux P on it)."""
+    p = synth.tiny_problem(kmesh=(1, 1, 2), omega=1.0, diffuse=False)
+    V = oracle.j3c(p, all_pairs=True)
+    L = p.cell.lattice[0] * 1 - p.cell.lattice[2]
+    q = synth.tiny_problem(kmesh=(1, 1, 2), omega=1.0, diffuse=False)
+    q.cell.coords = q.cell.coords.copy()
+    q.cell.coords[1] += L
+    W = oracle.j3c(q, all_pairs=True)
+    ks = oracle.kpoints(p)
+    on1_ao = np.repeat(p.basis.shell_atom == 1, [synth.cart_count(l) for l in p.basis.shell_l])
+    on1_ax = np.repeat(p.aux.shell_atom == 1, [synth.cart_count(l) for l in p.aux.shell_l])
+    for t, (k1, k2) in enumerate(oracle.kpair_list(p.kmesh, all_pairs=True)):
+        k12 = ks[k2] - ks[k1]
+        ph = (np.exp(1j * on1_ax * (k12 @ L))[:, None, None] * np.exp(1j * on1_ao * (ks[k1] @ L))[None, :, None] *
+              np.exp(-1j * on1_ao * (ks[k2] @ L))[None, None, :])
+        assert np.abs(W[t] - V[t] * ph).max() <= 1e-11
+
+
+def test_truncation_convergence():
+    """Tightening the oracle's per-term cutoff changes nothing above 1e-11
+    (SI: screening error controlled by epsilon)."""
+    p = synth.config1(omega=0.3)
+    sel = [0, 6]
+    V1 = oracle.j3c(p, aux_shells=sel, cut=1e-14)
+    V2 = oracle.j3c(p, aux_shells=sel, cut=1e-16)
+    V3 = oracle.j3c(p, aux_shells=sel, cut=1e-18)
+    assert np.abs(V1 - V3).max() <= 2e-11
+    assert np.abs(V2 - V3).max() <= 2e-13
+
+
+# ------------------------------------------------------ bookkeeping
+def test_table_s1_nk12_golden():
+    """N_k12 column of Table S1: unique k2 - k1 up to inversion."""
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(GOLDEN, "table_s1_nk12.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for n, nk, nk12 in rows:
+        assert n ** 3 == nk
+        assert oracle.unique_k12_count(n) == nk12
+        assert ((2 * n - 1) ** 3 + 1) // 2 == nk12
+
+
+def test_kpair_counts():
+    assert oracle.nkpairs((2, 2, 2)) == 36
+    assert [oracle.nkpairs((n, n, n)) for n in range(1, 6)] == [1, 36, 378, 2080, 7875]
