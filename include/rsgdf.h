@@ -1,0 +1,157 @@
+/*
+ * rsgdf.h -- C ABI of the MI355X (gfx950) range-separated Gaussian density
+ * fitting three-center integral library (librsgdf.so).
+ *
+ * Computes the periodic three-center Coulomb metric integrals
+ *     V_{P mu nu}^{k1 k2} = (chi_P^{k12 *} | 1/r | rho_{mu nu}^{k1 k2})
+ * of Eq. (M6) of Ye & Berkelbach, "Fast periodic Gaussian density fitting by
+ * range separation" (arXiv 2102.02989), with the G = 0 (q = 0) component
+ * removed as in Eq. (M10), by splitting 1/r into erfc(w r)/r + erf(w r)/r
+ * (Eq. M9):
+ *   short range : real-space double lattice sum, Eqs. (M12), (M13a), folded
+ *                 to k-point pairs through Born-von Karman cells (Eq. M14),
+ *                 screened with the bounds of the Supplementary Material
+ *                 (Eqs. S14, S23-S27), minus the G = 0 term of Eq. (M12);
+ *   long range  : reciprocal-space sum of Eq. (M10) over q = G + k12 with
+ *                 exp(-|q|^2/4w^2) >= g_thresh, using analytic Fourier
+ *                 transforms of the AO pair densities (Eq. M11).
+ *
+ * Units: bohr and hartree atomic units.  All arrays are row-major.
+ *
+ * Conventions
+ *   - Bloch functions phi^k(r) = sum_m e^{i k.m} phi(r - m) (Eq. M1).
+ *   - k-mesh: Gamma-centred k_j = sum_i (j_i / n_i) b_i, B = 2 pi A^{-T},
+ *     linear index j = (j1 n2 + j2) n3 + j3.
+ *   - k-pairs: only k1 <= k2, in row-major upper-triangle order
+ *     (for k1 in 0..Nk-1, for k2 in k1..Nk-1).  The other half follows from
+ *     V_{P nu mu}^{k2 k1} = conj(V_{P mu nu}^{k1 k2}).
+ *   - Functions follow shell order; Cartesian components within a shell are
+ *     x-power descending, then y-power descending (xx, xy, xz, yy, yz, zz).
+ *   - Coefficients multiply bare Cartesian monomials
+ *     (x-Ax)^i (y-Ay)^j (z-Az)^k exp(-a |r-A|^2); normalisation is the
+ *     caller's choice.
+ *   - Output: complex128, layout [nkpair][naux][nao][nao], interleaved
+ *     (re, im) doubles.
+ *
+ * Ownership: every input is read-only and may be freed after the call
+ * returns.  The output buffer is owned by the caller.  The library allocates
+ * its device scratch during the call and frees it before returning.
+ *
+ * Errors: functions return RSGDF_OK (0) or a negative code; the message of the
+ * last error on the calling thread is returned by rsgdf_last_error().
+ */
+#ifndef RSGDF_H
+#define RSGDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSGDF_OK 0
+#define RSGDF_EINVAL (-1)      /* invalid argument (shapes, l, exponents, mesh, omega, thresh, NaN) */
+#define RSGDF_ESIZE (-2)       /* output capacity smaller than rsgdf_j3c_nbytes(); nothing written  */
+#define RSGDF_ENOMEM (-3)      /* device scratch allocation failed                                  */
+#define RSGDF_EHIP (-4)        /* HIP runtime error; output contents undefined                      */
+#define RSGDF_EUNSUPPORTED (-5) /* valid request outside what this build implements                 */
+
+/* maximum angular momenta of this build */
+#define RSGDF_MAX_L_AO 2
+#define RSGDF_MAX_L_AUX 3
+
+/* long-range G-space contraction precision */
+#define RSGDF_FP64 0   /* plain: FP64 everywhere                                    */
+#define RSGDF_FP32 1   /* LR GEMM operands and accumulation in FP32                  */
+#define RSGDF_BF16X3 2 /* LR GEMM as three BF16 MFMA products, FP32 accumulation     */
+
+/* short-range image screening */
+#define RSGDF_SCREEN_RIGOROUS 0 /* Supplementary-Material bounds (Eqs. S14, S23-S27) */
+#define RSGDF_SCREEN_LEARNED 1  /* MLP predictor with the rigorous bound as fallback  */
+
+/* parts bit mask (for phase-by-phase checks; the default computes all) */
+#define RSGDF_PART_SR 1 /* real-space erfc lattice sum, folded                     */
+#define RSGDF_PART_G0 2 /* minus pi/(Omega w^2) S_P S_{mu nu}(k) on k1 == k2       */
+#define RSGDF_PART_LR 4 /* reciprocal-space erf part                               */
+#define RSGDF_PART_ALL 7
+
+typedef struct {
+  double lattice[9];     /* rows a1, a2, a3 (bohr); |det| > 0                       */
+  int32_t natm;          /* >= 1                                                     */
+  const double *coords;  /* host, [natm][3] (bohr)                                   */
+} rsgdf_cell;
+
+typedef struct {
+  int32_t nshell;              /* >= 1                                                 */
+  const int32_t *shell_atom;   /* host, [nshell], 0 <= atom < natm                     */
+  const int32_t *shell_l;      /* host, [nshell], 0..RSGDF_MAX_L_AO / _AUX             */
+  const int32_t *shell_nprim;  /* host, [nshell], 1..16                                */
+  const int32_t *shell_ptr;    /* host, [nshell], offset of the shell's primitives     */
+  const double *exps;          /* host, exponents > 0                                  */
+  const double *coefs;         /* host, raw contraction coefficients                   */
+} rsgdf_basis;
+
+typedef struct {
+  double g_thresh;       /* keep q with exp(-|q|^2/4w^2) >= g_thresh; <= 0 -> 1e-2*thresh   */
+  int32_t lr_precision;  /* RSGDF_FP64 | RSGDF_FP32 | RSGDF_BF16X3                          */
+  int32_t screening;     /* RSGDF_SCREEN_RIGOROUS | RSGDF_SCREEN_LEARNED                    */
+  int32_t parts;         /* RSGDF_PART_* mask; 0 -> RSGDF_PART_ALL                          */
+  int32_t sr_slices;     /* lanes cooperating on one (k-cell pair) unit; 0 -> automatic     */
+  const char *mlp_weights; /* learned screening weights (path) or NULL                      */
+  double mlp_margin;     /* log10 margin added to the learned prediction                    */
+} rsgdf_options;
+
+typedef struct rsgdf_stats {
+  double t_plan_ms;      /* host planning (basis packing, screening bounds, image lists)   */
+  double t_sr_ms;        /* short-range lattice-sum kernels                                 */
+  double t_fold_ms;      /* Bloch fold + G = 0 correction                                   */
+  double t_lr_ms;        /* aux and pair transforms + G-space contraction                   */
+  double t_total_ms;     /* wall time of the call                                           */
+  int64_t n_sr_terms;    /* evaluated (aux prim, AO prim a, AO prim b, image pair) tuples   */
+  int64_t n_sr_shell_terms; /* kept (aux shell, AO shell pair, image pair) terms            */
+  int64_t n_sr_candidates;  /* image pairs tested by the screening                          */
+  int64_t n_lr_terms;    /* (primitive pair, image, q) transform evaluations                */
+  int64_t n_g_total;     /* q vectors summed over the folded k12 classes                    */
+  int64_t n_triplets;    /* (aux shell, AO shell pair) work items                           */
+  int64_t n_aux_batches; /* aux-shell batches used to bound scratch memory                  */
+  int64_t bytes_out;     /* output bytes written                                            */
+  double sr_flops;       /* algorithmic FP64 operations of the SR kernels (static counts)   */
+} rsgdf_stats;
+
+typedef struct {
+  void *data;              /* complex128 [nkpair][naux][nao][nao]                           */
+  int64_t capacity_bytes;  /* size of data in bytes                                         */
+  int32_t on_device;       /* 1: data is device memory on the current HIP device;
+                              0: host memory (the call stages through a device buffer)    */
+  void *stream;            /* hipStream_t to run on, or NULL for the null stream           */
+  int64_t nkpair, naux, nao; /* filled on success                                          */
+  rsgdf_stats *stats;      /* optional, filled on success                                   */
+} rsgdf_out;
+
+/* Bytes needed for the output of rsgdf_build_j3c; < 0 on invalid input. */
+int64_t rsgdf_j3c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                         const int32_t kmesh[3]);
+
+/* V_{P mu nu}^{k1 k2} for all k1 <= k2 (Eq. M6 with the G = 0 term removed),
+ * FP64, rigorous screening at precision thresh (Eqs. S14, S23-S27), with
+ * g_thresh = 1e-2 * thresh.  Synchronous on out->stream.
+ * omega > 0 (bohr^-1) is the range-separation parameter of Eq. (M9). */
+int rsgdf_build_j3c(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                    const int32_t kmesh[3], double omega, double thresh, rsgdf_out *out);
+
+/* As rsgdf_build_j3c with explicit options (NULL = defaults). */
+int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                       const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                       rsgdf_out *out);
+
+/* Message of the last error on this thread ("" if none). */
+const char *rsgdf_last_error(void);
+
+/* Library version string. */
+const char *rsgdf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSGDF_H */

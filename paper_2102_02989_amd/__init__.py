@@ -1,0 +1,22 @@
+"""MI355X (gfx950) range-separated Gaussian density fitting three-center
+integrals (Ye & Berkelbach, arXiv 2102.02989).
+
+The compute path is the native library ``librsgdf.so`` (HIP kernels behind a
+C ABI, see ``include/rsgdf.h``); this package only marshals arguments.
+"""
+from .rsgdf import (  # noqa: F401
+    PART_ALL,
+    PART_G0,
+    PART_LR,
+    PART_SR,
+    FP64,
+    FP32,
+    BF16X3,
+    RsgdfError,
+    build_j3c,
+    j3c_nbytes,
+    library,
+    library_path,
+    nkpairs,
+    version,
+)

@@ -1,0 +1,1030 @@
+// capi.cpp -- C ABI and host planner of librsgdf (see include/rsgdf.h).
+//
+// The planner packs the bases, builds the lattice / k-mesh / Born-von Karman
+// tables, evaluates the short-range screening bounds of the Supplementary
+// Material per (aux shell, AO shell pair) (Eqs. S14, S15, S19, S23-S25),
+// enumerates the pair lattice images, builds the G-vector sets of the
+// long-range part per folded k12 (Eq. M10), uploads these tables and runs
+// the kernels on the caller's stream:
+//   per aux batch:  sr3c (SR lattice sums into BvK bins) -> fold (+ G = 0 term)
+//   then:           aux transforms, per k12 class and q chunk: pair transforms
+//                   -> G-space contraction accumulated into the output.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/rsgdf.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace rsgdf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail(RSGDF_EHIP, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call); \
+  } while (0)
+
+// RAII device buffer
+struct DBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) {
+    n = bytes;
+    if (bytes == 0) bytes = 16;
+    return hipMalloc(&p, bytes);
+  }
+  template <class T>
+  T *as() const {
+    return reinterpret_cast<T *>(p);
+  }
+};
+
+template <class T>
+hipError_t upload(DBuf &b, const std::vector<T> &v, hipStream_t s) {
+  hipError_t e = b.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int ncart_h(int l) { return (l + 1) * (l + 2) / 2; }
+
+double dfact_odd(int l) {  // (2l-1)!!
+  double r = 1.0;
+  for (int k = 2 * l - 1; k > 1; k -= 2) r *= k;
+  return r;
+}
+
+// ------------------------------------------------------------- validation
+int validate_basis(const rsgdf_basis *b, int natm, int lmax, const char *what) {
+  if (!b || b->nshell < 1 || !b->shell_atom || !b->shell_l || !b->shell_nprim || !b->shell_ptr || !b->exps ||
+      !b->coefs)
+    return fail(RSGDF_EINVAL, std::string(what) + ": null or empty basis");
+  for (int s = 0; s < b->nshell; ++s) {
+    if (b->shell_atom[s] < 0 || b->shell_atom[s] >= natm)
+      return fail(RSGDF_EINVAL, std::string(what) + ": shell atom index out of range");
+    if (b->shell_l[s] < 0) return fail(RSGDF_EINVAL, std::string(what) + ": negative angular momentum");
+    if (b->shell_l[s] > lmax)
+      return fail(RSGDF_EUNSUPPORTED, std::string(what) + ": angular momentum above this build's maximum");
+    if (b->shell_nprim[s] < 1 || b->shell_nprim[s] > 16)
+      return fail(RSGDF_EINVAL, std::string(what) + ": nprim must be in 1..16");
+    if (b->shell_ptr[s] < 0) return fail(RSGDF_EINVAL, std::string(what) + ": negative primitive offset");
+    for (int k = 0; k < b->shell_nprim[s]; ++k) {
+      const double a = b->exps[b->shell_ptr[s] + k], c = b->coefs[b->shell_ptr[s] + k];
+      if (!(a > 0.0) || !std::isfinite(a)) return fail(RSGDF_EINVAL, std::string(what) + ": exponents must be > 0");
+      if (!std::isfinite(c)) return fail(RSGDF_EINVAL, std::string(what) + ": non-finite coefficient");
+    }
+  }
+  return RSGDF_OK;
+}
+
+int64_t nfunc(const rsgdf_basis *b) {
+  int64_t n = 0;
+  for (int s = 0; s < b->nshell; ++s) n += ncart_h(b->shell_l[s]);
+  return n;
+}
+
+struct Lat {
+  Lattice L;
+  double an[3], bn[3];
+};
+
+int make_lattice(const rsgdf_cell *cell, const int32_t *kmesh, Lat &lt) {
+  const double *a = cell->lattice;
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(a[i])) return fail(RSGDF_EINVAL, "non-finite lattice");
+  const double c0[3] = {a[4] * a[8] - a[5] * a[7], a[5] * a[6] - a[3] * a[8], a[3] * a[7] - a[4] * a[6]};
+  const double det = a[0] * c0[0] + a[1] * c0[1] + a[2] * c0[2];
+  if (!(std::fabs(det) > 1e-8)) return fail(RSGDF_EINVAL, "singular lattice");
+  const double c1[3] = {a[7] * a[2] - a[8] * a[1], a[8] * a[0] - a[6] * a[2], a[6] * a[1] - a[7] * a[0]};
+  const double c2[3] = {a[1] * a[5] - a[2] * a[4], a[2] * a[3] - a[0] * a[5], a[0] * a[4] - a[1] * a[3]};
+  for (int i = 0; i < 9; ++i) lt.L.a[i] = a[i];
+  for (int j = 0; j < 3; ++j) {
+    lt.L.b[j] = 2.0 * kPi * c0[j] / det;
+    lt.L.b[3 + j] = 2.0 * kPi * c1[j] / det;
+    lt.L.b[6 + j] = 2.0 * kPi * c2[j] / det;
+  }
+  lt.L.vol = std::fabs(det);
+  for (int d = 0; d < 3; ++d) {
+    if (kmesh[d] < 1 || kmesh[d] > 64) return fail(RSGDF_EINVAL, "kmesh entries must be in 1..64");
+    lt.L.n[d] = kmesh[d];
+    lt.an[d] = std::sqrt(a[3 * d] * a[3 * d] + a[3 * d + 1] * a[3 * d + 1] + a[3 * d + 2] * a[3 * d + 2]);
+    const double *b = lt.L.b + 3 * d;
+    lt.bn[d] = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  }
+  lt.L.nk = kmesh[0] * kmesh[1] * kmesh[2];
+  lt.L.pad = 0;
+  return RSGDF_OK;
+}
+
+// ------------------------------------------------------------- Boys table
+// For each order L <= kMaxL and unit interval [i, i+1) of T < kBoysSwitch, the
+// Taylor coefficients of F_L about the interval centre Tc:
+//   F_L(Tc + u) = sum_j (-1)^j F_{L+j}(Tc) u^j / j!   (dF_n/dT = -F_{n+1}).
+// F_n(Tc) come from the power series e^{-T} sum_k (2T)^k / ((2n+1)(2n+3)...(2n+2k+1))
+// at a high order in extended precision and the downward recursion
+// F_n = (2T F_{n+1} + e^{-T}) / (2n+1).
+const std::vector<double> &boys_poly_table() {
+  static std::vector<double> tab;
+  if (!tab.empty()) return tab;
+  const int nc = kBoysPolyDeg + 1;
+  tab.resize((size_t)(kMaxL + 1) * kBoysIntervals * nc);
+  const int nmax = kMaxL + kBoysPolyDeg;
+  const int ntop = nmax + 40;
+  std::vector<long double> F(ntop + 1);
+  for (int i = 0; i < kBoysIntervals; ++i) {
+    const long double T = (long double)i + 0.5L;
+    long double term = 1.0L / (2 * ntop + 1), sum = term;
+    for (int k = 1; k < 10000; ++k) {
+      term *= 2.0L * T / (2 * ntop + 2 * k + 1);
+      sum += term;
+      if (term < 1e-24L * sum) break;
+    }
+    const long double e = expl(-T);
+    F[ntop] = e * sum;
+    for (int n = ntop - 1; n >= 0; --n) F[n] = (2.0L * T * F[n + 1] + e) / (2 * n + 1);
+    for (int L = 0; L <= kMaxL; ++L) {
+      long double fact = 1.0L;
+      for (int j = 0; j < nc; ++j) {
+        if (j > 0) fact *= j;
+        const long double c = ((j & 1) ? -1.0L : 1.0L) * F[L + j] / fact;
+        tab[((size_t)L * kBoysIntervals + i) * nc + j] = (double)c;
+      }
+    }
+  }
+  return tab;
+}
+
+// ------------------------------------------------------------- screening
+struct Screen {
+  double vol, dR, eps, omega;
+  double ncell_nf, r0;
+  double N(double R) const {  // N_cell(R, R+dR), Eq. S19
+    return (R > r0) ? 4.0 * kPi / vol * 2.0 * (R + dR) * (R + dR) * dR : ncell_nf;
+  }
+};
+
+double f_sr(double R, double eta1, double eta2) {  // Eq. S7
+  if (R < 1e-12) return 2.0 * (eta1 - eta2) / std::sqrt(kPi);
+  return (std::erf(eta1 * R) - std::erf(eta2 * R)) / R;
+}
+
+// largest R > 0 with K exp(-eta^2 R^2)/R >= eps (Eq. S14); the left side is decreasing
+double solve_rc(double K, double eta, double eps) {
+  auto g = [&](double R) { return std::log(K) - eta * eta * R * R - std::log(R) - std::log(eps); };
+  double lo = 1e-8, hi = 1.0;
+  if (g(lo) < 0) return lo;
+  while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
+  for (int it = 0; it < 80; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (g(mid) > 0) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
+// largest x with NF * x exp(-beta x^2) >= eps, or 0 (Eq. S23)
+double solve_r12(double NF, double beta, double eps) {
+  const double xs = 1.0 / std::sqrt(2.0 * beta);
+  if (!(NF > 0.0) || NF * xs * std::exp(-0.5) < eps) return 0.0;
+  auto g = [&](double x) { return std::log(NF) + std::log(x) - beta * x * x - std::log(eps); };
+  double lo = xs, hi = 2.0 * xs;
+  while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
+  for (int it = 0; it < 80; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (g(mid) > 0) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 64 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next(0);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (;;) {
+        const int64_t i0 = next.fetch_add(64);
+        if (i0 >= n) break;
+        for (int64_t i = i0; i < std::min(n, i0 + 64); ++i) f(i);
+      }
+    });
+  for (auto &t : th) t.join();
+}
+
+struct HostPlan {
+  Lat lt;
+  std::vector<Shell> ao, ax;
+  std::vector<double> ao_exp, ao_coef, ao_c1s, ax_exp, ax_coef, ax_c1s;
+  std::vector<Pair> pairs;
+  std::vector<int32_t> cls_off, nsr;
+  std::vector<double> img;
+  std::vector<double> rc_t;  // [naux_shell][npair] Eq. S14 bound
+  std::vector<double> amp_t; // [naux_shell][npair] 1s-model amplitude
+  int64_t nao = 0, naux = 0;
+  Screen scr;
+  // k-points
+  std::vector<double> kvec;     // [nk][3]
+  std::vector<int32_t> kp1, kp2;
+};
+
+int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis *ax, const int32_t *kmesh,
+               double omega, double thresh, HostPlan &hp) {
+  int rc = make_lattice(cell, kmesh, hp.lt);
+  if (rc) return rc;
+  const Lattice &L = hp.lt.L;
+  const int nk = L.nk;
+  // shells
+  auto pack = [](const rsgdf_basis *b, const double *coords, std::vector<Shell> &sh, std::vector<double> &ex,
+                 std::vector<double> &cf, std::vector<double> &c1s) {
+    int64_t foff = 0;
+    for (int s = 0; s < b->nshell; ++s) {
+      Shell x{};
+      const double *C = coords + 3 * b->shell_atom[s];
+      x.x = C[0];
+      x.y = C[1];
+      x.z = C[2];
+      x.l = b->shell_l[s];
+      x.nprim = b->shell_nprim[s];
+      x.pptr = (int32_t)ex.size();
+      x.foff = (int32_t)foff;
+      foff += ncart_h(x.l);
+      double amin = 1e300, cmin = 0.0;
+      for (int k = 0; k < x.nprim; ++k) {
+        const double a = b->exps[b->shell_ptr[s] + k], c = b->coefs[b->shell_ptr[s] + k];
+        ex.push_back(a);
+        cf.push_back(c);
+        // 1s function with the L2 norm of the x^l component of this primitive
+        const double c1 = std::fabs(c) * std::sqrt(dfact_odd(x.l) / std::pow(4.0 * a, x.l));
+        c1s.push_back(c1);
+        if (a < amin) {
+          amin = a;
+          cmin = c1;
+        }
+      }
+      x.a_d = amin;
+      x.c_d = cmin;
+      sh.push_back(x);
+    }
+    return foff;
+  };
+  hp.nao = pack(bs, cell->coords, hp.ao, hp.ao_exp, hp.ao_coef, hp.ao_c1s);
+  hp.naux = pack(ax, cell->coords, hp.ax, hp.ax_exp, hp.ax_coef, hp.ax_c1s);
+
+  // k-points and pairs
+  hp.kvec.resize(3 * nk);
+  for (int j0 = 0; j0 < L.n[0]; ++j0)
+    for (int j1 = 0; j1 < L.n[1]; ++j1)
+      for (int j2 = 0; j2 < L.n[2]; ++j2) {
+        const int k = (j0 * L.n[1] + j1) * L.n[2] + j2;
+        for (int d = 0; d < 3; ++d)
+          hp.kvec[3 * k + d] = (double)j0 / L.n[0] * L.b[d] + (double)j1 / L.n[1] * L.b[3 + d] +
+                               (double)j2 / L.n[2] * L.b[6 + d];
+      }
+  for (int k1 = 0; k1 < nk; ++k1)
+    for (int k2 = k1; k2 < nk; ++k2) {
+      hp.kp1.push_back(k1);
+      hp.kp2.push_back(k2);
+    }
+
+  // N_cell model (Eq. S19): N^NF = lattice points within 3 Omega^{1/3}
+  Screen &S = hp.scr;
+  S.vol = L.vol;
+  S.dR = 1.0;
+  S.eps = thresh;
+  S.omega = omega;
+  {
+    const double rnf = 3.0 * std::cbrt(L.vol);
+    int w[3];
+    for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(rnf * hp.lt.bn[d] / (2.0 * kPi)) + 1;
+    int64_t cnt = 0;
+    for (int i = -w[0]; i <= w[0]; ++i)
+      for (int j = -w[1]; j <= w[1]; ++j)
+        for (int k = -w[2]; k <= w[2]; ++k) {
+          double v[3];
+          for (int d = 0; d < 3; ++d) v[d] = i * L.a[d] + j * L.a[3 + d] + k * L.a[6 + d];
+          if (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] <= rnf * rnf) ++cnt;
+        }
+    S.ncell_nf = (double)cnt;
+    S.r0 = std::sqrt(S.ncell_nf * L.vol / (8.0 * kPi * S.dR)) - S.dR;
+  }
+
+  // AO shell pairs, oriented l(sa) >= l(sb)
+  const int nsh = (int)hp.ao.size();
+  for (int i = 0; i < nsh; ++i)
+    for (int j = i; j < nsh; ++j) {
+      Pair p{};
+      if (hp.ao[i].l >= hp.ao[j].l) {
+        p.sa = i;
+        p.sb = j;
+      } else {
+        p.sa = j;
+        p.sb = i;
+      }
+      p.diag = (i == j);
+      const double a1 = hp.ao[p.sa].a_d, a2 = hp.ao[p.sb].a_d;
+      p.beta_d = a1 * a2 / (a1 + a2);
+      hp.pairs.push_back(p);
+    }
+  const int npair = (int)hp.pairs.size();
+
+  // Per pair: S_h (Eq. S15, eps' = 1e-4) and R12min (Eq. S25) from the
+  // eps'-truncated image sum of h = exp(-beta R12^2).  The truncation is taken
+  // relative to the largest term (h >= eps' h_max), so a pair whose nearest
+  // image already has h < eps' keeps its leading terms.
+  const double epsp = 1e-4;
+  std::vector<double> Sh(npair);
+  parallel_for(npair, [&](int64_t ip) {
+    Pair &p = hp.pairs[ip];
+    const Shell &A = hp.ao[p.sa], &B = hp.ao[p.sb];
+    const double beta = p.beta_d;
+    const double AB[3] = {A.x - B.x, A.y - B.y, A.z - B.z};
+    const double dab = std::sqrt(AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2]);
+    const double rmax = dab + std::sqrt(std::log(1.0 / epsp) / beta) + 1.0;
+    int w[3];
+    for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil((rmax + 1e-9) * hp.lt.bn[d] / (2.0 * kPi)) + 2;
+    std::vector<double> r12all;
+    for (int i = -w[0]; i <= w[0]; ++i)
+      for (int j = -w[1]; j <= w[1]; ++j)
+        for (int k = -w[2]; k <= w[2]; ++k) {
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const double v = AB[d] - (i * L.a[d] + j * L.a[3 + d] + k * L.a[6 + d]);
+            d2 += v * v;
+          }
+          r12all.push_back(std::sqrt(d2));
+        }
+    std::sort(r12all.begin(), r12all.end());
+    const double hmax = std::exp(-beta * r12all[0] * r12all[0]);
+    std::vector<double> r12s;
+    double sh = 0.0;
+    for (double r : r12all) {
+      const double h = std::exp(-beta * r * r);
+      if (h >= epsp * hmax) {
+        sh += h;
+        r12s.push_back(r);
+      }
+    }
+    Sh[ip] = sh;
+    std::sort(r12s.begin(), r12s.end());
+    // crossing of N_cell(x) x/(2 beta) e^{-beta x^2} and sum_{R12 > x} h
+    double r12min = 0.0;
+    const double step = 0.05;
+    const double xend = r12s.back() + step;
+    for (double x = 0.0; x <= xend; x += step) {
+      double rhs = 0.0;
+      for (double r : r12s)
+        if (r > x) rhs += std::exp(-beta * r * r);
+      const double lhs = S.N(x) * x / (2.0 * beta) * std::exp(-beta * x * x);
+      if (lhs < rhs) r12min = x + step;
+    }
+    p.R12min = r12min;
+  });
+
+  // Triplets are built per call by the caller of this function (they need the
+  // aux batching); here compute per (aux shell, pair) the R_c bound and the
+  // largest R12 kept by any window, to size the pair image lists.
+  const int nxs = (int)hp.ax.size();
+  std::vector<double> r12pair(npair, 0.0);
+  {
+    std::vector<double> r12t((size_t)nxs * npair);
+    hp.rc_t.assign((size_t)nxs * npair, 0.0);
+    hp.amp_t.assign((size_t)nxs * npair, 0.0);
+    // 1s-model amplitudes of Eq. S4, pi^3 C_P C_mu C_nu / (a_P p)^{3/2}, summed
+    // over the primitives of contracted shells; the decay constants (eta1,
+    // eta2, beta) stay those of the most diffuse primitives.
+    std::vector<double> apair(npair), aaux(nxs);
+    for (int ip = 0; ip < npair; ++ip) {
+      const Shell &sA = hp.ao[hp.pairs[ip].sa], &sB = hp.ao[hp.pairs[ip].sb];
+      double a = 0.0;
+      for (int i = 0; i < sA.nprim; ++i)
+        for (int j = 0; j < sB.nprim; ++j)
+          a += hp.ao_c1s[sA.pptr + i] * hp.ao_c1s[sB.pptr + j] /
+               std::pow(hp.ao_exp[sA.pptr + i] + hp.ao_exp[sB.pptr + j], 1.5);
+      apair[ip] = a;
+    }
+    for (int P = 0; P < nxs; ++P) {
+      double a = 0.0;
+      for (int k = 0; k < hp.ax[P].nprim; ++k) a += hp.ax_c1s[hp.ax[P].pptr + k] / std::pow(hp.ax_exp[hp.ax[P].pptr + k], 1.5);
+      aaux[P] = a;
+    }
+    parallel_for((int64_t)nxs * npair, [&](int64_t t) {
+      const int P = (int)(t / npair), ip = (int)(t % npair);
+      const Pair &p = hp.pairs[ip];
+      const Shell &sP = hp.ax[P], &sA = hp.ao[p.sa], &sB = hp.ao[p.sb];
+      const double pd = sA.a_d + sB.a_d;
+      const double Aamp = kPi * kPi * kPi * aaux[P] * apair[ip];
+      hp.amp_t[t] = Aamp;
+      const double eta1 = std::sqrt(sP.a_d * pd / (sP.a_d + pd));
+      const double eta2 = 1.0 / std::sqrt(1.0 / (eta1 * eta1) + 1.0 / (omega * omega));
+      const double K = Aamp * Sh[ip] * 4.0 * kPi / L.vol / (std::sqrt(kPi) * 2.0 * eta2 * eta2 * eta2);
+      const double rc = solve_rc(K, eta2, thresh);
+      hp.rc_t[t] = rc;
+      const int W = std::max(1, (int)std::ceil(rc / S.dR));
+      double nfmax = 0.0;
+      for (int w = 0; w < W; ++w) nfmax = std::max(nfmax, S.N(w * S.dR) * f_sr(w * S.dR, eta1, eta2));
+      nfmax *= Aamp * 4.0 * kPi / L.vol / (2.0 * p.beta_d);
+      r12t[t] = solve_r12(nfmax, p.beta_d, thresh);
+    });
+    for (int P = 0; P < nxs; ++P)
+      for (int ip = 0; ip < npair; ++ip) r12pair[ip] = std::max(r12pair[ip], r12t[(size_t)P * npair + ip]);
+  }
+
+  // Pair image lists: all n' with |A - B - n'| <= max(R12 of the SR bounds,
+  // overlap radius sqrt(50/beta)), grouped by BvK class, sorted by distance.
+  hp.cls_off.assign((size_t)npair * (nk + 1), 0);
+  hp.nsr.assign((size_t)npair * nk, 0);
+  std::vector<std::vector<double>> lists(npair);
+  std::vector<std::vector<int32_t>> coffs(npair), nsrs(npair);
+  parallel_for(npair, [&](int64_t ip) {
+    Pair &p = hp.pairs[ip];
+    p.R12sr = std::max(p.R12min, r12pair[ip]);
+    const Shell &A = hp.ao[p.sa], &B = hp.ao[p.sb];
+    const double rlist = std::max(p.R12sr, std::sqrt(50.0 / p.beta_d));
+    int w[3];
+    for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(rlist * hp.lt.bn[d] / (2.0 * kPi)) + 2;
+    struct Im {
+      int c;
+      double r;
+      double v[3];
+    };
+    std::vector<Im> ims;
+    const double AB[3] = {A.x - B.x, A.y - B.y, A.z - B.z};
+    for (int i = -w[0]; i <= w[0]; ++i)
+      for (int j = -w[1]; j <= w[1]; ++j)
+        for (int k = -w[2]; k <= w[2]; ++k) {
+          Im im;
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            im.v[d] = i * L.a[d] + j * L.a[3 + d] + k * L.a[6 + d];
+            const double t = AB[d] - im.v[d];
+            d2 += t * t;
+          }
+          im.r = std::sqrt(d2);
+          if (im.r > rlist) continue;
+          const int r0 = ((i % L.n[0]) + L.n[0]) % L.n[0], r1 = ((j % L.n[1]) + L.n[1]) % L.n[1],
+                    r2 = ((k % L.n[2]) + L.n[2]) % L.n[2];
+          im.c = (r0 * L.n[1] + r1) * L.n[2] + r2;
+          ims.push_back(im);
+        }
+    std::sort(ims.begin(), ims.end(), [](const Im &x, const Im &y) { return x.c != y.c ? x.c < y.c : x.r < y.r; });
+    coffs[ip].assign(nk + 1, 0);
+    nsrs[ip].assign(nk, 0);
+    for (auto &im : ims) {
+      coffs[ip][im.c + 1]++;
+      if (im.r <= p.R12sr) nsrs[ip][im.c]++;
+    }
+    for (int c = 0; c < nk; ++c) coffs[ip][c + 1] += coffs[ip][c];
+    lists[ip].reserve(3 * ims.size());
+    for (auto &im : ims)
+      for (int d = 0; d < 3; ++d) lists[ip].push_back(im.v[d]);
+  });
+  for (int ip = 0; ip < npair; ++ip) {
+    Pair &p = hp.pairs[ip];
+    p.img_off = (int32_t)(hp.img.size() / 3);
+    p.cls_off = ip * (nk + 1);
+    p.nsr_off = ip * nk;
+    for (int c = 0; c <= nk; ++c) hp.cls_off[(size_t)ip * (nk + 1) + c] = coffs[ip][c];
+    for (int c = 0; c < nk; ++c) hp.nsr[(size_t)ip * nk + c] = nsrs[ip][c];
+    hp.img.insert(hp.img.end(), lists[ip].begin(), lists[ip].end());
+  }
+  if (hp.img.size() / 3 > (size_t)0x7fffffff) return fail(RSGDF_EUNSUPPORTED, "too many pair images");
+  return RSGDF_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rsgdf_last_error(void) { return g_err.c_str(); }
+
+const char *rsgdf_version(void) { return "rsgdf-mi355x 0.1 (gfx950)"; }
+
+int64_t rsgdf_j3c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                         const int32_t kmesh[3]) {
+  if (!cell || !basis || !auxbasis || !kmesh || cell->natm < 1 || !cell->coords) {
+    fail(RSGDF_EINVAL, "null argument");
+    return RSGDF_EINVAL;
+  }
+  int rc = validate_basis(basis, cell->natm, RSGDF_MAX_L_AO, "basis");
+  if (rc) return rc;
+  rc = validate_basis(auxbasis, cell->natm, RSGDF_MAX_L_AUX, "auxbasis");
+  if (rc) return rc;
+  for (int d = 0; d < 3; ++d)
+    if (kmesh[d] < 1 || kmesh[d] > 64) {
+      fail(RSGDF_EINVAL, "kmesh entries must be in 1..64");
+      return RSGDF_EINVAL;
+    }
+  const int64_t nk = (int64_t)kmesh[0] * kmesh[1] * kmesh[2];
+  const int64_t nao = nfunc(basis), naux = nfunc(auxbasis);
+  return nk * (nk + 1) / 2 * naux * nao * nao * 16;
+}
+
+int rsgdf_build_j3c(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                    const int32_t kmesh[3], double omega, double thresh, rsgdf_out *out) {
+  return rsgdf_build_j3c_ex(cell, basis, auxbasis, kmesh, omega, thresh, nullptr, out);
+}
+
+int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                       const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                       rsgdf_out *out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  g_err.clear();
+  if (!out) return fail(RSGDF_EINVAL, "null output");
+  const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
+  if (need < 0) return (int)need;
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
+  if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
+  for (int i = 0; i < 3 * cell->natm; ++i)
+    if (!std::isfinite(cell->coords[i])) return fail(RSGDF_EINVAL, "non-finite coordinates");
+  if (!out->data) return fail(RSGDF_EINVAL, "null output buffer");
+  if (out->capacity_bytes < need) return fail(RSGDF_ESIZE, "output capacity too small");
+  rsgdf_options o{};
+  o.g_thresh = -1.0;
+  o.lr_precision = RSGDF_FP64;
+  o.screening = RSGDF_SCREEN_RIGOROUS;
+  o.parts = RSGDF_PART_ALL;
+  if (opt) o = *opt;
+  if (o.parts == 0) o.parts = RSGDF_PART_ALL;
+  const double g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
+  if (o.lr_precision != RSGDF_FP64) return fail(RSGDF_EUNSUPPORTED, "reduced-precision LR not in this entry point");
+  if (o.screening != RSGDF_SCREEN_RIGOROUS) return fail(RSGDF_EUNSUPPORTED, "learned screening not in this entry point");
+
+  hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
+  HostPlan hp;
+  int rc = build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
+  if (rc) return rc;
+  const Lattice &L = hp.lt.L;
+  const int nk = L.nk;
+  const int nkp = (int)hp.kp1.size();
+  const int64_t nao = hp.nao, naux = hp.naux, nao2 = nao * nao;
+  const int npair = (int)hp.pairs.size();
+  const int nxs = (int)hp.ax.size();
+
+  // ---------------------------------------------------------- device tables
+  DBuf d_ao, d_ax, d_aoe, d_aoc, d_aoc1, d_axe, d_axc, d_axc1, d_pairs, d_coff, d_nsr, d_img, d_boys;
+  HIPCHK(upload(d_ao, hp.ao, st));
+  HIPCHK(upload(d_ax, hp.ax, st));
+  HIPCHK(upload(d_aoe, hp.ao_exp, st));
+  HIPCHK(upload(d_aoc, hp.ao_coef, st));
+  HIPCHK(upload(d_aoc1, hp.ao_c1s, st));
+  HIPCHK(upload(d_axe, hp.ax_exp, st));
+  HIPCHK(upload(d_axc, hp.ax_coef, st));
+  HIPCHK(upload(d_axc1, hp.ax_c1s, st));
+  HIPCHK(upload(d_pairs, hp.pairs, st));
+  HIPCHK(upload(d_coff, hp.cls_off, st));
+  HIPCHK(upload(d_nsr, hp.nsr, st));
+  HIPCHK(upload(d_img, hp.img, st));
+  HIPCHK(upload(d_boys, boys_poly_table(), st));
+
+  // output buffer (device)
+  DBuf d_outbuf;
+  double *d_out = nullptr;
+  if (out->on_device) {
+    d_out = reinterpret_cast<double *>(out->data);
+  } else {
+    HIPCHK(d_outbuf.alloc((size_t)need));
+    d_out = d_outbuf.as<double>();
+  }
+
+  // waves per SR work item (each takes every slices-th pair image); X carries
+  // one partial copy per slice, summed by the fold
+  int slices = o.sr_slices;
+  if (slices <= 0) {
+    const int64_t nitems = (int64_t)nxs * npair;
+    slices = (int)std::min<int64_t>(64, std::max<int64_t>(1, (8192 + nitems - 1) / nitems));
+  }
+  if (slices < 1 || slices > 64) return fail(RSGDF_EINVAL, "sr_slices must be in 1..64");
+  const int nb = slices * nk * nk;  // rows of X: (slice, c1, c2)
+
+  // phase tables: Phi[kp][(s,c1,c2)] = e^{-i k1.L_c1} e^{+i k2.L_c2}; kphase[k][c] = e^{+i k.L_c}
+  auto cell_ph = [&](int k, int c) {  // 2 pi sum_d j_d i_d / n_d
+    const int j[3] = {k / (L.n[1] * L.n[2]), (k / L.n[2]) % L.n[1], k % L.n[2]};
+    const int i[3] = {c / (L.n[1] * L.n[2]), (c / L.n[2]) % L.n[1], c % L.n[2]};
+    long double s = 0.0L;
+    for (int d = 0; d < 3; ++d) s += (long double)(j[d] * i[d] % L.n[d]) / L.n[d];
+    return (double)(2.0L * 3.14159265358979323846264338327950288L * s);
+  };
+  std::vector<double> phi((size_t)2 * nkp * nb), kph((size_t)2 * nk * nk);
+  for (int t = 0; t < nkp; ++t)
+    for (int c1 = 0; c1 < nk; ++c1)
+      for (int c2 = 0; c2 < nk; ++c2) {
+        const double ph = -cell_ph(hp.kp1[t], c1) + cell_ph(hp.kp2[t], c2);
+        for (int sl = 0; sl < slices; ++sl) {
+          phi[2 * ((size_t)t * nb + (size_t)sl * nk * nk + c1 * nk + c2)] = std::cos(ph);
+          phi[2 * ((size_t)t * nb + (size_t)sl * nk * nk + c1 * nk + c2) + 1] = std::sin(ph);
+        }
+      }
+  for (int k = 0; k < nk; ++k)
+    for (int c = 0; c < nk; ++c) {
+      kph[2 * (k * nk + c)] = std::cos(cell_ph(k, c));
+      kph[2 * (k * nk + c) + 1] = std::sin(cell_ph(k, c));
+    }
+  std::vector<int32_t> kdiag(nkp);
+  for (int t = 0; t < nkp; ++t) kdiag[t] = (hp.kp1[t] == hp.kp2[t]) ? hp.kp1[t] : -1;
+  // S_P = int chi_P over all space (aux functions), Eq. M13b
+  std::vector<double> SP(naux, 0.0);
+  for (int s = 0; s < nxs; ++s) {
+    const Shell &x = hp.ax[s];
+    int ic = 0;
+    for (int lx = x.l; lx >= 0; --lx)
+      for (int ly = x.l - lx; ly >= 0; --ly, ++ic) {
+        const int lz = x.l - lx - ly;
+        if ((lx | ly | lz) & 1) continue;
+        double v = 0.0;
+        for (int k = 0; k < x.nprim; ++k) {
+          const double g = hp.ax_exp[x.pptr + k];
+          double m = hp.ax_coef[x.pptr + k] * std::pow(kPi / g, 1.5);
+          const int pw[3] = {lx, ly, lz};
+          for (int d = 0; d < 3; ++d) {
+            double df = 1.0;
+            for (int q = pw[d] - 1; q > 1; q -= 2) df *= q;
+            m *= df / std::pow(2.0 * g, pw[d] / 2);
+          }
+          v += m;
+        }
+        SP[x.foff + ic] = v;
+      }
+  }
+  DBuf d_phi, d_kph, d_kdiag, d_SP, d_O, d_Smn;
+  HIPCHK(upload(d_phi, phi, st));
+  HIPCHK(upload(d_kph, kph, st));
+  HIPCHK(upload(d_kdiag, kdiag, st));
+  HIPCHK(upload(d_SP, SP, st));
+  const bool do_sr = o.parts & RSGDF_PART_SR, do_g0 = o.parts & RSGDF_PART_G0, do_lr = o.parts & RSGDF_PART_LR;
+
+  hipEvent_t ev[8];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t *e;
+    ~EvGuard() {
+      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } evg{ev};
+
+  const double t_plan = ms_since(t_start);
+  HIPCHK(hipEventRecord(ev[0], st));
+
+  // G = 0 overlaps
+  if (do_g0) {
+    HIPCHK(d_O.alloc((size_t)npair * nk * 36 * sizeof(double)));
+    HIPCHK(d_Smn.alloc((size_t)nk * nao2 * 2 * sizeof(double)));
+    OvlParams op{d_ao.as<Shell>(), d_aoe.as<double>(), d_aoc.as<double>(), d_pairs.as<Pair>(),
+                 d_coff.as<int32_t>(), d_img.as<double>(), npair, nk, d_O.as<double>()};
+    SmnParams sp{d_ao.as<Shell>(), d_pairs.as<Pair>(), d_O.as<double>(), d_kph.as<double>(), npair, nk,
+                 (int32_t)nao, 0, d_Smn.as<double>()};
+    HIPCHK(launch_overlaps(op, sp, st));
+  }
+
+  // ---------------------------------------------------------- SR + fold
+  // aux batches bounded by the scratch budget of X
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const double budget = std::min(0.45 * (double)free_b, 64e9);
+  std::vector<int> batch_start{0};
+  {
+    int64_t nf = 0;
+    for (int s = 0; s < nxs; ++s) {
+      const int64_t add = ncart_h(hp.ax[s].l);
+      if (nf > 0 && (double)(nf + add) * nb * nao2 * 8.0 > budget) {
+        batch_start.push_back(s);
+        nf = 0;
+      }
+      nf += add;
+    }
+    batch_start.push_back(nxs);
+  }
+  const int nbatch = (int)batch_start.size() - 1;
+  int64_t max_bf = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    int64_t nf = 0;
+    for (int s = batch_start[b]; s < batch_start[b + 1]; ++s) nf += ncart_h(hp.ax[s].l);
+    max_bf = std::max(max_bf, nf);
+  }
+  if (do_sr && (double)max_bf * nb * nao2 * 8.0 > 0.9 * (double)free_b)
+    return fail(RSGDF_ENOMEM, "one aux shell's short-range scratch does not fit in device memory");
+  DBuf d_X, d_trip, d_cnt;
+  if (do_sr) HIPCHK(d_X.alloc((size_t)max_bf * nb * nao2 * sizeof(double)));
+
+  // triplets for all batches, grouped by (batch, lP, pair class)
+  std::vector<Triplet> trips;
+  std::vector<int> tgrp_off;  // [(nbatch) * 24 + 1]
+  std::vector<int> tgrp_L;
+  {
+    const Screen &S = hp.scr;
+    std::vector<std::vector<Triplet>> grp((size_t)nbatch * 24);
+    std::vector<Triplet> all((size_t)nxs * npair);
+    for (int64_t t = 0; t < (int64_t)nxs * npair; ++t) {
+      Triplet tr{};
+      tr.aux = (int32_t)(t / npair);
+      tr.pair = (int32_t)(t % npair);
+      tr.rc_cut = hp.rc_t[t];
+      tr.amp = hp.amp_t[t];
+      tr.nwin = std::max(1, (int)std::ceil(tr.rc_cut / S.dR));
+      all[t] = tr;
+    }
+    for (int64_t t = 0; t < (int64_t)nxs * npair; ++t) {
+      const Triplet &tr = all[t];
+      if (tr.nwin > 256) return fail(RSGDF_EUNSUPPORTED, "R_c bound exceeds the window table (omega too small)");
+      int b = 0;
+      while (tr.aux >= batch_start[b + 1]) ++b;
+      const Pair &p = hp.pairs[tr.pair];
+      const int g = hp.ax[tr.aux].l * 6 + pair_class(hp.ao[p.sa].l, hp.ao[p.sb].l);
+      grp[(size_t)b * 24 + g].push_back(tr);
+    }
+    tgrp_off.push_back(0);
+    for (auto &g : grp) {
+      trips.insert(trips.end(), g.begin(), g.end());
+      tgrp_off.push_back((int)trips.size());
+    }
+  }
+  const int64_t ntrip = (int64_t)trips.size();
+  {
+    // the SR kernel packs lattice coordinates into 10-bit fields (|M| < 500)
+    double rcmax = 0.0, r12max = 0.0, diam = 0.0;
+    for (const Triplet &t : trips) rcmax = std::max(rcmax, t.rc_cut);
+    for (const Pair &p : hp.pairs) r12max = std::max(r12max, p.R12sr);
+    for (int d = 0; d < 3; ++d) diam += hp.lt.an[d];
+    for (int d = 0; d < 3; ++d)
+      if ((rcmax + r12max + 2.0 * diam) * hp.lt.bn[d] / (2.0 * kPi) + L.n[d] + 2 > 500.0)
+        return fail(RSGDF_EUNSUPPORTED, "screening radius too large for the packed image coordinates");
+  }
+  if (do_sr) {
+    HIPCHK(upload(d_trip, trips, st));
+    HIPCHK(d_cnt.alloc((size_t)ntrip * slices * 4 * sizeof(long long)));
+    HIPCHK(hipMemsetAsync(d_cnt.p, 0, (size_t)ntrip * slices * 4 * sizeof(long long), st));
+  }
+
+  float t_sr = 0.f, t_fold = 0.f;
+  for (int b = 0; b < nbatch; ++b) {
+    int64_t f0 = hp.ax[batch_start[b]].foff, nf = 0;
+    for (int s = batch_start[b]; s < batch_start[b + 1]; ++s) nf += ncart_h(hp.ax[s].l);
+    HIPCHK(hipEventRecord(ev[1], st));
+    if (do_sr) {
+      HIPCHK(hipMemsetAsync(d_X.p, 0, (size_t)nf * nb * nao2 * sizeof(double), st));
+      SRParams prm{};
+      prm.ao = d_ao.as<Shell>();
+      prm.ax = d_ax.as<Shell>();
+      prm.ao_exp = d_aoe.as<double>();
+      prm.ao_coef = d_aoc.as<double>();
+      prm.ax_exp = d_axe.as<double>();
+      prm.ax_coef = d_axc.as<double>();
+      prm.ao_c1s = d_aoc1.as<double>();
+      prm.ax_c1s = d_axc1.as<double>();
+      prm.pairs = d_pairs.as<Pair>();
+      prm.cls_off = d_coff.as<int32_t>();
+      prm.nsr = d_nsr.as<int32_t>();
+      prm.img = d_img.as<double>();
+      prm.trip = d_trip.as<Triplet>();
+      prm.ntrip = (int32_t)ntrip;
+      prm.slices = slices;
+      prm.lat = L;
+      prm.omega = omega;
+      prm.eps = thresh;
+      prm.dR = hp.scr.dR;
+      prm.ncell_nf = hp.scr.ncell_nf;
+      prm.ncell_r0 = hp.scr.r0;
+      prm.boys = d_boys.as<double>();
+      prm.X = d_X.as<double>();
+      prm.aux_f0 = (int32_t)f0;
+      prm.naux_b = (int32_t)nf;
+      prm.nao = (int32_t)nao;
+      prm.counts = d_cnt.as<long long>();
+      for (int g = 0; g < 24; ++g) {
+        const int t0 = tgrp_off[(size_t)b * 24 + g], t1 = tgrp_off[(size_t)b * 24 + g + 1];
+        HIPCHK(launch_sr3c(g / 6, g % 6, prm, t0, t1 - t0, st));
+      }
+    }
+    HIPCHK(hipEventRecord(ev[2], st));
+    FoldParams fp{};
+    fp.phi = d_phi.as<double>();
+    fp.X = do_sr ? d_X.as<double>() : nullptr;
+    fp.out = d_out;
+    fp.kdiag = d_kdiag.as<int32_t>();
+    fp.SP = d_SP.as<double>() + f0;
+    fp.Smn = do_g0 ? d_Smn.as<double>() : nullptr;
+    fp.g0fac = do_g0 ? kPi / (L.vol * omega * omega) : 0.0;
+    fp.ne = nf * nao2;
+    fp.out_off = f0 * nao2;
+    fp.plane = naux * nao2;
+    fp.nkp = nkp;
+    fp.nb = nb;
+    fp.nao2 = (int32_t)nao2;
+    HIPCHK(launch_fold(fp, st));
+    HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipEventSynchronize(ev[3]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
+    t_sr += ms;
+    HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    t_fold += ms;
+  }
+
+  // ---------------------------------------------------------- LR
+  float t_lr = 0.f;
+  int64_t n_lr = 0, n_g = 0;
+  if (do_lr) {
+    HIPCHK(hipEventRecord(ev[4], st));
+    // G sets per folded k12 class: q = G + k_c, q != 0, exp(-q^2/4w^2) >= g_thr
+    const double q2max = -4.0 * omega * omega * std::log(g_thr);
+    std::vector<double> qv;
+    std::vector<int64_t> qoff{0};
+    for (int c = 0; c < nk; ++c) {
+      const double *kc = &hp.kvec[3 * c];
+      const double qm = std::sqrt(std::max(q2max, 0.0)) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
+      int w[3];
+      for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(qm * hp.lt.an[d] / (2.0 * kPi)) + 1;
+      for (int i = -w[0]; i <= w[0]; ++i)
+        for (int j = -w[1]; j <= w[1]; ++j)
+          for (int k = -w[2]; k <= w[2]; ++k) {
+            double q[3], q2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              q[d] = i * L.b[d] + j * L.b[3 + d] + k * L.b[6 + d] + kc[d];
+              q2 += q[d] * q[d];
+            }
+            if (q2 < 1e-20) continue;
+            if (std::exp(-q2 / (4.0 * omega * omega)) < g_thr) continue;
+            qv.insert(qv.end(), q, q + 3);
+          }
+      qoff.push_back((int64_t)qv.size() / 3);
+    }
+    const int64_t nq_tot = qoff.back();
+    n_g = nq_tot;
+    // k-pairs per class
+    std::vector<std::vector<int>> cls_kp(nk);
+    for (int t = 0; t < nkp; ++t) {
+      const int k1 = hp.kp1[t], k2 = hp.kp2[t];
+      const int j1[3] = {k1 / (L.n[1] * L.n[2]), (k1 / L.n[2]) % L.n[1], k1 % L.n[2]};
+      const int j2[3] = {k2 / (L.n[1] * L.n[2]), (k2 / L.n[2]) % L.n[1], k2 % L.n[2]};
+      int c = 0;
+      for (int d = 0; d < 3; ++d) c = c * L.n[d] + ((j2[d] - j1[d]) % L.n[d] + L.n[d]) % L.n[d];
+      cls_kp[c].push_back(t);
+    }
+    DBuf d_q, d_A;
+    HIPCHK(upload(d_q, qv, st));
+    HIPCHK(d_A.alloc((size_t)naux * std::max<int64_t>(nq_tot, 1) * 2 * sizeof(double)));
+    AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
+                   (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
+    HIPCHK(launch_auxft(ap, st));
+    // B buffer: one class, one q chunk
+    int max_kpi = 0;
+    for (auto &v : cls_kp) max_kpi = std::max<int>(max_kpi, (int)v.size());
+    const double bbudget = std::min(0.25 * (double)free_b, 16e9);
+    int64_t qchunk = (int64_t)(bbudget / ((double)std::max(1, max_kpi) * nao2 * 16.0));
+    qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 4096));
+    int64_t max_nq = 0;
+    for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, qoff[c + 1] - qoff[c]);
+    qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
+    DBuf d_B, d_kp, d_k2, d_nterm;
+    HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
+    HIPCHK(d_kp.alloc((size_t)std::max(1, max_kpi) * sizeof(int32_t)));
+    HIPCHK(d_k2.alloc((size_t)std::max(1, max_kpi) * 3 * sizeof(double)));
+    const int64_t max_threads = (((int64_t)npair * 2 * qchunk * max_kpi + 63) / 64) * 64;
+    HIPCHK(d_nterm.alloc((size_t)std::max<int64_t>(max_threads, 64) * sizeof(long long)));
+    std::vector<long long> hterm;
+    for (int c = 0; c < nk; ++c) {
+      const int nkpi = (int)cls_kp[c].size();
+      const int64_t nqc = qoff[c + 1] - qoff[c];
+      if (nkpi == 0 || nqc == 0) continue;
+      std::vector<int32_t> kpl(cls_kp[c].begin(), cls_kp[c].end());
+      std::vector<double> k2l;
+      for (int t : cls_kp[c])
+        for (int d = 0; d < 3; ++d) k2l.push_back(hp.kvec[3 * hp.kp2[t] + d]);
+      HIPCHK(hipMemcpyAsync(d_kp.p, kpl.data(), kpl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(d_k2.p, k2l.data(), k2l.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
+        const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
+        PairFTParams pp{};
+        pp.ao = d_ao.as<Shell>();
+        pp.ao_exp = d_aoe.as<double>();
+        pp.ao_coef = d_aoc.as<double>();
+        pp.pairs = d_pairs.as<Pair>();
+        pp.cls_off = d_coff.as<int32_t>();
+        pp.img = d_img.as<double>();
+        pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);
+        pp.k2 = d_k2.as<double>();
+        pp.npair = npair;
+        pp.nq = nq;
+        pp.nkpi = nkpi;
+        pp.nao = (int32_t)nao;
+        pp.nk = nk;
+        pp.cutoff = 1e-4 * thresh * 1e-4;
+        pp.B = d_B.as<double>();
+        pp.nterm = d_nterm.as<long long>();
+        const int64_t nth = (((int64_t)npair * 2 * nq * nkpi + 63) / 64) * 64;
+        HIPCHK(launch_pairft(pp, nth, st));
+        LRGemmParams gp{};
+        gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
+        gp.lda = nq_tot;
+        gp.B = d_B.as<double>();
+        gp.out = d_out;
+        gp.kp_of = d_kp.as<int32_t>();
+        gp.plane = naux * nao2;
+        gp.naux = (int32_t)naux;
+        gp.nq = nq;
+        gp.nmn = (int32_t)nao2;
+        HIPCHK(launch_lr_gemm_f64(gp, nkpi, st));
+        hterm.resize(nth);
+        HIPCHK(hipMemcpyAsync(hterm.data(), d_nterm.p, nth * sizeof(long long), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (long long v : hterm) n_lr += v;
+      }
+    }
+    HIPCHK(hipEventRecord(ev[5], st));
+    HIPCHK(hipEventSynchronize(ev[5]));
+    HIPCHK(hipEventElapsedTime(&t_lr, ev[4], ev[5]));
+  }
+
+  if (!out->on_device) {
+    HIPCHK(hipMemcpyAsync(out->data, d_out, (size_t)need, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+
+  // ---------------------------------------------------------- stats
+  out->nkpair = nkp;
+  out->naux = naux;
+  out->nao = nao;
+  if (out->stats) {
+    rsgdf_stats &s = *out->stats;
+    std::memset(&s, 0, sizeof(s));
+    s.t_plan_ms = t_plan;
+    s.t_sr_ms = t_sr;
+    s.t_fold_ms = t_fold;
+    s.t_lr_ms = t_lr;
+    s.n_lr_terms = n_lr;
+    s.n_g_total = n_g;
+    s.n_triplets = ntrip;
+    s.n_aux_batches = nbatch;
+    s.bytes_out = need;
+    if (do_sr && ntrip > 0) {
+      std::vector<long long> cnt((size_t)ntrip * slices * 4);
+      HIPCHK(hipMemcpy(cnt.data(), d_cnt.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
+      double flops = 0.0;
+      for (int b = 0; b < nbatch; ++b)
+        for (int g = 0; g < 24; ++g) {
+          const int lP = g / 6, pc = g % 6;
+          static const int la_of[6] = {0, 1, 1, 2, 2, 2}, lb_of[6] = {0, 0, 1, 0, 1, 2};
+          const int Lt = lP + la_of[pc] + lb_of[pc];
+          long long nt = 0;
+          for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t)
+            for (int w = 0; w < slices; ++w) {
+              nt += cnt[((size_t)t * slices + w) * 4];
+              s.n_sr_shell_terms += cnt[((size_t)t * slices + w) * 4 + 2];
+            }
+          s.n_sr_terms += nt;
+          flops += (double)nt * sr_term_flops(Lt);
+        }
+      s.sr_flops = flops;
+      // optional per-work-item dump (aux shell, pair, l_P, l_a, l_b, terms) for workload analysis
+      if (const char *fn = std::getenv("RSGDF_COUNTS_FILE")) {
+        if (FILE *f = std::fopen(fn, "w")) {
+          for (int64_t t = 0; t < ntrip; ++t) {
+            long long nt = 0;
+            for (int w = 0; w < slices; ++w) nt += cnt[((size_t)t * slices + w) * 4];
+            const Pair &pr = hp.pairs[trips[t].pair];
+            std::fprintf(f, "%d %d %d %d %d %lld %.3f\n", trips[t].aux, trips[t].pair, hp.ax[trips[t].aux].l,
+                         hp.ao[pr.sa].l, hp.ao[pr.sb].l, nt, trips[t].rc_cut);
+          }
+          std::fclose(f);
+        }
+      }
+    }
+    s.t_total_ms = ms_since(t_start);
+  }
+  return RSGDF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// kernels.h -- parameter blocks and host launchers of the fold, overlap and
+// long-range kernels (shared by the host planner and the .hip sources).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace rsgdf {
+
+struct FoldParams {
+  const double *phi;      // complex [nkp][nb]
+  const double *X;        // real [nb][ne] (may be null: no SR part)
+  double *out;            // complex [nkp][naux][nao][nao]
+  const int32_t *kdiag;   // [nkp]: k index if k1 == k2 else -1
+  const double *SP;       // [naux_b] lattice-free aux integrals int chi_P
+  const double *Smn;      // complex [nk][nao*nao]
+  double g0fac;           // pi / (Omega w^2), 0 disables the G = 0 term
+  int64_t ne;             // naux_b * nao * nao
+  int64_t out_off;        // aux_f0 * nao * nao
+  int64_t plane;          // naux * nao * nao
+  int32_t nkp, nb, nao2, pad;
+};
+
+struct OvlParams {
+  const Shell *ao;
+  const double *ao_exp, *ao_coef;
+  const Pair *pairs;
+  const int32_t *cls_off;
+  const double *img;
+  int32_t npair, nk;
+  double *O;             // [npair][nk][36]
+};
+
+struct SmnParams {
+  const Shell *ao;
+  const Pair *pairs;
+  const double *O;
+  const double *kphase;  // complex [nk][nk]: exp(+i k.L_c)
+  int32_t npair, nk, nao, pad;
+  double *S;             // complex [nk][nao][nao]
+};
+
+struct AuxFTParams {
+  const Shell *ax;
+  const double *ax_exp, *ax_coef;
+  const double *q;       // [nq][3]
+  int32_t nq, nshell, naux, pad;
+  double wfac;           // 4 pi / Omega
+  double omega;
+  double *A;             // complex [naux][nq] (row stride nq)
+};
+
+struct PairFTParams {
+  const Shell *ao;
+  const double *ao_exp, *ao_coef;
+  const Pair *pairs;
+  const int32_t *cls_off;
+  const double *img;
+  const double *q;        // [nq][3] chunk
+  const double *k2;       // [nkpi][3] k2 vector of each k-pair of the class
+  int32_t npair, nq, nkpi, nao, nk;
+  int32_t pad;
+  double cutoff;          // skip primitive-pair images with |c_a c_b| K (pi/p)^{3/2} below this
+  double *B;              // complex [nkpi][nq][nao][nao]
+  long long *nterm;       // [gridDim.x * blockDim.x] transform evaluations
+};
+
+struct LRGemmParams {
+  const double *A;        // complex, row P has stride lda (complex elements); columns q0.. of the class
+  int64_t lda;
+  const double *B;        // complex [nkpi][nq][nmn]
+  double *out;            // complex [nkp][naux][nmn]
+  const int32_t *kp_of;   // [nkpi] global k-pair index
+  int64_t plane;          // naux * nmn
+  int32_t naux, nq, nmn, pad;
+};
+
+int pair_class(int la, int lb);
+int sr_term_flops(int L);
+hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int trip0, int ntrip, hipStream_t stream);
+hipError_t launch_fold(const FoldParams &fp, hipStream_t stream);
+hipError_t launch_overlaps(const OvlParams &op, const SmnParams &sp, hipStream_t stream);
+hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream);
+hipError_t launch_pairft(const PairFTParams &pp, int64_t nthreads_padded, hipStream_t stream);
+hipError_t launch_lr_gemm_f64(const LRGemmParams &gp, int nkpi, hipStream_t stream);
+
+}  // namespace rsgdf

@@ -1,0 +1,88 @@
+// plan.h -- data shared between the host planner and the gfx950 kernels.
+//
+// Everything here is plain-old-data copied to the device once per call:
+// packed shells and primitives, AO shell pairs with their lattice-image
+// lists (grouped by Born-von Karman class), (aux shell, AO pair) work items
+// with their screening radii, and the G-vector sets of the long-range part.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsgdf {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kMaxLAO = 2;
+constexpr int kMaxLAux = 3;
+constexpr int kMaxL = 2 * kMaxLAO + kMaxLAux;  // 7
+constexpr int kMaxWin = 512;                   // SR screening windows of width dR
+constexpr double kBoysSwitch = 36.0;           // polynomial table below, asymptotic recursion above
+constexpr int kBoysIntervals = 36;             // unit intervals of T in [0, 36)
+constexpr int kBoysPolyDeg = 12;               // Taylor degree about each interval centre
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int nherm(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
+
+// Packed shell (AO or aux).  a_d, c_d: exponent and 1s-equivalent amplitude
+// of the most diffuse primitive (used by the screening bounds, which treat
+// every function as 1s and a contracted shell by its most diffuse primitive).
+struct Shell {
+  double x, y, z;
+  double a_d, c_d;
+  int32_t l, nprim, pptr, foff;
+};
+
+// AO shell pair, oriented so that l(sa) >= l(sb).  Images n' of shell sb are
+// listed in img[img_off + cls_off[c] .. img_off + cls_off[c+1]) for each BvK
+// class c of n', sorted by |A - B - n'| within a class.  nsr[c] is the count
+// of leading images of class c inside the short-range R12 radius.
+struct Pair {
+  int32_t sa, sb, diag, pad;
+  int32_t img_off;   // offset into the image-vector array
+  int32_t cls_off;   // offset into the per-class offset array (Nk + 1 entries)
+  int32_t nsr_off;   // offset into the per-class short-range count array (Nk entries)
+  int32_t pad2;
+  double beta_d;     // a_d(sa) a_d(sb) / (a_d(sa) + a_d(sb))
+  double R12min;     // Eq. S25 crossing radius
+  double R12sr;      // largest R12 any window of any aux shell can keep
+};
+
+// (aux shell, AO pair) short-range work item.
+struct Triplet {
+  int32_t aux, pair, nwin, pad;
+  double rc_cut;     // Eq. S14 bound on R_c
+  double amp;        // 1s-model amplitude A of Eq. S4 (primitive amplitudes summed)
+};
+
+// Lattice and k-mesh constants.
+struct Lattice {
+  double a[9];       // rows a1, a2, a3
+  double b[9];       // rows b1, b2, b3, a_i . b_j = 2 pi delta_ij
+  double vol;
+  int32_t n[3];      // k-mesh
+  int32_t nk;
+  int32_t pad;
+};
+
+struct SRParams {
+  const Shell *ao;
+  const Shell *ax;
+  const double *ao_exp, *ao_coef;
+  const double *ax_exp, *ax_coef;
+  const double *ao_c1s, *ax_c1s;  // 1s-equivalent amplitudes per primitive (screening)
+  const Pair *pairs;
+  const int32_t *cls_off;   // per pair: Nk+1 offsets
+  const int32_t *nsr;       // per pair: Nk counts
+  const double *img;        // image vectors, 3 doubles each
+  const Triplet *trip;
+  int32_t ntrip;
+  int32_t slices;           // waves per work item (interleaved pair images)
+  Lattice lat;
+  double omega, eps, dR;
+  double ncell_nf, ncell_r0;  // N_cell model of Eq. S19
+  const double *boys;       // [L = 0..kMaxL][kBoysIntervals][kBoysPolyDeg + 1]
+  double *X;                // [slices][Nk][Nk][naux_b][nao][nao]
+  int32_t aux_f0, naux_b, nao, pad;
+  long long *counts;        // [item][4]: primitive terms, contractions, shell terms, 0
+};
+
+}  // namespace rsgdf

@@ -1,0 +1,473 @@
+// sr3c.hip -- short-range (erfc-attenuated) three-center lattice sums on gfx950.
+//
+// Work item: (aux shell P, AO shell pair, slice).  One wavefront per item.
+// The term (P^0 | erfc(w r)/r | mu^m nu^{m+n'}) of Eq. (M12)/(M13a) is
+// rewritten by translation as (P^{-m} | mu^0 nu^{n'}): for a pair image n' the
+// AO pair density is fixed and the aux function moves over lattice vectors m.
+// Terms are grouped by Born-von Karman cells (Eq. M14): c1 = c(m) and
+// c2 = c(m + n').
+//
+// Lane layout: the 64 lanes form groups of gs lanes, group g owning BvK cell
+// c1 = g.  For each pair image n' (taken in the pair list order, which is
+// sorted by the BvK class of n', so the target (c1, c2) changes only with the
+// class) the wave
+//   1. enumerates the lattice vectors m of each cell inside the screening
+//      radius and keeps those passing the per-term window test of the
+//      Supplementary Material (R_c <= R_c^cut of Eq. S14 and R12 <= R12^cut(R_c)
+//      of Eqs. S23-S25, most diffuse primitives as 1s functions); survivors are
+//      compacted into per-group LDS lists with ballots (deterministic order);
+//   2. for every primitive pair (and aux primitive) sums the Hermite Coulomb
+//      integrals R_tuv of the erfc operator over the group's list (the only
+//      m-dependent factor of the McMurchie-Davidson expression), reduces them
+//      over the group with a fixed xor-butterfly, and contracts them with the
+//      pair (E^ab) and aux (E^c) Hermite coefficients;
+//   3. adds the Cartesian block into an LDS accumulator per group, flushed to
+//      X[slice][c1][c2][P][mu][nu] when the class of n' changes.
+// Every X element is owned by one wave and one group, so results are
+// deterministic without atomics; the fold adds the slices.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace rsgdf {
+
+constexpr int kCandCap = 1536;    // lattice-vector candidates held in LDS per wave
+constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators in LDS
+constexpr int kSRWinCap = 256;    // screening windows held in LDS
+
+// F_L(T) for 0 <= T < kBoysSwitch from the per-L polynomial table (Taylor
+// expansion of degree kBoysPolyDeg about each unit interval's centre), then the
+// downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1).
+template <int L>
+__device__ __forceinline__ void boys_poly(double T, const double *__restrict__ tab, double (&F)[L + 1]) {
+  const int i = (int)T;
+  const double u = T - (i + 0.5);
+  const double *c = tab + i * (kBoysPolyDeg + 1);
+  double s = c[kBoysPolyDeg];
+#pragma unroll
+  for (int j = kBoysPolyDeg - 1; j >= 0; --j) s = fma(s, u, c[j]);
+  F[L] = s;
+  if (L > 0) {
+    const double e = exp(-T);
+    const double t2 = 2.0 * T;
+#pragma unroll
+    for (int n = L - 1; n >= 0; --n) F[n] = fma(t2, F[n + 1], e) * (1.0 / (2 * n + 1));
+  }
+}
+
+// G_n = F_n(T) - theta^{2n+1} F_n(theta^2 T) (erfc operator, see device_math.h);
+// zero once theta^2 T >= kBoysSwitch (both terms share their asymptote to
+// within e^{-theta^2 T}).
+template <int L>
+__device__ __forceinline__ void gvals_sr(double T, double th2, double th, const double *__restrict__ tab,
+                                         double (&G)[L + 1]) {
+  const double x = th2 * T;
+  if (x >= kBoysSwitch) {
+#pragma unroll
+    for (int n = 0; n <= L; ++n) G[n] = 0.0;
+    return;
+  }
+  double F1[L + 1], F2[L + 1];
+  if (T < kBoysSwitch) boys_poly<L>(T, tab, F1);
+  else boys_large<L>(T, F1);
+  boys_poly<L>(x, tab, F2);
+  double f = th;
+#pragma unroll
+  for (int n = 0; n <= L; ++n) {
+    G[n] = F1[n] - f * F2[n];
+    f *= th2;
+  }
+}
+
+__device__ __forceinline__ int pack3(int a, int b, int c) {
+  return ((a + 512) & 1023) | (((b + 512) & 1023) << 10) | (((c + 512) & 1023) << 20);
+}
+__device__ __forceinline__ void unpack3(int v, int &a, int &b, int &c) {
+  a = (v & 1023) - 512;
+  b = ((v >> 10) & 1023) - 512;
+  c = ((v >> 20) & 1023) - 512;
+}
+
+template <int LP, int LA, int LB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+void sr3c_kernel(const SRParams prm, const int trip0) {
+  constexpr int NCP = ncart(LP), NCA = ncart(LA), NCB = ncart(LB);
+  constexpr int NBLK = NCP * NCA * NCB;
+  constexpr int LAB = LA + LB, L = LAB + LP;
+  constexpr int NH = nherm(L);
+  __shared__ double s_nf[kSRWinCap];
+  __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
+  __shared__ int s_cand[kCandCap];
+  __shared__ double s_blk[kBlkCap];
+
+  const int lane = threadIdx.x;
+  const int item = blockIdx.x;
+  const int S = prm.slices;
+  const int slice = item % S;
+  const Triplet tr = prm.trip[trip0 + item / S];
+  const Shell shP = prm.ax[tr.aux];
+  const Pair pr = prm.pairs[tr.pair];
+  const Shell shA = prm.ao[pr.sa];
+  const Shell shB = prm.ao[pr.sb];
+  const Lattice &lat = prm.lat;
+  const int nk = lat.nk;
+  const double omega = prm.omega, eps = prm.eps, dR = prm.dR;
+  const double fourpi_vol = 4.0 * kPi / lat.vol;
+
+  // ---- per-item tables in LDS: Boys polynomials of order L, screening windows
+  for (int i = lane; i < kBoysIntervals * (kBoysPolyDeg + 1); i += 64)
+    s_boys[i] = prm.boys[L * kBoysIntervals * (kBoysPolyDeg + 1) + i];
+  const double pd = shA.a_d + shB.a_d;
+  const double beta = shA.a_d * shB.a_d / pd;
+  const double eta1 = sqrt(shP.a_d * pd / (shP.a_d + pd));
+  const double eta2 = 1.0 / sqrt(1.0 / (eta1 * eta1) + 1.0 / (omega * omega));
+  const int W = tr.nwin;
+  const double rc_cut = tr.rc_cut;
+  {
+    const double pref = tr.amp * fourpi_vol / (2.0 * beta);
+    for (int w = lane; w < W; w += 64) {
+      const double R = w * dR;
+      const double N = (R > prm.ncell_r0) ? fourpi_vol * 2.0 * (R + dR) * (R + dR) * dR : prm.ncell_nf;
+      const double f = (R < 1e-12) ? 2.0 * (eta1 - eta2) * 0.564189583547756286948079451561 /* 1/sqrt(pi) */
+                                   : (erf(eta1 * R) - erf(eta2 * R)) / R;
+      s_nf[w] = pref * N * f;
+    }
+  }
+  for (int i = lane; i < kBlkCap; i += 64) s_blk[i] = 0.0;
+  __syncthreads();
+  const double xstar = 1.0 / sqrt(2.0 * beta);
+  const double gmax = xstar * exp(-0.5);
+  const double inv_dR = 1.0 / dR;
+
+  const double Ax = shA.x, Ay = shA.y, Az = shA.z;
+  const double Cx = shP.x, Cy = shP.y, Cz = shP.z;
+  const double *a = lat.a;
+  const double *b = lat.b;
+  const double inv2pi = 1.0 / (2.0 * kPi);
+  double bn[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) bn[d] = sqrt(b[3 * d] * b[3 * d] + b[3 * d + 1] * b[3 * d + 1] + b[3 * d + 2] * b[3 * d + 2]);
+
+  // group layout
+  int gs = 1;
+  while (gs * 2 * nk <= 64) gs *= 2;
+  const int ngrp_max = 64 / gs;
+  const int lig = lane % gs;
+  const int gl = lane / gs;  // group index inside a round of BvK cells
+  const unsigned long long gmask_lo = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
+  const bool blk_in_lds = (long long)NBLK * (nk < ngrp_max ? nk : ngrp_max) <= kBlkCap;
+
+  const size_t xplane = (size_t)prm.naux_b * prm.nao * prm.nao;
+  const int pf0 = shP.foff - prm.aux_f0;
+  long long n_terms = 0, n_contr = 0, n_shell = 0;
+
+  const int nimg_all = prm.cls_off[pr.cls_off + nk];
+  const int nround = (nk + ngrp_max - 1) / ngrp_max;
+
+  for (int round = 0; round < nround; ++round) {
+    const int c1 = round * ngrp_max + gl;  // this group's BvK cell
+    const int ngrp = min(ngrp_max, nk - round * ngrp_max);
+    const bool grp_on = gl < ngrp;
+    int i1[3] = {0, 0, 0};
+    if (grp_on) {
+      i1[0] = c1 / (lat.n[1] * lat.n[2]);
+      i1[1] = (c1 / lat.n[2]) % lat.n[1];
+      i1[2] = c1 % lat.n[2];
+    }
+    const int capb = kCandCap / ngrp;
+    int cur_cls = -1;  // class of the n' whose sums sit in the LDS accumulator
+
+    // flush the LDS accumulator of class cls into X
+    auto flush = [&](int cls) {
+      if (!blk_in_lds || cls < 0) return;
+      if (grp_on) {
+        // c2 = c1 + cls (component-wise mod n)
+        const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
+        const int c2 = (((i1[0] + dc0) % lat.n[0]) * lat.n[1] + (i1[1] + dc1) % lat.n[1]) * lat.n[2] +
+                       (i1[2] + dc2) % lat.n[2];
+        double *X12 = prm.X + (size_t)((slice * nk + c1) * nk + c2) * xplane;
+        double *X21 = prm.X + (size_t)((slice * nk + c2) * nk + c1) * xplane;
+        for (int comp = lig; comp < NBLK; comp += gs) {
+          const double v = s_blk[gl * NBLK + comp];
+          s_blk[gl * NBLK + comp] = 0.0;
+          if (v == 0.0) continue;
+          const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
+          const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
+          X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += v;
+          if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += v;
+        }
+      }
+    };
+
+    int cls = 0;
+    for (int ii = slice; ii < nimg_all; ii += S) {
+      // class of this image (the list is grouped by class)
+      while (prm.cls_off[pr.cls_off + cls + 1] <= ii) ++cls;
+      if (ii - prm.cls_off[pr.cls_off + cls] >= prm.nsr[pr.nsr_off + cls]) continue;  // beyond the SR radius
+      const double *nv = prm.img + 3 * (size_t)(pr.img_off + ii);
+      const double Bx = shB.x + nv[0], By = shB.y + nv[1], Bz = shB.z + nv[2];
+      const double ABx = Ax - Bx, ABy = Ay - By, ABz = Az - Bz;
+      const double r12sq = ABx * ABx + ABy * ABy + ABz * ABz;
+      const double R12 = sqrt(r12sq);
+      // window test of Eqs. S23-S24: keep R_c window w iff R12 <= R12cut(w)
+      double thr;
+      if (R12 <= pr.R12min) thr = 0.0;
+      else if (R12 <= xstar) thr = eps / gmax;
+      else thr = eps / (R12 * exp(-beta * r12sq));
+      int wmax = -1;
+      for (int w = 0; w < W; ++w)
+        if (s_nf[w] >= thr) wmax = w;
+      if (wmax < 0) continue;
+      if (cls != cur_cls) {
+        flush(cur_cls);
+        cur_cls = cls;
+      }
+      const double rmax = fmin((wmax + 1) * dR, rc_cut);
+      const double rmax2 = rmax * rmax;
+      // diffuse pair centre relative to the aux centre
+      const double Pdx = (shA.a_d * Ax + shB.a_d * Bx) / pd, Pdy = (shA.a_d * Ay + shB.a_d * By) / pd,
+                   Pdz = (shA.a_d * Az + shB.a_d * Bz) / pd;
+      const double X0x = Pdx - Cx, X0y = Pdy - Cy, X0z = Pdz - Cz;
+      // box of lattice coordinates M_d = i1_d + n_d j_d around -X0
+      int lo0, lo1, lo2, dim0, dim1, dim2;
+      {
+        const double f0 = -(b[0] * X0x + b[1] * X0y + b[2] * X0z) * inv2pi;
+        const double f1 = -(b[3] * X0x + b[4] * X0y + b[5] * X0z) * inv2pi;
+        const double f2 = -(b[6] * X0x + b[7] * X0y + b[8] * X0z) * inv2pi;
+        const double sp0 = rmax * bn[0] * inv2pi, sp1 = rmax * bn[1] * inv2pi, sp2 = rmax * bn[2] * inv2pi;
+        lo0 = (int)ceil((f0 - sp0 - i1[0]) / lat.n[0]);
+        lo1 = (int)ceil((f1 - sp1 - i1[1]) / lat.n[1]);
+        lo2 = (int)ceil((f2 - sp2 - i1[2]) / lat.n[2]);
+        dim0 = max(0, (int)floor((f0 + sp0 - i1[0]) / lat.n[0]) - lo0 + 1);
+        dim1 = max(0, (int)floor((f1 + sp1 - i1[1]) / lat.n[1]) - lo1 + 1);
+        dim2 = max(0, (int)floor((f2 + sp2 - i1[2]) / lat.n[2]) - lo2 + 1);
+      }
+      const int nbox = grp_on ? dim0 * dim1 * dim2 : 0;
+      // chunks of gs candidates; the wave loops to the largest group box
+      int nchunk = (nbox + gs - 1) / gs;
+      for (int off = 32; off >= 1; off >>= 1) nchunk = max(nchunk, __shfl_xor(nchunk, off, 64));
+
+      int pass = 0;
+      for (;;) {
+        // ---- enumerate and compact (this pass keeps candidates [pass*capb, (pass+1)*capb))
+        const int base = pass * capb;
+        int cnt = 0;
+        for (int ch = 0; ch < nchunk; ++ch) {
+          const int q = ch * gs + lig;
+          bool valid = false;
+          int M0 = 0, M1 = 0, M2 = 0;
+          if (q < nbox) {
+            const int j2 = q % dim2, j1 = (q / dim2) % dim1, j0 = q / (dim1 * dim2);
+            M0 = i1[0] + lat.n[0] * (lo0 + j0);
+            M1 = i1[1] + lat.n[1] * (lo1 + j1);
+            M2 = i1[2] + lat.n[2] * (lo2 + j2);
+            const double mx = X0x + M0 * a[0] + M1 * a[3] + M2 * a[6];
+            const double my = X0y + M0 * a[1] + M1 * a[4] + M2 * a[7];
+            const double mz = X0z + M0 * a[2] + M1 * a[5] + M2 * a[8];
+            const double rc2 = mx * mx + my * my + mz * mz;
+            if (rc2 <= rmax2) {
+              const double rc = sqrt(rc2);
+              const int w = (int)(rc * inv_dR);
+              valid = (rc <= rc_cut) && (w < W) && (s_nf[w] >= thr);
+            }
+          }
+          const unsigned long long bal = __ballot(valid);
+          const unsigned long long gb = (bal >> (gl * gs)) & gmask_lo;
+          const int pos = cnt + __popcll(gb & ((1ull << lig) - 1ull));
+          if (valid && pos >= base && pos < base + capb) s_cand[gl * capb + pos - base] = pack3(M0, M1, M2);
+          cnt += __popcll(gb);
+        }
+        const int total = cnt;
+        const int navail = min(max(total - base, 0), capb);
+        if (pass == 0 && lig == 0 && grp_on) n_shell += total;
+        __syncthreads();
+
+        // ---- primitive pairs: image-summed Hermite integrals, then contraction
+        for (int ka = 0; ka < shA.nprim; ++ka) {
+          const double ga = prm.ao_exp[shA.pptr + ka], ca = prm.ao_coef[shA.pptr + ka];
+          const double ca1 = prm.ao_c1s[shA.pptr + ka];
+          for (int kb = 0; kb < shB.nprim; ++kb) {
+            const double gb = prm.ao_exp[shB.pptr + kb], cb = prm.ao_coef[shB.pptr + kb];
+            const double cb1 = prm.ao_c1s[shB.pptr + kb];
+            const double p = ga + gb, oop = 1.0 / p;
+            const double Kab = exp(-ga * gb * oop * r12sq);
+            const double Px = (ga * Ax + gb * Bx) * oop, Py = (ga * Ay + gb * By) * oop, Pz = (ga * Az + gb * Bz) * oop;
+            // offset of this primitive pair's centre from the aux centre at m = 0
+            const double dPx = Px - Pdx + X0x, dPy = Py - Pdy + X0y, dPz = Pz - Pdz + X0z;
+            for (int kc = 0; kc < shP.nprim; ++kc) {
+              const double gc = prm.ax_exp[shP.pptr + kc], cc = prm.ax_coef[shP.pptr + kc];
+              const double cc1 = prm.ax_c1s[shP.pptr + kc];
+              // primitive screen: image-summed 1s estimate for this n' far below
+              // the target precision
+              const double e1 = sqrt(gc * p / (gc + p));
+              const double e2 = 1.0 / sqrt(1.0 / (e1 * e1) + 1.0 / (omega * omega));
+              const double nm = 4.18879020478639098 * rmax2 * rmax / lat.vol + 1.0;
+              const double est = kPi * kPi * kPi * cc1 * ca1 * cb1 / (gc * p * sqrt(gc * p)) * Kab * 2.0 * (e1 - e2) *
+                                 0.564189583547756286948079451561 * nm;
+              if (est < 1e-4 * eps) continue;
+              const double rho = p * gc / (p + gc);
+              const double th2 = omega * omega / (omega * omega + rho);
+              const double th = sqrt(th2);
+              const double m2rho = -2.0 * rho;
+              double Rb[NH];
+#pragma unroll
+              for (int i = 0; i < NH; ++i) Rb[i] = 0.0;
+              for (int e = lig; e < navail; e += gs) {
+                int M0, M1, M2;
+                unpack3(s_cand[gl * capb + e], M0, M1, M2);
+                const double X = dPx + M0 * a[0] + M1 * a[3] + M2 * a[6];
+                const double Y = dPy + M0 * a[1] + M1 * a[4] + M2 * a[7];
+                const double Z = dPz + M0 * a[2] + M1 * a[5] + M2 * a[8];
+                const double T = rho * (X * X + Y * Y + Z * Z);
+                double g[L + 1];
+                gvals_sr<L>(T, th2, th, s_boys, g);
+                double f = 1.0;
+#pragma unroll
+                for (int n = 1; n <= L; ++n) {
+                  f *= m2rho;
+                  g[n] *= f;
+                }
+                double R[NH];
+                hermite_R<L>(X, Y, Z, g, R);
+#pragma unroll
+                for (int i = 0; i < NH; ++i) Rb[i] += R[i];
+                ++n_terms;
+              }
+              // group reduction (fixed xor butterfly: identical result on every lane)
+              for (int off = 1; off < gs; off <<= 1) {
+#pragma unroll
+                for (int i = 0; i < NH; ++i) Rb[i] += __shfl_xor(Rb[i], off, 64);
+              }
+              // ---- contraction with the Hermite expansion coefficients
+              double Ex[LA + 1][LB + 1][LAB + 1], Ey[LA + 1][LB + 1][LAB + 1], Ez[LA + 1][LB + 1][LAB + 1];
+              hermite_E<LA, LB>(Px - Ax, Px - Bx, 0.5 * oop, Ex);
+              hermite_E<LA, LB>(Py - Ay, Py - By, 0.5 * oop, Ey);
+              hermite_E<LA, LB>(Pz - Az, Pz - Bz, 0.5 * oop, Ez);
+              const double pref = 2.0 * kPi * kPi * sqrt(kPi) / (p * gc * sqrt(p + gc));
+              const double coef = ((LP & 1) ? -1.0 : 1.0) * cc * ca * cb * Kab * pref;
+              double EP[LP + 1][LP + 1];
+              hermite_E1<LP>(0.5 / gc, EP);
+              double *X12 = nullptr, *X21 = nullptr;
+              if (!blk_in_lds && grp_on) {
+                const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
+                const int c2 = (((i1[0] + dc0) % lat.n[0]) * lat.n[1] + (i1[1] + dc1) % lat.n[1]) * lat.n[2] +
+                               (i1[2] + dc2) % lat.n[2];
+                X12 = prm.X + (size_t)((slice * nk + c1) * nk + c2) * xplane;
+                X21 = prm.X + (size_t)((slice * nk + c2) * nk + c1) * xplane;
+              }
+#pragma unroll
+              for (int ic = 0; ic < NCP; ++ic) {
+                const int cx = cart_lx(LP, ic), cy = cart_ly(LP, ic), cz = cart_lz(LP, ic);
+                double Wc[nherm(LAB)];
+#pragma unroll
+                for (int t = 0; t <= LAB; ++t)
+#pragma unroll
+                  for (int uu = 0; uu <= LAB - t; ++uu)
+#pragma unroll
+                    for (int v = 0; v <= LAB - t - uu; ++v) {
+                      double s = 0.0;
+#pragma unroll
+                      for (int tau = cx & 1; tau <= cx; tau += 2)
+#pragma unroll
+                        for (int nu = cy & 1; nu <= cy; nu += 2)
+#pragma unroll
+                          for (int phi = cz & 1; phi <= cz; phi += 2)
+                            s += EP[cx][tau] * EP[cy][nu] * EP[cz][phi] * Rb[hidx(t + tau, uu + nu, v + phi)];
+                      Wc[hidx(t, uu, v)] = s;
+                    }
+#pragma unroll
+                for (int ia = 0; ia < NCA; ++ia) {
+                  const int ax_ = cart_lx(LA, ia), ay_ = cart_ly(LA, ia), az_ = cart_lz(LA, ia);
+#pragma unroll
+                  for (int ib = 0; ib < NCB; ++ib) {
+                    const int bx_ = cart_lx(LB, ib), by_ = cart_ly(LB, ib), bz_ = cart_lz(LB, ib);
+                    const int comp = (ic * NCA + ia) * NCB + ib;
+                    if (comp % gs != lig || !grp_on) continue;
+                    double s = 0.0;
+#pragma unroll
+                    for (int t = 0; t <= ax_ + bx_; ++t)
+#pragma unroll
+                      for (int uu = 0; uu <= ay_ + by_; ++uu)
+#pragma unroll
+                        for (int v = 0; v <= az_ + bz_; ++v)
+                          s += Ex[ax_][bx_][t] * Ey[ay_][by_][uu] * Ez[az_][bz_][v] * Wc[hidx(t, uu, v)];
+                    if (blk_in_lds) {
+                      s_blk[gl * NBLK + comp] += coef * s;
+                    } else {
+                      const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
+                      X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += coef * s;
+                      if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += coef * s;
+                    }
+                  }
+                }
+              }
+              ++n_contr;
+            }
+          }
+        }
+        // more candidates than one pass holds?
+        int more = (total > base + capb) ? 1 : 0;
+        for (int off = 32; off >= 1; off >>= 1) more = max(more, __shfl_xor(more, off, 64));
+        __syncthreads();
+        if (!more) break;
+        ++pass;
+      }
+    }
+    flush(cur_cls);
+    __syncthreads();
+  }
+
+  // ---- work counters (deterministic integer reduction), one slot per item
+  for (int off = 32; off >= 1; off >>= 1) {
+    n_terms += __shfl_xor(n_terms, off, 64);
+    n_contr += __shfl_xor(n_contr, off, 64);
+    n_shell += __shfl_xor(n_shell, off, 64);
+  }
+  if (lane == 0) {
+    long long *dst = prm.counts + 4 * ((size_t)trip0 * S + item);
+    dst[0] = n_terms;
+    dst[1] = n_contr;
+    dst[2] = n_shell;
+    dst[3] = 0;
+  }
+}
+
+// Static per-term FP64 operation count of the image loop for class L:
+// position and T (13) + attenuated Boys values (two degree-12 polynomials,
+// two downward recursions, theta scaling) + (-2 rho)^n scaling (2L) +
+// Hermite recursion + image accumulation (nherm(L)).  An exp counts as one.
+int sr_term_flops(int L) {
+  const int geo = 13;
+  const int boys = 2 * (2 * kBoysPolyDeg + 3 * L + 1) + 3 * (L + 1);
+  return geo + boys + 2 * L + hermite_R_flops(L) + nherm(L);
+}
+
+typedef void (*sr_kernel_t)(const SRParams, const int);
+
+#define RSGDF_SR_ENTRY(LP, LA, LB) &sr3c_kernel<LP, LA, LB>
+static const sr_kernel_t kSRTable[4][6] = {
+    {RSGDF_SR_ENTRY(0, 0, 0), RSGDF_SR_ENTRY(0, 1, 0), RSGDF_SR_ENTRY(0, 1, 1), RSGDF_SR_ENTRY(0, 2, 0),
+     RSGDF_SR_ENTRY(0, 2, 1), RSGDF_SR_ENTRY(0, 2, 2)},
+    {RSGDF_SR_ENTRY(1, 0, 0), RSGDF_SR_ENTRY(1, 1, 0), RSGDF_SR_ENTRY(1, 1, 1), RSGDF_SR_ENTRY(1, 2, 0),
+     RSGDF_SR_ENTRY(1, 2, 1), RSGDF_SR_ENTRY(1, 2, 2)},
+    {RSGDF_SR_ENTRY(2, 0, 0), RSGDF_SR_ENTRY(2, 1, 0), RSGDF_SR_ENTRY(2, 1, 1), RSGDF_SR_ENTRY(2, 2, 0),
+     RSGDF_SR_ENTRY(2, 2, 1), RSGDF_SR_ENTRY(2, 2, 2)},
+    {RSGDF_SR_ENTRY(3, 0, 0), RSGDF_SR_ENTRY(3, 1, 0), RSGDF_SR_ENTRY(3, 1, 1), RSGDF_SR_ENTRY(3, 2, 0),
+     RSGDF_SR_ENTRY(3, 2, 1), RSGDF_SR_ENTRY(3, 2, 2)},
+};
+
+// pair class index of (la, lb) with la >= lb
+int pair_class(int la, int lb) {
+  static const int t[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
+  return t[la][lb];
+}
+
+hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int trip0, int ntrip, hipStream_t stream) {
+  if (ntrip <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kSRTable[lP][pc], dim3((unsigned)(ntrip * prm.slices)), dim3(64), 0, stream, prm, trip0);
+  return hipGetLastError();
+}
+
+}  // namespace rsgdf

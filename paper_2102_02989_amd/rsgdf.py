@@ -1,0 +1,178 @@
+"""ctypes binding of librsgdf.so (argument marshalling only).
+
+Every step of the computation runs in the native library; there is no
+Python or CPU fallback.  Importing works without a GPU; calling
+``build_j3c`` needs the library and a HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "librsgdf.so")
+
+RSGDF_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ESIZE", -3: "ENOMEM", -4: "EHIP", -5: "EUNSUPPORTED"}
+FP64, FP32, BF16X3 = 0, 1, 2
+SCREEN_RIGOROUS, SCREEN_LEARNED = 0, 1
+PART_SR, PART_G0, PART_LR = 1, 2, 4
+PART_ALL = 7
+
+
+class RsgdfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rsgdf error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Cell(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_double * 9), ("natm", ctypes.c_int32), ("coords", ctypes.c_void_p)]
+
+
+class BasisT(ctypes.Structure):
+    _fields_ = [("nshell", ctypes.c_int32), ("shell_atom", ctypes.c_void_p), ("shell_l", ctypes.c_void_p),
+                ("shell_nprim", ctypes.c_void_p), ("shell_ptr", ctypes.c_void_p), ("exps", ctypes.c_void_p),
+                ("coefs", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("g_thresh", ctypes.c_double), ("lr_precision", ctypes.c_int32), ("screening", ctypes.c_int32),
+                ("parts", ctypes.c_int32), ("sr_slices", ctypes.c_int32), ("mlp_weights", ctypes.c_char_p),
+                ("mlp_margin", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t_plan_ms", ctypes.c_double), ("t_sr_ms", ctypes.c_double), ("t_fold_ms", ctypes.c_double),
+                ("t_lr_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("n_sr_terms", ctypes.c_int64),
+                ("n_sr_shell_terms", ctypes.c_int64), ("n_sr_candidates", ctypes.c_int64),
+                ("n_lr_terms", ctypes.c_int64), ("n_g_total", ctypes.c_int64), ("n_triplets", ctypes.c_int64),
+                ("n_aux_batches", ctypes.c_int64), ("bytes_out", ctypes.c_int64), ("sr_flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("capacity_bytes", ctypes.c_int64), ("on_device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("nkpair", ctypes.c_int64), ("naux", ctypes.c_int64),
+                ("nao", ctypes.c_int64), ("stats", ctypes.POINTER(Stats))]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def library():
+    """Load librsgdf.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RsgdfError(-5, f"native library missing: {_LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        L.rsgdf_j3c_nbytes.restype = ctypes.c_int64
+        L.rsgdf_j3c_nbytes.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P]
+        L.rsgdf_build_j3c.restype = ctypes.c_int
+        L.rsgdf_build_j3c.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(Out)]
+        L.rsgdf_build_j3c_ex.restype = ctypes.c_int
+        L.rsgdf_build_j3c_ex.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                         ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options),
+                                         ctypes.POINTER(Out)]
+        L.rsgdf_last_error.restype = ctypes.c_char_p
+        L.rsgdf_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return library().rsgdf_version().decode()
+
+
+class _Marshal:
+    """Keeps the numpy arrays alive while the C structs point at them."""
+
+    def __init__(self, cell, basis, aux, kmesh):
+        self.keep = []
+        lat = np.ascontiguousarray(cell.lattice, np.float64).reshape(9)
+        crd = np.ascontiguousarray(cell.coords, np.float64)
+        self.keep += [lat, crd]
+        self.cell = Cell((ctypes.c_double * 9)(*lat.tolist()), int(crd.shape[0]), crd.ctypes.data)
+        self.basis = self._basis(basis)
+        self.aux = self._basis(aux)
+        self.kmesh = np.ascontiguousarray(kmesh, np.int32)
+        self.keep.append(self.kmesh)
+
+    def _basis(self, b):
+        arrs = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
+                np.ascontiguousarray(b.shell_nprim, np.int32), np.ascontiguousarray(b.shell_ptr, np.int32),
+                np.ascontiguousarray(b.exps, np.float64), np.ascontiguousarray(b.coefs, np.float64)]
+        self.keep += arrs
+        return BasisT(len(arrs[1]), *[a.ctypes.data for a in arrs])
+
+
+def _check(rc):
+    if rc != RSGDF_OK:
+        raise RsgdfError(rc, library().rsgdf_last_error().decode())
+
+
+def j3c_nbytes(cell, basis, aux, kmesh) -> int:
+    m = _Marshal(cell, basis, aux, kmesh)
+    n = library().rsgdf_j3c_nbytes(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                   m.kmesh.ctypes.data)
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def nkpairs(kmesh) -> int:
+    nk = int(np.prod(kmesh))
+    return nk * (nk + 1) // 2
+
+
+def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None, lr_precision=FP64,
+              screening=SCREEN_RIGOROUS, parts=PART_ALL, sr_slices=0, mlp_weights=None, mlp_margin=0.0,
+              stream=None):
+    """Run rsgdf_build_j3c_ex.
+
+    ``out``: a contiguous complex128 torch tensor on the GPU of shape
+    [nkpair, naux, nao, nao] (allocated here if None), or a numpy complex128
+    array (host output, staged through device memory by the library).
+    ``stream``: a torch.cuda.Stream (defaults to the current stream).
+    Returns (out, stats dict)."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    nbytes = j3c_nbytes(cell, basis, aux, kmesh)
+    shape = (nkpairs(kmesh), aux.nfunc, basis.nfunc, basis.nfunc)
+    on_device = True
+    if out is None:
+        import torch
+        out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    if isinstance(out, np.ndarray):
+        if out.dtype != np.complex128 or not out.flags.c_contiguous or out.nbytes < nbytes:
+            raise ValueError("host output must be a contiguous complex128 array of the full size")
+        on_device = False
+        ptr, cap = out.ctypes.data, out.nbytes
+        sptr = None
+    else:
+        import torch
+        if out.dtype != torch.complex128 or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("device output must be a contiguous complex128 CUDA tensor")
+        ptr, cap = out.data_ptr(), out.numel() * 16
+        if stream is None:
+            stream = torch.cuda.current_stream(out.device)
+        sptr = stream.cuda_stream
+    stats = Stats()
+    o = Out(ptr, cap, int(on_device), sptr, 0, 0, 0, ctypes.pointer(stats))
+    opts = Options(-1.0 if g_thresh is None else float(g_thresh), int(lr_precision), int(screening), int(parts),
+                   int(sr_slices), None if mlp_weights is None else str(mlp_weights).encode(), float(mlp_margin))
+    rc = library().rsgdf_build_j3c_ex(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                      m.kmesh.ctypes.data, float(omega), float(thresh), ctypes.byref(opts),
+                                      ctypes.byref(o))
+    _check(rc)
+    return out, stats.as_dict()
