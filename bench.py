@@ -1,0 +1,120 @@
+"""Benchmark: periodic RS-GDF three-center integrals (j3c) on one MI355X.
+
+Workload: the 8-atom diamond-like cubic cell (a = 6.74 bohr), Cartesian
+3s2p1d AO (n_AO = 120) and 8s6p4d2f aux (n_aux = 560) Gaussian bases drawn
+from a seeded generator, 2x2x2 k-mesh (36 k-pairs), omega = 0.1,
+threshold 1e-10, complex128 output (4.64 GB).  One step = one full
+rsgdf_build_j3c call (host planning + short-range lattice sums + Bloch fold
++ G=0 term + long-range reciprocal sum) into a preallocated device buffer.
+
+Prints one JSON line.  value = short-range primitive integrals per second
+(evaluated (aux primitive, AO primitive, AO primitive, image pair) tuples
+divided by the build wall time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR = 78.6e12  # 256 CU x 4 SIMD x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
+
+
+def cpu_baseline(problem, gpu_rate_unit="prim-integrals/s"):
+    """The oracle timed on the host cores on a bounded sample: aux shells of
+    atoms 0-3 against the first AO shell pair (s-s, 6x6 primitives), all 36
+    k-pairs; rate = oracle SR primitive terms / wall time."""
+    import numpy as np
+
+    import oracle
+    nshell_per_atom = problem.aux.nshell // problem.cell.natm
+    aux = [s for s in range(problem.aux.nshell) if problem.aux.shell_atom[s] < 4]
+    t0 = time.perf_counter()
+    _, counts = oracle.j3c(problem, aux_shells=aux, pairs=[(0, 0)], parts=oracle.PART_SR, return_counts=True)
+    dt = time.perf_counter() - t0
+    return {"value": float(counts[0]) / dt, "unit": gpu_rate_unit, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"C2 SR sum, aux shells of atoms 0-3 ({len(aux)} shells, {nshell_per_atom} per atom) x AO "
+                      f"pair (0,0), 36 k-pairs: {int(counts[0])} primitive terms in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2102_02989_amd as P
+    import synth
+
+    problem = synth.config2() if args.config == "c2" else synth.config1()
+    shape = (P.nkpairs(problem.kmesh), problem.aux.nfunc, problem.basis.nfunc, problem.basis.nfunc)
+    out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+
+    def step():
+        _, st = P.build_j3c(problem.cell, problem.basis, problem.aux, problem.kmesh, problem.omega,
+                            problem.thresh, out, g_thresh=problem.g_thr)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    n_terms = stats[-1]["n_sr_terms"]
+    value = n_terms / (ms * 1e-3)
+    t_sr = sum(s["t_sr_ms"] for s in stats) / len(stats)
+    flops = stats[-1]["sr_flops"]
+    achieved = flops / (t_sr * 1e-3)
+    line = {
+        "metric": "j3c build s per k-mesh + primitive integrals/s, chosen vs plain, err<=1e-6",
+        "value": value,
+        "unit": "prim-integrals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian bases and cells)",
+        "config": {"workload": f"{problem.name}: {problem.cell.natm}-atom cubic cell a=6.74, n_AO="
+                               f"{problem.basis.nfunc}, n_aux={problem.aux.nfunc}, kmesh "
+                               f"{'x'.join(map(str, problem.kmesh))} ({shape[0]} k-pairs), omega={problem.omega}, "
+                               f"thresh={problem.thresh}, plain FP64",
+                   "build_s": ms * 1e-3, "form": "plain", "chosen": None},
+        "phases_ms": {k: stats[-1][k] for k in ("t_plan_ms", "t_sr_ms", "t_fold_ms", "t_lr_ms", "t_total_ms")},
+        "counts": {k: stats[-1][k] for k in ("n_sr_terms", "n_sr_shell_terms", "n_lr_terms", "n_g_total",
+                                             "n_triplets")},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                     "kernel": "sr3c_kernel (all 24 angular-momentum classes of one build)",
+                     "flops_per_launch": flops, "avg_launch_ms": t_sr},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -620,17 +620,9 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     d_out = d_outbuf.as<double>();
   }
 
-  // waves per SR work item (each takes every slices-th pair image); X carries
-  // one partial copy per slice, summed by the fold
-  int slices = o.sr_slices;
-  if (slices <= 0) {
-    const int64_t nitems = (int64_t)nxs * npair;
-    slices = (int)std::min<int64_t>(64, std::max<int64_t>(1, (8192 + nitems - 1) / nitems));
-  }
-  if (slices < 1 || slices > 64) return fail(RSGDF_EINVAL, "sr_slices must be in 1..64");
-  const int nb = slices * nk * nk;  // rows of X: (slice, c1, c2)
+  const int nb = nk * nk;  // rows of X: (c1, c2)
 
-  // phase tables: Phi[kp][(s,c1,c2)] = e^{-i k1.L_c1} e^{+i k2.L_c2}; kphase[k][c] = e^{+i k.L_c}
+  // phase tables: Phi[kp][(c1,c2)] = e^{-i k1.L_c1} e^{+i k2.L_c2}; kphase[k][c] = e^{+i k.L_c}
   auto cell_ph = [&](int k, int c) {  // 2 pi sum_d j_d i_d / n_d
     const int j[3] = {k / (L.n[1] * L.n[2]), (k / L.n[2]) % L.n[1], k % L.n[2]};
     const int i[3] = {c / (L.n[1] * L.n[2]), (c / L.n[2]) % L.n[1], c % L.n[2]};
@@ -643,10 +635,8 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     for (int c1 = 0; c1 < nk; ++c1)
       for (int c2 = 0; c2 < nk; ++c2) {
         const double ph = -cell_ph(hp.kp1[t], c1) + cell_ph(hp.kp2[t], c2);
-        for (int sl = 0; sl < slices; ++sl) {
-          phi[2 * ((size_t)t * nb + (size_t)sl * nk * nk + c1 * nk + c2)] = std::cos(ph);
-          phi[2 * ((size_t)t * nb + (size_t)sl * nk * nk + c1 * nk + c2) + 1] = std::sin(ph);
-        }
+        phi[2 * ((size_t)t * nb + c1 * nk + c2)] = std::cos(ph);
+        phi[2 * ((size_t)t * nb + c1 * nk + c2) + 1] = std::sin(ph);
       }
   for (int k = 0; k < nk; ++k)
     for (int c = 0; c < nk; ++c) {
@@ -782,11 +772,140 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       if ((rcmax + r12max + 2.0 * diam) * hp.lt.bn[d] / (2.0 * kPi) + L.n[d] + 2 > 500.0)
         return fail(RSGDF_EUNSUPPORTED, "screening radius too large for the packed image coordinates");
   }
+  // ---- SR work list: a cost estimate per item (primitive triplets x pair
+  // images x lattice vectors in the R_c ball x per-term operations) decides how
+  // many waves share it, first by BvK cell ranges (disjoint outputs), then by
+  // interleaved pair-image slices with private partial blocks.
+  std::vector<SRWork> work;
+  std::vector<int> wgrp_off;        // [(nbatch) * 24 + 1]
+  std::vector<double> wgrp_cost;    // summed estimate per group
+  std::vector<SRPartGroup> pgroups;
+  std::vector<int> pgrp_off{0};     // per batch
+  int64_t part_total = 0;
+  {
+    std::vector<double> est(ntrip);
+    double tot = 0.0;
+    for (int64_t t = 0; t < ntrip; ++t) {
+      const Triplet &tr = trips[t];
+      const Pair &pp = hp.pairs[tr.pair];
+      const Shell &sA = hp.ao[pp.sa], &sB = hp.ao[pp.sb], &sP = hp.ax[tr.aux];
+      int64_t nimg = 0;
+      for (int c = 0; c < nk; ++c) nimg += hp.nsr[(size_t)tr.pair * nk + c];
+      const double nm = 4.18879020478639098 * tr.rc_cut * tr.rc_cut * tr.rc_cut / L.vol + 1.0;
+      const int Lt = sP.l + sA.l + sB.l;
+      est[t] = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg * nm * sr_term_flops(Lt);
+      tot += est[t];
+    }
+    // target cost per wave: 8 waves per SIMD over the build
+    const double target = std::max(tot / (8.0 * 1024.0), 1.0);
+    const double part_budget = 1.0e9;  // bytes of partial blocks
+    double part_bytes = 0.0;
+    std::vector<std::vector<SRWork>> grp((size_t)nbatch * 24);
+    std::vector<std::vector<double>> gcost((size_t)nbatch * 24);
+    for (int b = 0; b < nbatch; ++b) {
+      for (int g = 0; g < 24; ++g) {
+        for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t) {
+          const Triplet &tr = trips[t];
+          const Pair &pp = hp.pairs[tr.pair];
+          const int nblk = ncart_h(hp.ax[tr.aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+          const int64_t want = std::max<int64_t>(1, (int64_t)std::ceil(est[t] / target));
+          const int nsplit = (int)std::min<int64_t>(want, nk);
+          int ncbw = (nk + nsplit - 1) / nsplit;
+          ncbw = std::min(ncbw, 64);
+          const int nranges = (nk + ncbw - 1) / ncbw;
+          int nsl = (int)std::min<int64_t>(64, (want + nranges - 1) / nranges);
+          if (nsl > 1 && part_bytes + (double)nsl * nk * nk * nblk * 8.0 > part_budget) nsl = 1;
+          for (int r = 0; r < nranges; ++r) {
+            const int cb0 = r * ncbw, ncb = std::min(ncbw, nk - cb0);
+            int64_t pbase = -1;
+            if (nsl > 1) {
+              SRPartGroup pg{};
+              pg.trip = t;
+              pg.cb0 = cb0;
+              pg.ncb = ncb;
+              pg.nslice = nsl;
+              pg.part = part_total;
+              pgroups.push_back(pg);
+              pbase = part_total;
+              part_total += (int64_t)nsl * ncb * nk * nblk;
+              part_bytes += (double)nsl * ncb * nk * nblk * 8.0;
+            }
+            for (int sl = 0; sl < nsl; ++sl) {
+              SRWork w{};
+              w.trip = t;
+              w.cb0 = (int16_t)cb0;
+              w.ncb = (int16_t)ncb;
+              w.slice = (int16_t)sl;
+              w.nslice = (int16_t)nsl;
+              w.part = (nsl > 1) ? pbase + (int64_t)sl * ncb * nk * nblk : -1;
+              grp[(size_t)b * 24 + g].push_back(w);
+              gcost[(size_t)b * 24 + g].push_back(est[t] / ((double)nranges * nsl));
+            }
+          }
+        }
+      }
+      pgrp_off.push_back((int)pgroups.size());
+    }
+    // heaviest waves first inside each class launch
+    wgrp_off.push_back(0);
+    for (size_t g = 0; g < grp.size(); ++g) {
+      std::vector<int> idx(grp[g].size());
+      for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return gcost[g][x] > gcost[g][y]; });
+      double c = 0.0;
+      for (int i : idx) {
+        work.push_back(grp[g][i]);
+        c += gcost[g][i];
+      }
+      wgrp_off.push_back((int)work.size());
+      wgrp_cost.push_back(c);
+    }
+    // element prefix sums of the partial groups (per batch)
+    for (int b = 0; b < nbatch; ++b) {
+      int64_t off = 0;
+      for (int i = pgrp_off[b]; i < pgrp_off[b + 1]; ++i) {
+        SRPartGroup &pg = pgroups[i];
+        const Pair &pp = hp.pairs[trips[pg.trip].pair];
+        const int nblk = ncart_h(hp.ax[trips[pg.trip].aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+        pg.elem_off = off;
+        off += (int64_t)pg.ncb * nk * nblk;
+      }
+    }
+  }
+  const int64_t nwork = (int64_t)work.size();
+  DBuf d_work, d_part, d_pgrp;
   if (do_sr) {
     HIPCHK(upload(d_trip, trips, st));
-    HIPCHK(d_cnt.alloc((size_t)ntrip * slices * 4 * sizeof(long long)));
-    HIPCHK(hipMemsetAsync(d_cnt.p, 0, (size_t)ntrip * slices * 4 * sizeof(long long), st));
+    HIPCHK(upload(d_work, work, st));
+    HIPCHK(upload(d_pgrp, pgroups, st));
+    HIPCHK(d_part.alloc((size_t)std::max<int64_t>(part_total, 1) * sizeof(double)));
+    HIPCHK(d_cnt.alloc((size_t)nwork * 4 * sizeof(long long)));
+    HIPCHK(hipMemsetAsync(d_cnt.p, 0, (size_t)nwork * 4 * sizeof(long long), st));
   }
+  // side streams for concurrent class launches (default priority)
+  static thread_local std::vector<std::pair<int, hipStream_t>> side_streams;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::vector<hipStream_t> ss;
+  for (auto &pr_ : side_streams)
+    if (pr_.first == dev) ss.push_back(pr_.second);
+  while (ss.size() < 4) {
+    hipStream_t s_;
+    HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    side_streams.push_back({dev, s_});
+    ss.push_back(s_);
+  }
+  hipEvent_t evf, evj[4];
+  HIPCHK(hipEventCreateWithFlags(&evf, hipEventDisableTiming));
+  for (auto &e : evj) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  struct EvGuard2 {
+    hipEvent_t f;
+    hipEvent_t *j;
+    ~EvGuard2() {
+      (void)hipEventDestroy(f);
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(j[i]);
+    }
+  } evg2{evf, evj};
 
   float t_sr = 0.f, t_fold = 0.f;
   for (int b = 0; b < nbatch; ++b) {
@@ -795,6 +914,7 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     HIPCHK(hipEventRecord(ev[1], st));
     if (do_sr) {
       HIPCHK(hipMemsetAsync(d_X.p, 0, (size_t)nf * nb * nao2 * sizeof(double), st));
+      if (part_total > 0) HIPCHK(hipMemsetAsync(d_part.p, 0, (size_t)part_total * sizeof(double), st));
       SRParams prm{};
       prm.ao = d_ao.as<Shell>();
       prm.ax = d_ax.as<Shell>();
@@ -809,8 +929,8 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       prm.nsr = d_nsr.as<int32_t>();
       prm.img = d_img.as<double>();
       prm.trip = d_trip.as<Triplet>();
-      prm.ntrip = (int32_t)ntrip;
-      prm.slices = slices;
+      prm.work = d_work.as<SRWork>();
+      prm.part = d_part.as<double>();
       prm.lat = L;
       prm.omega = omega;
       prm.eps = thresh;
@@ -823,9 +943,32 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       prm.naux_b = (int32_t)nf;
       prm.nao = (int32_t)nao;
       prm.counts = d_cnt.as<long long>();
-      for (int g = 0; g < 24; ++g) {
-        const int t0 = tgrp_off[(size_t)b * 24 + g], t1 = tgrp_off[(size_t)b * 24 + g + 1];
-        HIPCHK(launch_sr3c(g / 6, g % 6, prm, t0, t1 - t0, st));
+      // fork: classes in decreasing cost order, round-robin over the side streams
+      HIPCHK(hipEventRecord(evf, st));
+      for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, evf, 0));
+      std::vector<int> order(24);
+      for (int g = 0; g < 24; ++g) order[g] = g;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int x, int y) { return wgrp_cost[(size_t)b * 24 + x] > wgrp_cost[(size_t)b * 24 + y]; });
+      int k = 0;
+      for (int g : order) {
+        const int w0 = wgrp_off[(size_t)b * 24 + g], w1 = wgrp_off[(size_t)b * 24 + g + 1];
+        if (w1 == w0) continue;
+        HIPCHK(launch_sr3c(g / 6, g % 6, prm, w0, w1 - w0, ss[k % ss.size()]));
+        ++k;
+      }
+      for (size_t i = 0; i < ss.size(); ++i) {
+        HIPCHK(hipEventRecord(evj[i], ss[i]));
+        HIPCHK(hipStreamWaitEvent(st, evj[i], 0));
+      }
+      // sum split items into X
+      const int pg0 = pgrp_off[b], pg1 = pgrp_off[b + 1];
+      if (pg1 > pg0) {
+        const SRPartGroup &last = pgroups[pg1 - 1];
+        const Pair &pp = hp.pairs[trips[last.trip].pair];
+        const int nblk = ncart_h(hp.ax[trips[last.trip].aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+        const int64_t nelem = last.elem_off + (int64_t)last.ncb * nk * nblk;
+        HIPCHK(launch_sr_reduce(prm, d_pgrp.as<SRPartGroup>() + pg0, pg1 - pg0, nelem, st));
       }
     }
     HIPCHK(hipEventRecord(ev[2], st));
@@ -990,8 +1133,13 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     s.n_aux_batches = nbatch;
     s.bytes_out = need;
     if (do_sr && ntrip > 0) {
-      std::vector<long long> cnt((size_t)ntrip * slices * 4);
+      std::vector<long long> cnt((size_t)nwork * 4);
       HIPCHK(hipMemcpy(cnt.data(), d_cnt.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
+      std::vector<long long> tterms(ntrip, 0), tshell(ntrip, 0);
+      for (int64_t w = 0; w < nwork; ++w) {
+        tterms[work[w].trip] += cnt[(size_t)w * 4];
+        tshell[work[w].trip] += cnt[(size_t)w * 4 + 2];
+      }
       double flops = 0.0;
       for (int b = 0; b < nbatch; ++b)
         for (int g = 0; g < 24; ++g) {
@@ -1000,9 +1148,9 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
           const int Lt = lP + la_of[pc] + lb_of[pc];
           long long nt = 0;
           for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t)
-            for (int w = 0; w < slices; ++w) {
-              nt += cnt[((size_t)t * slices + w) * 4];
-              s.n_sr_shell_terms += cnt[((size_t)t * slices + w) * 4 + 2];
+            {
+              nt += tterms[t];
+              s.n_sr_shell_terms += tshell[t];
             }
           s.n_sr_terms += nt;
           flops += (double)nt * sr_term_flops(Lt);
@@ -1013,7 +1161,7 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
         if (FILE *f = std::fopen(fn, "w")) {
           for (int64_t t = 0; t < ntrip; ++t) {
             long long nt = 0;
-            for (int w = 0; w < slices; ++w) nt += cnt[((size_t)t * slices + w) * 4];
+            nt = tterms[t];
             const Pair &pr = hp.pairs[trips[t].pair];
             std::fprintf(f, "%d %d %d %d %d %lld %.3f\n", trips[t].aux, trips[t].pair, hp.ax[trips[t].aux].l,
                          hp.ao[pr.sa].l, hp.ao[pr.sb].l, nt, trips[t].rc_cut);

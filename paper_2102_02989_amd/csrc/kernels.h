@@ -78,7 +78,9 @@ struct LRGemmParams {
 
 int pair_class(int la, int lb);
 int sr_term_flops(int L);
-hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int trip0, int ntrip, hipStream_t stream);
+hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int w0, int nwork, hipStream_t stream);
+hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int ngroups, int64_t nelem,
+                            hipStream_t stream);
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream);
 hipError_t launch_overlaps(const OvlParams &op, const SmnParams &sp, hipStream_t stream);
 hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream);

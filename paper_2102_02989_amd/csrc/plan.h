@@ -53,6 +53,25 @@ struct Triplet {
   double amp;        // 1s-model amplitude A of Eq. S4 (primitive amplitudes summed)
 };
 
+// One wavefront's share of a work item: BvK cells c1 in [cb0, cb0 + ncb) and
+// pair images with list index = slice (mod nslice).  part >= 0: the wave
+// writes its sums to a private partial block [ncb][Nk][nblk] at that offset
+// (summed into X afterwards in a fixed order); part < 0: it adds into X.
+struct SRWork {
+  int32_t trip;
+  int16_t cb0, ncb;
+  int16_t slice, nslice;
+  int32_t pad;
+  int64_t part;
+};
+
+// Partial blocks of one (work item, cell range) split over nslice waves.
+struct SRPartGroup {
+  int32_t trip, cb0, ncb, nslice;
+  int64_t part;       // first slice's block (doubles)
+  int64_t elem_off;   // prefix sum of ncb * Nk * nblk over groups
+};
+
 // Lattice and k-mesh constants.
 struct Lattice {
   double a[9];       // rows a1, a2, a3
@@ -74,15 +93,15 @@ struct SRParams {
   const int32_t *nsr;       // per pair: Nk counts
   const double *img;        // image vectors, 3 doubles each
   const Triplet *trip;
-  int32_t ntrip;
-  int32_t slices;           // waves per work item (interleaved pair images)
+  const SRWork *work;
+  double *part;             // partial blocks of split work items
   Lattice lat;
   double omega, eps, dR;
   double ncell_nf, ncell_r0;  // N_cell model of Eq. S19
   const double *boys;       // [L = 0..kMaxL][kBoysIntervals][kBoysPolyDeg + 1]
-  double *X;                // [slices][Nk][Nk][naux_b][nao][nao]
+  double *X;                // [Nk][Nk][naux_b][nao][nao]
   int32_t aux_f0, naux_b, nao, pad;
-  long long *counts;        // [item][4]: primitive terms, contractions, shell terms, 0
+  long long *counts;        // [work entry][4]: primitive terms, contractions, shell terms, 0
 };
 
 }  // namespace rsgdf

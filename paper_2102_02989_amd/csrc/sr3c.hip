@@ -1,6 +1,7 @@
 // sr3c.hip -- short-range (erfc-attenuated) three-center lattice sums on gfx950.
 //
-// Work item: (aux shell P, AO shell pair, slice).  One wavefront per item.
+// Work item: (aux shell P, AO shell pair); a wavefront takes a range of BvK
+// cells c1 and an interleaved share of the pair images (SRWork).
 // The term (P^0 | erfc(w r)/r | mu^m nu^{m+n'}) of Eq. (M12)/(M13a) is
 // rewritten by translation as (P^{-m} | mu^0 nu^{n'}): for a pair image n' the
 // AO pair density is fixed and the aux function moves over lattice vectors m.
@@ -22,9 +23,11 @@
 //      over the group with a fixed xor-butterfly, and contracts them with the
 //      pair (E^ab) and aux (E^c) Hermite coefficients;
 //   3. adds the Cartesian block into an LDS accumulator per group, flushed to
-//      X[slice][c1][c2][P][mu][nu] when the class of n' changes.
-// Every X element is owned by one wave and one group, so results are
-// deterministic without atomics; the fold adds the slices.
+//      X[c1][c2][P][mu][nu] (or to the wave's partial block when the images
+//      of the item are split over several waves) when the class of n' changes.
+// Every X element (and every partial element) is owned by one wave and one
+// group, so results are deterministic without atomics; split items are summed
+// by sr_reduce_kernel in slice order.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -92,7 +95,7 @@ __device__ __forceinline__ void unpack3(int v, int &a, int &b, int &c) {
 
 template <int LP, int LA, int LB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-void sr3c_kernel(const SRParams prm, const int trip0) {
+void sr3c_kernel(const SRParams prm, const int w0) {
   constexpr int NCP = ncart(LP), NCA = ncart(LA), NCB = ncart(LB);
   constexpr int NBLK = NCP * NCA * NCB;
   constexpr int LAB = LA + LB, L = LAB + LP;
@@ -103,10 +106,10 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
   __shared__ double s_blk[kBlkCap];
 
   const int lane = threadIdx.x;
-  const int item = blockIdx.x;
-  const int S = prm.slices;
-  const int slice = item % S;
-  const Triplet tr = prm.trip[trip0 + item / S];
+  const SRWork wk = prm.work[w0 + blockIdx.x];
+  const int S = wk.nslice;
+  const int slice = wk.slice;
+  const Triplet tr = prm.trip[wk.trip];
   const Shell shP = prm.ax[tr.aux];
   const Pair pr = prm.pairs[tr.pair];
   const Shell shA = prm.ao[pr.sa];
@@ -150,25 +153,25 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) bn[d] = sqrt(b[3 * d] * b[3 * d] + b[3 * d + 1] * b[3 * d + 1] + b[3 * d + 2] * b[3 * d + 2]);
 
-  // group layout
+  // group layout: ncb groups of gs lanes, group gl owns BvK cell cb0 + gl
+  const int ncbw = wk.ncb;
   int gs = 1;
-  while (gs * 2 * nk <= 64) gs *= 2;
-  const int ngrp_max = 64 / gs;
+  while (gs * 2 * ncbw <= 64) gs *= 2;
   const int lig = lane % gs;
-  const int gl = lane / gs;  // group index inside a round of BvK cells
+  const int gl = lane / gs;
   const unsigned long long gmask_lo = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
-  const bool blk_in_lds = (long long)NBLK * (nk < ngrp_max ? nk : ngrp_max) <= kBlkCap;
+  const bool blk_in_lds = (long long)NBLK * ncbw <= kBlkCap;
+  double *const part = (wk.part >= 0) ? prm.part + wk.part : nullptr;
 
   const size_t xplane = (size_t)prm.naux_b * prm.nao * prm.nao;
   const int pf0 = shP.foff - prm.aux_f0;
   long long n_terms = 0, n_contr = 0, n_shell = 0;
 
   const int nimg_all = prm.cls_off[pr.cls_off + nk];
-  const int nround = (nk + ngrp_max - 1) / ngrp_max;
 
-  for (int round = 0; round < nround; ++round) {
-    const int c1 = round * ngrp_max + gl;  // this group's BvK cell
-    const int ngrp = min(ngrp_max, nk - round * ngrp_max);
+  {
+    const int c1 = wk.cb0 + gl;  // this group's BvK cell
+    const int ngrp = ncbw;
     const bool grp_on = gl < ngrp;
     int i1[3] = {0, 0, 0};
     if (grp_on) {
@@ -187,12 +190,17 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
         const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
         const int c2 = (((i1[0] + dc0) % lat.n[0]) * lat.n[1] + (i1[1] + dc1) % lat.n[1]) * lat.n[2] +
                        (i1[2] + dc2) % lat.n[2];
-        double *X12 = prm.X + (size_t)((slice * nk + c1) * nk + c2) * xplane;
-        double *X21 = prm.X + (size_t)((slice * nk + c2) * nk + c1) * xplane;
+        double *X12 = prm.X + (size_t)(c1 * nk + c2) * xplane;
+        double *X21 = prm.X + (size_t)(c2 * nk + c1) * xplane;
+        double *pb = part ? part + ((size_t)gl * nk + c2) * NBLK : nullptr;
         for (int comp = lig; comp < NBLK; comp += gs) {
           const double v = s_blk[gl * NBLK + comp];
           s_blk[gl * NBLK + comp] = 0.0;
           if (v == 0.0) continue;
+          if (pb) {
+            pb[comp] += v;
+            continue;
+          }
           const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
           const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
           X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += v;
@@ -349,13 +357,14 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
               const double coef = ((LP & 1) ? -1.0 : 1.0) * cc * ca * cb * Kab * pref;
               double EP[LP + 1][LP + 1];
               hermite_E1<LP>(0.5 / gc, EP);
-              double *X12 = nullptr, *X21 = nullptr;
+              double *X12 = nullptr, *X21 = nullptr, *pb = nullptr;
               if (!blk_in_lds && grp_on) {
                 const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
                 const int c2 = (((i1[0] + dc0) % lat.n[0]) * lat.n[1] + (i1[1] + dc1) % lat.n[1]) * lat.n[2] +
                                (i1[2] + dc2) % lat.n[2];
-                X12 = prm.X + (size_t)((slice * nk + c1) * nk + c2) * xplane;
-                X21 = prm.X + (size_t)((slice * nk + c2) * nk + c1) * xplane;
+                X12 = prm.X + (size_t)(c1 * nk + c2) * xplane;
+                X21 = prm.X + (size_t)(c2 * nk + c1) * xplane;
+                if (part) pb = part + ((size_t)gl * nk + c2) * NBLK;
               }
 #pragma unroll
               for (int ic = 0; ic < NCP; ++ic) {
@@ -395,6 +404,8 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
                           s += Ex[ax_][bx_][t] * Ey[ay_][by_][uu] * Ez[az_][bz_][v] * Wc[hidx(t, uu, v)];
                     if (blk_in_lds) {
                       s_blk[gl * NBLK + comp] += coef * s;
+                    } else if (pb) {
+                      pb[comp] += coef * s;
                     } else {
                       const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
                       X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += coef * s;
@@ -426,7 +437,7 @@ void sr3c_kernel(const SRParams prm, const int trip0) {
     n_shell += __shfl_xor(n_shell, off, 64);
   }
   if (lane == 0) {
-    long long *dst = prm.counts + 4 * ((size_t)trip0 * S + item);
+    long long *dst = prm.counts + 4 * ((size_t)w0 + blockIdx.x);
     dst[0] = n_terms;
     dst[1] = n_contr;
     dst[2] = n_shell;
@@ -442,6 +453,46 @@ int sr_term_flops(int L) {
   const int geo = 13;
   const int boys = 2 * (2 * kBoysPolyDeg + 3 * L + 1) + 3 * (L + 1);
   return geo + boys + 2 * L + hermite_R_flops(L) + nherm(L);
+}
+
+// Sum the partial blocks of split work items (slice order) into X, direct and
+// transposed entries.  One thread per element of a (work item, cell range).
+__global__ void sr_reduce_kernel(const SRParams prm, const SRPartGroup *__restrict__ groups, int ngroups,
+                                 int64_t nelem) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nelem) return;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (groups[mid].elem_off <= gid) lo = mid;
+    else hi = mid - 1;
+  }
+  const SRPartGroup g = groups[lo];
+  const int64_t e = gid - g.elem_off;
+  const Triplet tr = prm.trip[g.trip];
+  const Pair pr = prm.pairs[tr.pair];
+  const Shell shP = prm.ax[tr.aux], shA = prm.ao[pr.sa], shB = prm.ao[pr.sb];
+  const int nca = ncart(shA.l), ncb = ncart(shB.l), nblk = ncart(shP.l) * nca * ncb;
+  const int nk = prm.lat.nk;
+  const int64_t blk = (int64_t)g.ncb * nk * nblk;
+  double v = 0.0;
+  for (int s = 0; s < g.nslice; ++s) v += prm.part[g.part + s * blk + e];
+  const int comp = (int)(e % nblk);
+  const int c2 = (int)((e / nblk) % nk);
+  const int c1 = g.cb0 + (int)(e / ((int64_t)nblk * nk));
+  const int ic = comp / (nca * ncb), ia = (comp / ncb) % nca, ib = comp % ncb;
+  const size_t xplane = (size_t)prm.naux_b * prm.nao * prm.nao;
+  const size_t rowP = (size_t)(shP.foff - prm.aux_f0 + ic) * prm.nao;
+  prm.X[(size_t)(c1 * nk + c2) * xplane + (rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += v;
+  if (!pr.diag) prm.X[(size_t)(c2 * nk + c1) * xplane + (rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += v;
+}
+
+hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int ngroups, int64_t nelem,
+                            hipStream_t stream) {
+  if (ngroups <= 0 || nelem <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sr_reduce_kernel, dim3((unsigned)((nelem + 255) / 256)), dim3(256), 0, stream, prm, groups,
+                     ngroups, nelem);
+  return hipGetLastError();
 }
 
 typedef void (*sr_kernel_t)(const SRParams, const int);
@@ -464,9 +515,9 @@ int pair_class(int la, int lb) {
   return t[la][lb];
 }
 
-hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int trip0, int ntrip, hipStream_t stream) {
-  if (ntrip <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kSRTable[lP][pc], dim3((unsigned)(ntrip * prm.slices)), dim3(64), 0, stream, prm, trip0);
+hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int w0, int nwork, hipStream_t stream) {
+  if (nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kSRTable[lP][pc], dim3((unsigned)nwork), dim3(64), 0, stream, prm, w0);
   return hipGetLastError();
 }
 
