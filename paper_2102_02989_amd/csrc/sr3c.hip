@@ -39,6 +39,35 @@ namespace rsgdf {
 constexpr int kCandCap = 1536;    // lattice-vector candidates held in LDS per wave
 constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators in LDS
 constexpr int kSRWinCap = 256;    // screening windows held in LDS
+constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
+
+// (t,u,v) of Hermite index h (inverse of hidx)
+__device__ __forceinline__ void herm_decode(int h, int &t, int &u, int &v) {
+  int s = 0;
+  while (nherm(s) <= h) ++s;
+  const int rem = h - (s > 0 ? nherm(s - 1) : 0);
+  int r = 0;
+  while ((r + 1) * (r + 2) / 2 <= rem) ++r;
+  v = rem - r * (r + 1) / 2;
+  u = r - v;
+  t = s - r;
+}
+
+// Cartesian powers of component i of angular momentum l
+__device__ __forceinline__ void cart_decode(int l, int i, int &x, int &y, int &z) {
+  int n = 0;
+  for (int lx = l; lx >= 0; --lx)
+    for (int ly = l - lx; ly >= 0; --ly) {
+      if (n == i) {
+        x = lx;
+        y = ly;
+        z = l - lx - ly;
+        return;
+      }
+      ++n;
+    }
+  x = y = z = 0;
+}
 
 // F_L(T) for 0 <= T < kBoysSwitch from the per-L polynomial table (Taylor
 // expansion of degree kBoysPolyDeg about each unit interval's centre), then the
@@ -100,10 +129,17 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   constexpr int NBLK = NCP * NCA * NCB;
   constexpr int LAB = LA + LB, L = LAB + LP;
   constexpr int NH = nherm(L);
-  __shared__ double s_nf[kSRWinCap];
+  constexpr int NHAB = nherm(LAB);
+  constexpr int EA = (LA + 1) * (LB + 1) * (LAB + 1);
+  constexpr int BLK = (NBLK * kMaxCellsPerWave <= kBlkCap) ? NBLK * kMaxCellsPerWave : 1;
+  __shared__ float s_nf[kSRWinCap];
   __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
   __shared__ int s_cand[kCandCap];
-  __shared__ double s_blk[kBlkCap];
+  __shared__ double s_blk[BLK];
+  __shared__ double s_R[kMaxCellsPerWave * NH];
+  __shared__ double s_W[NCP * NHAB];
+  __shared__ double s_E[3 * EA];
+  __shared__ double s_EP[(LP + 1) * (LP + 1)];
 
   const int lane = threadIdx.x;
   const SRWork wk = prm.work[w0 + blockIdx.x];
@@ -135,10 +171,10 @@ void sr3c_kernel(const SRParams prm, const int w0) {
       const double N = (R > prm.ncell_r0) ? fourpi_vol * 2.0 * (R + dR) * (R + dR) * dR : prm.ncell_nf;
       const double f = (R < 1e-12) ? 2.0 * (eta1 - eta2) * 0.564189583547756286948079451561 /* 1/sqrt(pi) */
                                    : (erf(eta1 * R) - erf(eta2 * R)) / R;
-      s_nf[w] = pref * N * f;
+      s_nf[w] = (float)(pref * N * f);
     }
   }
-  for (int i = lane; i < kBlkCap; i += 64) s_blk[i] = 0.0;
+  for (int i = lane; i < BLK; i += 64) s_blk[i] = 0.0;
   __syncthreads();
   const double xstar = 1.0 / sqrt(2.0 * beta);
   const double gmax = xstar * exp(-0.5);
@@ -160,7 +196,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   const int lig = lane % gs;
   const int gl = lane / gs;
   const unsigned long long gmask_lo = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
-  const bool blk_in_lds = (long long)NBLK * ncbw <= kBlkCap;
+  const bool blk_in_lds = BLK > 1 && NBLK * ncbw <= BLK;
   double *const part = (wk.part >= 0) ? prm.part + wk.part : nullptr;
 
   const size_t xplane = (size_t)prm.naux_b * prm.nao * prm.nao;
@@ -348,71 +384,90 @@ void sr3c_kernel(const SRParams prm, const int w0) {
 #pragma unroll
                 for (int i = 0; i < NH; ++i) Rb[i] += __shfl_xor(Rb[i], off, 64);
               }
-              // ---- contraction with the Hermite expansion coefficients
-              double Ex[LA + 1][LB + 1][LAB + 1], Ey[LA + 1][LB + 1][LAB + 1], Ez[LA + 1][LB + 1][LAB + 1];
-              hermite_E<LA, LB>(Px - Ax, Px - Bx, 0.5 * oop, Ex);
-              hermite_E<LA, LB>(Py - Ay, Py - By, 0.5 * oop, Ey);
-              hermite_E<LA, LB>(Pz - Az, Pz - Bz, 0.5 * oop, Ez);
+              // ---- contraction with the Hermite expansion coefficients: the
+              // group sums go to LDS and the whole wave contracts one group at
+              // a time, output components spread over the 64 lanes.
+              if (lig == 0 && grp_on) {
+#pragma unroll
+                for (int i = 0; i < NH; ++i) s_R[gl * NH + i] = Rb[i];
+              }
+              if (lane < 3) {
+                double E1[LA + 1][LB + 1][LAB + 1];
+                const double PAd = (lane == 0) ? Px - Ax : (lane == 1 ? Py - Ay : Pz - Az);
+                const double PBd = (lane == 0) ? Px - Bx : (lane == 1 ? Py - By : Pz - Bz);
+                hermite_E<LA, LB>(PAd, PBd, 0.5 * oop, E1);
+#pragma unroll
+                for (int i = 0; i <= LA; ++i)
+#pragma unroll
+                  for (int j = 0; j <= LB; ++j)
+#pragma unroll
+                    for (int t = 0; t <= LAB; ++t) s_E[lane * EA + (i * (LB + 1) + j) * (LAB + 1) + t] = E1[i][j][t];
+              } else if (lane == 3) {
+                double E2[LP + 1][LP + 1];
+                hermite_E1<LP>(0.5 / gc, E2);
+#pragma unroll
+                for (int i = 0; i <= LP; ++i)
+#pragma unroll
+                  for (int t = 0; t <= LP; ++t) s_EP[i * (LP + 1) + t] = E2[i][t];
+              }
+              __syncthreads();
               const double pref = 2.0 * kPi * kPi * sqrt(kPi) / (p * gc * sqrt(p + gc));
               const double coef = ((LP & 1) ? -1.0 : 1.0) * cc * ca * cb * Kab * pref;
-              double EP[LP + 1][LP + 1];
-              hermite_E1<LP>(0.5 / gc, EP);
-              double *X12 = nullptr, *X21 = nullptr, *pb = nullptr;
-              if (!blk_in_lds && grp_on) {
-                const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
-                const int c2 = (((i1[0] + dc0) % lat.n[0]) * lat.n[1] + (i1[1] + dc1) % lat.n[1]) * lat.n[2] +
-                               (i1[2] + dc2) % lat.n[2];
-                X12 = prm.X + (size_t)(c1 * nk + c2) * xplane;
-                X21 = prm.X + (size_t)(c2 * nk + c1) * xplane;
-                if (part) pb = part + ((size_t)gl * nk + c2) * NBLK;
-              }
-#pragma unroll
-              for (int ic = 0; ic < NCP; ++ic) {
-                const int cx = cart_lx(LP, ic), cy = cart_ly(LP, ic), cz = cart_lz(LP, ic);
-                double Wc[nherm(LAB)];
-#pragma unroll
-                for (int t = 0; t <= LAB; ++t)
-#pragma unroll
-                  for (int uu = 0; uu <= LAB - t; ++uu)
-#pragma unroll
-                    for (int v = 0; v <= LAB - t - uu; ++v) {
-                      double s = 0.0;
-#pragma unroll
-                      for (int tau = cx & 1; tau <= cx; tau += 2)
-#pragma unroll
-                        for (int nu = cy & 1; nu <= cy; nu += 2)
-#pragma unroll
-                          for (int phi = cz & 1; phi <= cz; phi += 2)
-                            s += EP[cx][tau] * EP[cy][nu] * EP[cz][phi] * Rb[hidx(t + tau, uu + nu, v + phi)];
-                      Wc[hidx(t, uu, v)] = s;
+              for (int g = 0; g < ngrp; ++g) {
+                // W[ic][h] = sum_{tau nu phi} E^c R_{h + (tau nu phi)}
+                for (int idx = lane; idx < NCP * NHAB; idx += 64) {
+                  const int ic = idx / NHAB, h = idx - (idx / NHAB) * NHAB;
+                  int t, u, v, cx, cy, cz;
+                  herm_decode(h, t, u, v);
+                  cart_decode(LP, ic, cx, cy, cz);
+                  double sw = 0.0;
+                  for (int tau = cx & 1; tau <= cx; tau += 2)
+                    for (int nu = cy & 1; nu <= cy; nu += 2)
+                      for (int phi = cz & 1; phi <= cz; phi += 2)
+                        sw += s_EP[cx * (LP + 1) + tau] * s_EP[cy * (LP + 1) + nu] * s_EP[cz * (LP + 1) + phi] *
+                              s_R[g * NH + hidx(t + tau, u + nu, v + phi)];
+                  s_W[idx] = sw;
+                }
+                __syncthreads();
+                double *X12 = nullptr, *X21 = nullptr, *pb = nullptr;
+                if (!blk_in_lds) {
+                  const int cg = wk.cb0 + g;
+                  const int ig0 = cg / (lat.n[1] * lat.n[2]), ig1 = (cg / lat.n[2]) % lat.n[1], ig2 = cg % lat.n[2];
+                  const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
+                  const int c2 = (((ig0 + dc0) % lat.n[0]) * lat.n[1] + (ig1 + dc1) % lat.n[1]) * lat.n[2] +
+                                 (ig2 + dc2) % lat.n[2];
+                  X12 = prm.X + (size_t)(cg * nk + c2) * xplane;
+                  X21 = prm.X + (size_t)(c2 * nk + cg) * xplane;
+                  if (part) pb = part + ((size_t)g * nk + c2) * NBLK;
+                }
+                for (int comp = lane; comp < NBLK; comp += 64) {
+                  const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
+                  int ax_, ay_, az_, bx_, by_, bz_, q0, q1, q2;
+                  cart_decode(LA, ia, ax_, ay_, az_);
+                  cart_decode(LB, ib, bx_, by_, bz_);
+                  (void)q0; (void)q1; (void)q2;
+                  const double *ex = s_E + 0 * EA + (ax_ * (LB + 1) + bx_) * (LAB + 1);
+                  const double *ey = s_E + 1 * EA + (ay_ * (LB + 1) + by_) * (LAB + 1);
+                  const double *ez = s_E + 2 * EA + (az_ * (LB + 1) + bz_) * (LAB + 1);
+                  const double *wr = s_W + ic * NHAB;
+                  double so = 0.0;
+                  for (int t = 0; t <= ax_ + bx_; ++t)
+                    for (int u = 0; u <= ay_ + by_; ++u) {
+                      const double exy = ex[t] * ey[u];
+                      for (int v = 0; v <= az_ + bz_; ++v) so += exy * ez[v] * wr[hidx(t, u, v)];
                     }
-#pragma unroll
-                for (int ia = 0; ia < NCA; ++ia) {
-                  const int ax_ = cart_lx(LA, ia), ay_ = cart_ly(LA, ia), az_ = cart_lz(LA, ia);
-#pragma unroll
-                  for (int ib = 0; ib < NCB; ++ib) {
-                    const int bx_ = cart_lx(LB, ib), by_ = cart_ly(LB, ib), bz_ = cart_lz(LB, ib);
-                    const int comp = (ic * NCA + ia) * NCB + ib;
-                    if (comp % gs != lig || !grp_on) continue;
-                    double s = 0.0;
-#pragma unroll
-                    for (int t = 0; t <= ax_ + bx_; ++t)
-#pragma unroll
-                      for (int uu = 0; uu <= ay_ + by_; ++uu)
-#pragma unroll
-                        for (int v = 0; v <= az_ + bz_; ++v)
-                          s += Ex[ax_][bx_][t] * Ey[ay_][by_][uu] * Ez[az_][bz_][v] * Wc[hidx(t, uu, v)];
-                    if (blk_in_lds) {
-                      s_blk[gl * NBLK + comp] += coef * s;
-                    } else if (pb) {
-                      pb[comp] += coef * s;
-                    } else {
-                      const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
-                      X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += coef * s;
-                      if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += coef * s;
-                    }
+                  const double val = coef * so;
+                  if (blk_in_lds) {
+                    s_blk[g * NBLK + comp] += val;
+                  } else if (pb) {
+                    pb[comp] += val;
+                  } else {
+                    const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
+                    X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += val;
+                    if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
                   }
                 }
+                __syncthreads();
               }
               ++n_contr;
             }
