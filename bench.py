@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed steps, run one plain device copy of this many MiB (a known-size "
+                         "reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported",
@@ -111,6 +114,14 @@ def main():
                      "flops_per_launch": flops, "avg_launch_ms": t_sr},
         "cpu_baseline": None,
     }
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = n * 8
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(line), flush=True)

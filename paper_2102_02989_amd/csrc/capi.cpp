@@ -811,7 +811,7 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
           const int64_t want = std::max<int64_t>(1, (int64_t)std::ceil(est[t] / target));
           const int nsplit = (int)std::min<int64_t>(want, nk);
           int ncbw = (nk + nsplit - 1) / nsplit;
-          ncbw = std::min(ncbw, 8);  // lane groups per wave (kernel LDS layout)
+          ncbw = std::min(ncbw, sr_cells_per_wave(nblk));  // lane groups per wave (LDS accumulators)
           const int nranges = (nk + ncbw - 1) / ncbw;
           int nsl = (int)std::min<int64_t>(64, (want + nranges - 1) / nranges);
           if (nsl > 1 && part_bytes + (double)nsl * nk * nk * nblk * 8.0 > part_budget) nsl = 1;

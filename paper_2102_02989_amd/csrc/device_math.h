@@ -87,6 +87,70 @@ __device__ __forceinline__ void hermite_R(double X, double Y, double Z, const do
   }
 }
 
+// As hermite_R<L> but adds R^(0)_tuv into Racc: levels n >= 1 are built in a
+// scratch array of nherm(L-1) entries; level 0 is formed and accumulated
+// directly, shell by shell from the top (it only reads level-1 values).
+template <int L>
+__device__ __forceinline__ void hermite_R_acc(double X, double Y, double Z, const double (&g)[L + 1],
+                                              double (&Racc)[nherm(L)]) {
+  if constexpr (L == 0) {
+    Racc[0] += g[0];
+  } else {
+    double R[nherm(L - 1)];
+    R[0] = g[L];
+#pragma unroll
+    for (int n = L - 1; n >= 1; --n) {
+#pragma unroll
+      for (int s = L - n; s >= 1; --s) {
+#pragma unroll
+        for (int t = s; t >= 0; --t) {
+#pragma unroll
+          for (int u = s - t; u >= 0; --u) {
+            const int v = s - t - u;
+            double val;
+            if (t > 0) {
+              val = X * R[hidx(t - 1, u, v)];
+              if (t > 1) val += (t - 1) * R[hidx(t - 2, u, v)];
+            } else if (u > 0) {
+              val = Y * R[hidx(t, u - 1, v)];
+              if (u > 1) val += (u - 1) * R[hidx(t, u - 2, v)];
+            } else {
+              val = Z * R[hidx(t, u, v - 1)];
+              if (v > 1) val += (v - 1) * R[hidx(t, u, v - 2)];
+            }
+            R[hidx(t, u, v)] = val;
+          }
+        }
+      }
+      R[0] = g[n];
+    }
+    // level 0: R^(0)_{tuv} from level-1 entries (shells s-1, s-2)
+#pragma unroll
+    for (int s = L; s >= 1; --s) {
+#pragma unroll
+      for (int t = s; t >= 0; --t) {
+#pragma unroll
+        for (int u = s - t; u >= 0; --u) {
+          const int v = s - t - u;
+          double val;
+          if (t > 0) {
+            val = X * R[hidx(t - 1, u, v)];
+            if (t > 1) val += (t - 1) * R[hidx(t - 2, u, v)];
+          } else if (u > 0) {
+            val = Y * R[hidx(t, u - 1, v)];
+            if (u > 1) val += (u - 1) * R[hidx(t, u - 2, v)];
+          } else {
+            val = Z * R[hidx(t, u, v - 1)];
+            if (v > 1) val += (v - 1) * R[hidx(t, u, v - 2)];
+          }
+          Racc[hidx(t, u, v)] += val;
+        }
+      }
+    }
+    Racc[0] += g[0];
+  }
+}
+
 // Static FP64 operation count of hermite_R<L> (one multiply or add = 1).
 __host__ __device__ constexpr int hermite_R_flops(int L) {
   int f = 0;

@@ -41,6 +41,12 @@ constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators
 constexpr int kSRWinCap = 256;    // screening windows held in LDS
 constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
 
+// cells per wave for which the Cartesian accumulators of a class fit in LDS
+__host__ __device__ constexpr int sr_max_cells(int nblk) {
+  return (kBlkCap / nblk) < 1 ? 1 : ((kBlkCap / nblk) > kMaxCellsPerWave ? kMaxCellsPerWave : kBlkCap / nblk);
+}
+int sr_cells_per_wave(int nblk) { return sr_max_cells(nblk); }
+
 // (t,u,v) of Hermite index h (inverse of hidx)
 __device__ __forceinline__ void herm_decode(int h, int &t, int &u, int &v) {
   int s = 0;
@@ -122,8 +128,12 @@ __device__ __forceinline__ void unpack3(int v, int &a, int &b, int &c) {
   c = ((v >> 20) & 1023) - 512;
 }
 
+// waves per SIMD the class's register need allows (the image loop keeps two
+// Hermite arrays of nherm(L) doubles live)
+__host__ __device__ constexpr int sr_waves(int L) { return L >= 4 ? 1 : 2; }
+
 template <int LP, int LA, int LB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sr_waves(LP + LA + LB))))
 void sr3c_kernel(const SRParams prm, const int w0) {
   constexpr int NCP = ncart(LP), NCA = ncart(LA), NCB = ncart(LB);
   constexpr int NBLK = NCP * NCA * NCB;
@@ -131,7 +141,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   constexpr int NH = nherm(L);
   constexpr int NHAB = nherm(LAB);
   constexpr int EA = (LA + 1) * (LB + 1) * (LAB + 1);
-  constexpr int BLK = (NBLK * kMaxCellsPerWave <= kBlkCap) ? NBLK * kMaxCellsPerWave : 1;
+  constexpr int BLK = NBLK * sr_max_cells(NBLK);
   __shared__ float s_nf[kSRWinCap];
   __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
   __shared__ int s_cand[kCandCap];
@@ -196,7 +206,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   const int lig = lane % gs;
   const int gl = lane / gs;
   const unsigned long long gmask_lo = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
-  const bool blk_in_lds = BLK > 1 && NBLK * ncbw <= BLK;
+  const bool blk_in_lds = NBLK * ncbw <= BLK;
   double *const part = (wk.part >= 0) ? prm.part + wk.part : nullptr;
 
   const size_t xplane = (size_t)prm.naux_b * prm.nao * prm.nao;
@@ -373,10 +383,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
                   f *= m2rho;
                   g[n] *= f;
                 }
-                double R[NH];
-                hermite_R<L>(X, Y, Z, g, R);
-#pragma unroll
-                for (int i = 0; i < NH; ++i) Rb[i] += R[i];
+                hermite_R_acc<L>(X, Y, Z, g, Rb);
                 ++n_terms;
               }
               // group reduction (fixed xor butterfly: identical result on every lane)
