@@ -116,6 +116,8 @@ typedef struct rsgdf_stats {
   int64_t n_aux_batches; /* aux-shell batches used to bound scratch memory                  */
   int64_t bytes_out;     /* output bytes written                                            */
   double sr_flops;       /* algorithmic FP64 operations of the SR kernels (static counts)   */
+  double t_lr_gemm_ms;   /* G-space contraction kernels alone                               */
+  double lr_gemm_flops;  /* 8 naux N_q n_AO^2 per k-pair (real operations of complex MACs)  */
 } rsgdf_stats;
 
 typedef struct {

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -580,7 +581,8 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
   if (opt) o = *opt;
   if (o.parts == 0) o.parts = RSGDF_PART_ALL;
   const double g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
-  if (o.lr_precision != RSGDF_FP64) return fail(RSGDF_EUNSUPPORTED, "reduced-precision LR not in this entry point");
+  if (o.lr_precision != RSGDF_FP64 && o.lr_precision != RSGDF_FP32 && o.lr_precision != RSGDF_BF16X3)
+    return fail(RSGDF_EINVAL, "unknown lr_precision");
   if (o.screening != RSGDF_SCREEN_RIGOROUS) return fail(RSGDF_EUNSUPPORTED, "learned screening not in this entry point");
 
   hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
@@ -997,8 +999,10 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
   }
 
   // ---------------------------------------------------------- LR
-  float t_lr = 0.f;
-  int64_t n_lr = 0, n_g = 0;
+  float t_lr = 0.f, t_lr_gemm = 0.f;
+  long long n_lr = 0;
+  int64_t n_g = 0;
+  double lr_flops = 0.0;
   if (do_lr) {
     HIPCHK(hipEventRecord(ev[4], st));
     // G sets per folded k12 class: q = G + k_c, q != 0, exp(-q^2/4w^2) >= g_thr
@@ -1010,6 +1014,7 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       const double qm = std::sqrt(std::max(q2max, 0.0)) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
       int w[3];
       for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(qm * hp.lt.an[d] / (2.0 * kPi)) + 1;
+      std::vector<std::array<double, 4>> qc;  // (|q|^2, q)
       for (int i = -w[0]; i <= w[0]; ++i)
         for (int j = -w[1]; j <= w[1]; ++j)
           for (int k = -w[2]; k <= w[2]; ++k) {
@@ -1020,8 +1025,14 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
             }
             if (q2 < 1e-20) continue;
             if (std::exp(-q2 / (4.0 * omega * omega)) < g_thr) continue;
-            qv.insert(qv.end(), q, q + 3);
+            qc.push_back({q2, q[0], q[1], q[2]});
           }
+      // by |q|, so that neighbouring lanes of the pair-transform kernel
+      // drop the same primitive pairs (the e^{-q^2/4p} factor)
+      std::stable_sort(qc.begin(), qc.end(), [](const std::array<double, 4> &x, const std::array<double, 4> &y) {
+        return x[0] < y[0];
+      });
+      for (const auto &e : qc) qv.insert(qv.end(), e.begin() + 1, e.end());
       qoff.push_back((int64_t)qv.size() / 3);
     }
     const int64_t nq_tot = qoff.back();
@@ -1042,34 +1053,49 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
                    (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
     HIPCHK(launch_auxft(ap, st));
-    // B buffer: one class, one q chunk
+    // Per q chunk: pair transforms binned by BvK class (I, no Bloch phase),
+    // the k2 phases of the class's k-pairs (B), then the G-space contraction.
     int max_kpi = 0;
     for (auto &v : cls_kp) max_kpi = std::max<int>(max_kpi, (int)v.size());
     const double bbudget = std::min(0.25 * (double)free_b, 16e9);
-    int64_t qchunk = (int64_t)(bbudget / ((double)std::max(1, max_kpi) * nao2 * 16.0));
-    qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 4096));
+    int64_t qchunk = (int64_t)(bbudget / ((double)(nk + std::max(1, max_kpi)) * nao2 * 16.0));
+    qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 8192));
     int64_t max_nq = 0;
     for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, qoff[c + 1] - qoff[c]);
     qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
-    DBuf d_B, d_kp, d_k2, d_nterm;
+    DBuf d_I, d_B, d_kp, d_ph, d_nterm, d_amax;
+    HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
+    HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
-    HIPCHK(d_kp.alloc((size_t)std::max(1, max_kpi) * sizeof(int32_t)));
-    HIPCHK(d_k2.alloc((size_t)std::max(1, max_kpi) * 3 * sizeof(double)));
-    const int64_t max_threads = (((int64_t)npair * 2 * qchunk * max_kpi + 63) / 64) * 64;
-    HIPCHK(d_nterm.alloc((size_t)std::max<int64_t>(max_threads, 64) * sizeof(long long)));
-    std::vector<long long> hterm;
+    HIPCHK(d_kp.alloc((size_t)nkp * sizeof(int32_t)));
+    HIPCHK(d_ph.alloc((size_t)nkp * nk * 2 * sizeof(double)));
+    HIPCHK(d_nterm.alloc(sizeof(long long)));
+    HIPCHK(hipMemsetAsync(d_nterm.p, 0, sizeof(long long), st));
+    // k-pair lists and e^{+i k2.L_c} rows of every class, uploaded once
+    std::vector<int32_t> kpl;
+    std::vector<double> phl;
+    std::vector<int64_t> kpl_off{0};
+    for (int c = 0; c < nk; ++c) {
+      for (int t : cls_kp[c]) {
+        kpl.push_back(t);
+        const int k2 = hp.kp2[t];
+        phl.insert(phl.end(), kph.begin() + 2 * (size_t)k2 * nk, kph.begin() + 2 * (size_t)(k2 + 1) * nk);
+      }
+      kpl_off.push_back((int64_t)kpl.size());
+    }
+    if (!kpl.empty()) {
+      HIPCHK(hipMemcpyAsync(d_kp.p, kpl.data(), kpl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(d_ph.p, phl.data(), phl.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    std::vector<hipEvent_t> gev;
+    const int lr_nq_hi = 32;
     for (int c = 0; c < nk; ++c) {
       const int nkpi = (int)cls_kp[c].size();
       const int64_t nqc = qoff[c + 1] - qoff[c];
       if (nkpi == 0 || nqc == 0) continue;
-      std::vector<int32_t> kpl(cls_kp[c].begin(), cls_kp[c].end());
-      std::vector<double> k2l;
-      for (int t : cls_kp[c])
-        for (int d = 0; d < 3; ++d) k2l.push_back(hp.kvec[3 * hp.kp2[t] + d]);
-      HIPCHK(hipMemcpyAsync(d_kp.p, kpl.data(), kpl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(d_k2.p, k2l.data(), k2l.size() * sizeof(double), hipMemcpyHostToDevice, st));
       for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
         const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
+        HIPCHK(launch_amax(d_A.as<double>() + 2 * (qoff[c] + q0), nq_tot, (int)naux, nq, d_amax.as<double>(), st));
         PairFTParams pp{};
         pp.ao = d_ao.as<Shell>();
         pp.ao_exp = d_aoe.as<double>();
@@ -1078,34 +1104,51 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
         pp.cls_off = d_coff.as<int32_t>();
         pp.img = d_img.as<double>();
         pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);
-        pp.k2 = d_k2.as<double>();
+        pp.amax = d_amax.as<double>();
         pp.npair = npair;
         pp.nq = nq;
-        pp.nkpi = nkpi;
         pp.nao = (int32_t)nao;
         pp.nk = nk;
-        pp.cutoff = 1e-4 * thresh * 1e-4;
-        pp.B = d_B.as<double>();
+        for (int d = 0; d < 3; ++d) pp.kn[d] = L.n[d];
+        pp.kcls[0] = c / (L.n[1] * L.n[2]);
+        pp.kcls[1] = (c / L.n[2]) % L.n[1];
+        pp.kcls[2] = c % L.n[2];
+        pp.eps = 1e-8 * thresh;
+        pp.B = d_I.as<double>();
         pp.nterm = d_nterm.as<long long>();
-        const int64_t nth = (((int64_t)npair * 2 * nq * nkpi + 63) / 64) * 64;
-        HIPCHK(launch_pairft(pp, nth, st));
+        HIPCHK(launch_pairft_binned(pp, st));
+        HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.as<double>(), nk, nkpi, nq,
+                             nao2, st));
         LRGemmParams gp{};
         gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
         gp.lda = nq_tot;
         gp.B = d_B.as<double>();
         gp.out = d_out;
-        gp.kp_of = d_kp.as<int32_t>();
+        gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
         gp.plane = naux * nao2;
         gp.naux = (int32_t)naux;
         gp.nq = nq;
         gp.nmn = (int32_t)nao2;
-        HIPCHK(launch_lr_gemm_f64(gp, nkpi, st));
-        hterm.resize(nth);
-        HIPCHK(hipMemcpyAsync(hterm.data(), d_nterm.p, nth * sizeof(long long), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (long long v : hterm) n_lr += v;
+        gp.nq_hi = (q0 == 0) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        gev.push_back(e0);
+        gev.push_back(e1);
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(launch_lr_gemm_mfma(o.lr_precision, gp, nkpi, st));
+        HIPCHK(hipEventRecord(e1, st));
+        lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
       }
     }
+    HIPCHK(hipMemcpyAsync(&n_lr, d_nterm.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < gev.size(); i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, gev[i], gev[i + 1]));
+      t_lr_gemm += ms;
+    }
+    for (hipEvent_t e : gev) (void)hipEventDestroy(e);
     HIPCHK(hipEventRecord(ev[5], st));
     HIPCHK(hipEventSynchronize(ev[5]));
     HIPCHK(hipEventElapsedTime(&t_lr, ev[4], ev[5]));
@@ -1128,6 +1171,8 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     s.t_fold_ms = t_fold;
     s.t_lr_ms = t_lr;
     s.n_lr_terms = n_lr;
+    s.t_lr_gemm_ms = t_lr_gemm;
+    s.lr_gemm_flops = lr_flops;
     s.n_g_total = n_g;
     s.n_triplets = ntrip;
     s.n_aux_batches = nbatch;

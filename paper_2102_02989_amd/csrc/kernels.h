@@ -57,23 +57,25 @@ struct PairFTParams {
   const Pair *pairs;
   const int32_t *cls_off;
   const double *img;
-  const double *q;        // [nq][3] chunk
-  const double *k2;       // [nkpi][3] k2 vector of each k-pair of the class
-  int32_t npair, nq, nkpi, nao, nk;
-  int32_t pad;
-  double cutoff;          // skip primitive-pair images with |c_a c_b| K (pi/p)^{3/2} below this
-  double *B;              // complex [nkpi][nq][nao][nao]
-  long long *nterm;       // [gridDim.x * blockDim.x] transform evaluations
+  const double *q;        // [nq][3] chunk, all q = G + k_cls of one class
+  const double *amax;     // [nq] max_P |A[P][q]|
+  int32_t npair, nq, nao, nk;
+  int32_t kn[3];          // k-mesh (BvK class arithmetic)
+  int32_t kcls[3];        // mesh coordinates j_d of k_cls
+  double eps;             // skip terms whose weighted bound is below this
+  double *B;              // complex I[Nk BvK classes][nao][nao][nq]
+  long long *nterm;       // running count of transform evaluations
 };
 
 struct LRGemmParams {
   const double *A;        // complex, row P has stride lda (complex elements); columns q0.. of the class
   int64_t lda;
-  const double *B;        // complex [nkpi][nq][nmn]
+  const double *B;        // complex [nkpi][nmn][nq]
   double *out;            // complex [nkp][naux][nmn]
   const int32_t *kp_of;   // [nkpi] global k-pair index
   int64_t plane;          // naux * nmn
-  int32_t naux, nq, nmn, pad;
+  int32_t naux, nq, nmn;
+  int32_t nq_hi;          // leading q columns taken in FP64 by the reduced-precision forms
 };
 
 int pair_class(int la, int lb);
@@ -85,7 +87,10 @@ hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int 
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream);
 hipError_t launch_overlaps(const OvlParams &op, const SmnParams &sp, hipStream_t stream);
 hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream);
-hipError_t launch_pairft(const PairFTParams &pp, int64_t nthreads_padded, hipStream_t stream);
-hipError_t launch_lr_gemm_f64(const LRGemmParams &gp, int nkpi, hipStream_t stream);
+hipError_t launch_lr_gemm_mfma(int mode, const LRGemmParams &gp, int nkpi, hipStream_t stream);
+hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream);
+hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *amax, hipStream_t stream);
+hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,
+                         hipStream_t stream);
 
 }  // namespace rsgdf

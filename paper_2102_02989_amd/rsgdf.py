@@ -49,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("t_lr_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("n_sr_terms", ctypes.c_int64),
                 ("n_sr_shell_terms", ctypes.c_int64), ("n_sr_candidates", ctypes.c_int64),
                 ("n_lr_terms", ctypes.c_int64), ("n_g_total", ctypes.c_int64), ("n_triplets", ctypes.c_int64),
-                ("n_aux_batches", ctypes.c_int64), ("bytes_out", ctypes.c_int64), ("sr_flops", ctypes.c_double)]
+                ("n_aux_batches", ctypes.c_int64), ("bytes_out", ctypes.c_int64), ("sr_flops", ctypes.c_double),
+                ("t_lr_gemm_ms", ctypes.c_double), ("lr_gemm_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
