@@ -7,9 +7,15 @@ threshold 1e-10, complex128 output (4.64 GB).  One step = one full
 rsgdf_build_j3c call (host planning + short-range lattice sums + Bloch fold
 + G=0 term + long-range reciprocal sum) into a preallocated device buffer.
 
-Prints one JSON line.  value = short-range primitive integrals per second
-(evaluated (aux primitive, AO primitive, AO primitive, image pair) tuples
-divided by the build wall time).
+Two forms are timed on the same input: plain (every stage FP64) and chosen
+(the G-space contraction with FP32 operands on the matrix cores, FP32
+accumulation promoted to FP64 every 16 q; Boys, erfc and the Bloch sums stay
+FP64).  The chosen form's maximum absolute deviation from the plain output is
+measured on the whole tensor.
+
+Prints one JSON line.  value = primitive integrals per second: the evaluated
+(aux primitive, AO primitive, AO primitive, image pair) tuples of the build
+divided by the chosen form's build wall time.
 """
 from __future__ import annotations
 
@@ -23,6 +29,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR = 78.6e12  # 256 CU x 4 SIMD x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
+CHOSEN_LR, CHOSEN_LR_NAME = 1, "fp32"  # G-space contraction operands of the chosen form
+SR_SOURCES = ("paper_2102_02989_amd/csrc/sr3c.hip", "paper_2102_02989_amd/csrc/device_math.h",
+              "paper_2102_02989_amd/csrc/plan.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sr3c_c2_traffic.json")
+
+
+def sr_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes of one SR phase from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary, or None when the SR kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sr_source_hash") != sr_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(problem, gpu_rate_unit="prim-integrals/s"):
@@ -49,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=["c1", "c2"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--form", default="both", choices=["both", "plain", "chosen"],
+                    help="time the plain FP64 build, the chosen form, or both (value = chosen)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (a known-size "
                          "reference for HBM traffic counters)")
@@ -65,28 +99,49 @@ def main():
 
     problem = synth.config2() if args.config == "c2" else synth.config1()
     shape = (P.nkpairs(problem.kmesh), problem.aux.nfunc, problem.basis.nfunc, problem.basis.nfunc)
-    out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    out_plain = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    out_chosen = torch.empty(shape, dtype=torch.complex128, device="cuda") if args.form == "both" else out_plain
+    forms = {"plain": dict(lr_precision=P.FP64), "chosen": dict(lr_precision=CHOSEN_LR)}
 
-    def step():
+    def step(form, out):
         _, st = P.build_j3c(problem.cell, problem.basis, problem.aux, problem.kmesh, problem.omega,
-                            problem.thresh, out, g_thresh=problem.g_thr)
+                            problem.thresh, out, g_thresh=problem.g_thr, **forms[form])
         return st
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(step())
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = dt / args.steps * 1e3
-    n_terms = stats[-1]["n_sr_terms"]
+    def timed(form, out):
+        for _ in range(args.warmup):
+            step(form, out)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stats.append(step(form, out))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3, stats
+
+    run = ["plain", "chosen"] if args.form == "both" else [args.form]
+    res = {}
+    for form in run:
+        res[form] = timed(form, out_plain if form == "plain" else out_chosen)
+    head = "chosen" if "chosen" in res else "plain"
+    ms, stats = res[head]
+    n_terms = res["plain"][1][-1]["n_sr_terms"] if "plain" in res else stats[-1]["n_sr_terms"]
     value = n_terms / (ms * 1e-3)
     t_sr = sum(s["t_sr_ms"] for s in stats) / len(stats)
     flops = stats[-1]["sr_flops"]
     achieved = flops / (t_sr * 1e-3)
+    cfg = {"workload": f"{problem.name}: {problem.cell.natm}-atom cubic cell a=6.74, n_AO="
+                       f"{problem.basis.nfunc}, n_aux={problem.aux.nfunc}, kmesh "
+                       f"{'x'.join(map(str, problem.kmesh))} ({shape[0]} k-pairs), omega={problem.omega}, "
+                       f"thresh={problem.thresh}",
+           "form": head,
+           "chosen": {"lr_precision": CHOSEN_LR_NAME, "screening": "rigorous"} if head == "chosen" else None}
+    for form, (fms, _) in res.items():
+        cfg[f"{form}_build_s"] = fms * 1e-3
+    if len(res) == 2:
+        cfg["speedup_chosen_vs_plain"] = res["plain"][0] / res["chosen"][0]
+        cfg["chosen_max_abs_err_vs_plain"] = float((out_chosen - out_plain).abs().max())
+    traffic = recorded_traffic()
     line = {
         "metric": "j3c build s per k-mesh + primitive integrals/s, chosen vs plain, err<=1e-6",
         "value": value,
@@ -100,17 +155,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded Gaussian bases and cells)",
-        "config": {"workload": f"{problem.name}: {problem.cell.natm}-atom cubic cell a=6.74, n_AO="
-                               f"{problem.basis.nfunc}, n_aux={problem.aux.nfunc}, kmesh "
-                               f"{'x'.join(map(str, problem.kmesh))} ({shape[0]} k-pairs), omega={problem.omega}, "
-                               f"thresh={problem.thresh}, plain FP64",
-                   "build_s": ms * 1e-3, "form": "plain", "chosen": None},
-        "phases_ms": {k: stats[-1][k] for k in ("t_plan_ms", "t_sr_ms", "t_fold_ms", "t_lr_ms", "t_total_ms")},
+        "config": cfg,
+        "phases_ms": {k: stats[-1][k] for k in ("t_plan_ms", "t_sr_ms", "t_fold_ms", "t_lr_ms", "t_lr_gemm_ms",
+                                                 "t_total_ms")},
         "counts": {k: stats[-1][k] for k in ("n_sr_terms", "n_sr_shell_terms", "n_lr_terms", "n_g_total",
                                              "n_triplets")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
-                     "kernel": "sr3c_kernel (all 24 angular-momentum classes of one build)",
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
+                     "kernel": "sr3c_kernel (the 24 angular-momentum classes of one build, on 4 streams)",
                      "flops_per_launch": flops, "avg_launch_ms": t_sr},
         "cpu_baseline": None,
     }

@@ -60,10 +60,14 @@ extern "C" {
 #define RSGDF_MAX_L_AO 2
 #define RSGDF_MAX_L_AUX 3
 
-/* long-range G-space contraction precision */
-#define RSGDF_FP64 0   /* plain: FP64 everywhere                                    */
-#define RSGDF_FP32 1   /* LR GEMM operands and accumulation in FP32                  */
-#define RSGDF_BF16X3 2 /* LR GEMM as three BF16 MFMA products, FP32 accumulation     */
+/* long-range G-space contraction precision (Eq. M10's q sum as a complex
+ * matrix product per k12 class).  In every form the transforms, the kernel
+ * weight, the Bloch phases and the output are FP64; the reduced forms take
+ * the 32 smallest-|q| vectors of each class in FP64 and add each 16-q FP32
+ * partial into FP64 registers. */
+#define RSGDF_FP64 0   /* plain: FP64 matrix-core products                          */
+#define RSGDF_FP32 1   /* operands rounded to FP32, FP32 matrix-core products        */
+#define RSGDF_BF16X3 2 /* operands split hi + lo in BF16, three BF16 products        */
 
 /* short-range image screening */
 #define RSGDF_SCREEN_RIGOROUS 0 /* Supplementary-Material bounds (Eqs. S14, S23-S27) */
@@ -141,7 +145,9 @@ int64_t rsgdf_j3c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *basis, const
 int rsgdf_build_j3c(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                     const int32_t kmesh[3], double omega, double thresh, rsgdf_out *out);
 
-/* As rsgdf_build_j3c with explicit options (NULL = defaults). */
+/* As rsgdf_build_j3c with explicit options (NULL = defaults).  Returns
+ * RSGDF_EINVAL for an unknown lr_precision and RSGDF_EUNSUPPORTED for
+ * screening = RSGDF_SCREEN_LEARNED without usable mlp_weights. */
 int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                        const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
                        rsgdf_out *out);

@@ -1180,9 +1180,10 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     if (do_sr && ntrip > 0) {
       std::vector<long long> cnt((size_t)nwork * 4);
       HIPCHK(hipMemcpy(cnt.data(), d_cnt.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
-      std::vector<long long> tterms(ntrip, 0), tshell(ntrip, 0);
+      std::vector<long long> tterms(ntrip, 0), tshell(ntrip, 0), tcontr(ntrip, 0);
       for (int64_t w = 0; w < nwork; ++w) {
         tterms[work[w].trip] += cnt[(size_t)w * 4];
+        tcontr[work[w].trip] += cnt[(size_t)w * 4 + 1];
         tshell[work[w].trip] += cnt[(size_t)w * 4 + 2];
       }
       double flops = 0.0;
@@ -1201,15 +1202,16 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
           flops += (double)nt * sr_term_flops(Lt);
         }
       s.sr_flops = flops;
-      // optional per-work-item dump (aux shell, pair, l_P, l_a, l_b, terms) for workload analysis
+      // optional per-item dump (aux shell, pair, l_P, l_a, l_b, terms, contractions, shell terms,
+      // R_c cut) for workload analysis
       if (const char *fn = std::getenv("RSGDF_COUNTS_FILE")) {
         if (FILE *f = std::fopen(fn, "w")) {
           for (int64_t t = 0; t < ntrip; ++t) {
             long long nt = 0;
             nt = tterms[t];
             const Pair &pr = hp.pairs[trips[t].pair];
-            std::fprintf(f, "%d %d %d %d %d %lld %.3f\n", trips[t].aux, trips[t].pair, hp.ax[trips[t].aux].l,
-                         hp.ao[pr.sa].l, hp.ao[pr.sb].l, nt, trips[t].rc_cut);
+            std::fprintf(f, "%d %d %d %d %d %lld %lld %lld %.3f\n", trips[t].aux, trips[t].pair, hp.ax[trips[t].aux].l,
+                         hp.ao[pr.sa].l, hp.ao[pr.sb].l, nt, tcontr[t], tshell[t], trips[t].rc_cut);
           }
           std::fclose(f);
         }
