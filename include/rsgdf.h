@@ -101,7 +101,7 @@ typedef struct {
   int32_t screening;     /* RSGDF_SCREEN_RIGOROUS | RSGDF_SCREEN_LEARNED                    */
   int32_t parts;         /* RSGDF_PART_* mask; 0 -> RSGDF_PART_ALL                          */
   int32_t sr_slices;     /* lanes cooperating on one (k-cell pair) unit; 0 -> automatic     */
-  const char *mlp_weights; /* learned screening weights (path) or NULL                      */
+  const float *mlp_weights; /* host, RSGDF_MLP_NPARAM floats (layout below), or NULL        */
   double mlp_margin;     /* log10 margin added to the learned prediction                    */
 } rsgdf_options;
 
@@ -121,6 +121,8 @@ typedef struct rsgdf_stats {
   int64_t bytes_out;     /* output bytes written                                            */
   double sr_flops;       /* algorithmic FP64 operations of the SR kernels (static counts)   */
   double t_lr_gemm_ms;   /* G-space contraction kernels alone                               */
+  int64_t n_screen_candidates; /* (aux shell, AO pair, pair image) candidates (learned mode) */
+  int64_t n_screen_skipped;    /* candidates the network dropped                            */
   double lr_gemm_flops;  /* 8 naux N_q n_AO^2 per k-pair (real operations of complex MACs)  */
 } rsgdf_stats;
 
@@ -151,6 +153,56 @@ int rsgdf_build_j3c(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgd
 int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                        const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
                        rsgdf_out *out);
+
+/* ---- learned screening (a project addition to the Supplementary-Material
+ * bounds).  A candidate is one (aux shell, AO shell pair, pair image n') unit
+ * of the short-range lattice sum that passed the rigorous test of Eqs.
+ * S23-S27.  Its target is log10 of the sum over BvK cells c1 of max |block|
+ * it adds to the short-range intermediate (an upper bound of its effect on
+ * any output element), floored at log10(thresh) - 4.  Features (16 floats, raw): log10 beta_d, log10 p_d,
+ * log10 alpha_P (most diffuse primitives), R12 = |A - B - n'|, R_c,min (pair
+ * centre to the nearest aux image), l_a, l_b, l_P, log10 A (1s-model
+ * amplitude, Eq. S4), log10 omega, log10 of the 1s estimate at R_c,min
+ * (Eqs. S4-S9), then five zeros.
+ *
+ * Network parameters: RSGDF_MLP_NPARAM floats, in order: feature mean [16],
+ * 1/std [16], W1 [64][16], b1 [64], W2 [64][64], b2 [64], W3 [64], b3 [1],
+ * training-range lower bounds [16], upper bounds [16].  ReLU hidden layers. */
+#define RSGDF_MLP_NFEAT 16
+#define RSGDF_MLP_NPARAM 5377
+
+/* Run the plain short-range sum with magnitude logging (no output is
+ * written) and return a seeded sample (fraction sample_frac in (0, 1]) of
+ * the candidates with their features and targets, host arrays feat
+ * [n][16] and target [n].  *n_out is always set; RSGDF_ESIZE (nothing
+ * copied) if it exceeds capacity.  stream: hipStream_t or NULL. */
+int rsgdf_screen_log(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                     const int32_t kmesh[3], double omega, double thresh, double sample_frac, uint64_t seed,
+                     float *feat, float *target, int64_t capacity, int64_t *n_out, void *stream);
+
+/* Train the network on the GPU (FP32 forward/backward kernels, Adam with
+ * step size lr, mini-batches of `batch`, seeded shuffles).  Loss: mean of
+ * w (pred - y)^2 with w = kappa (>= 1) for under-predictions, 1 otherwise.
+ * init != 0 first sets the standardisation and training range from X and
+ * draws He-initialised weights from seed.  params is read and written (host,
+ * RSGDF_MLP_NPARAM floats); loss_history (host, epochs floats) or NULL
+ * receives the full-data loss after each epoch. */
+int rsgdf_mlp_train(float *params, const float *X, const float *y, int64_t n, int32_t epochs, int32_t batch,
+                    float lr, float kappa, uint64_t seed, int32_t init, float *loss_history, void *stream);
+
+/* Loss and its gradient with respect to W1 .. b3 (5313 floats, parameter
+ * order) over all n samples, from the training kernels. */
+int rsgdf_mlp_grad(const float *params, const float *X, const float *y, int64_t n, float kappa, float *grad,
+                   float *loss, void *stream);
+
+/* Predictions for n raw feature rows: mode 0 FP32 vector ALUs, mode 1 the
+ * FP16 matrix-core path used by the keep mask. */
+int rsgdf_mlp_predict(const float *params, const float *X, int64_t n, int32_t mode, float *pred, void *stream);
+
+/* Margin = the `quantile` quantile (1 = max) of y - prediction (mode 1) over
+ * the given samples, floored at 0. */
+int rsgdf_mlp_margin(const float *params, const float *X, const float *y, int64_t n, double quantile,
+                     double *margin, void *stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char *rsgdf_last_error(void);

@@ -12,11 +12,20 @@ from .rsgdf import (  # noqa: F401
     FP64,
     FP32,
     BF16X3,
+    MLP_NFEAT,
+    MLP_NPARAM,
+    SCREEN_LEARNED,
+    SCREEN_RIGOROUS,
     RsgdfError,
     build_j3c,
     j3c_nbytes,
     library,
     library_path,
+    mlp_grad,
+    mlp_margin,
+    mlp_predict,
+    mlp_train,
     nkpairs,
+    screen_log,
     version,
 )

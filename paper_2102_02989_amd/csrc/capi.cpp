@@ -19,12 +19,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <random>
 #include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/rsgdf.h"
 #include "kernels.h"
+#include "learned.h"
 #include "plan.h"
 
 using namespace rsgdf;
@@ -559,11 +561,33 @@ int rsgdf_build_j3c(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgd
   return rsgdf_build_j3c_ex(cell, basis, auxbasis, kmesh, omega, thresh, nullptr, out);
 }
 
-int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
-                       const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
-                       rsgdf_out *out) {
+}  // extern "C"
+
+namespace {
+
+// Learned-screening hooks of one build: magnitude logging (SR only, no fold
+// or LR, no output written) or the keep mask of a trained network.
+struct LearnCtl {
+  bool log = false;
+  double sample_frac = 1.0;
+  uint64_t seed = 0;
+  std::vector<float> feat, tgt;   // logging results (host)
+  long long ncand = 0, nskip = 0;
+};
+
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+               const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt, rsgdf_out *out,
+               LearnCtl *ctl) {
   const auto t_start = std::chrono::steady_clock::now();
   g_err.clear();
+  const bool logging = ctl && ctl->log;
   if (!out) return fail(RSGDF_EINVAL, "null output");
   const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
   if (need < 0) return (int)need;
@@ -571,8 +595,10 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
   if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
   for (int i = 0; i < 3 * cell->natm; ++i)
     if (!std::isfinite(cell->coords[i])) return fail(RSGDF_EINVAL, "non-finite coordinates");
-  if (!out->data) return fail(RSGDF_EINVAL, "null output buffer");
-  if (out->capacity_bytes < need) return fail(RSGDF_ESIZE, "output capacity too small");
+  if (!logging) {
+    if (!out->data) return fail(RSGDF_EINVAL, "null output buffer");
+    if (out->capacity_bytes < need) return fail(RSGDF_ESIZE, "output capacity too small");
+  }
   rsgdf_options o{};
   o.g_thresh = -1.0;
   o.lr_precision = RSGDF_FP64;
@@ -583,7 +609,11 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
   const double g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
   if (o.lr_precision != RSGDF_FP64 && o.lr_precision != RSGDF_FP32 && o.lr_precision != RSGDF_BF16X3)
     return fail(RSGDF_EINVAL, "unknown lr_precision");
-  if (o.screening != RSGDF_SCREEN_RIGOROUS) return fail(RSGDF_EUNSUPPORTED, "learned screening not in this entry point");
+  if (o.screening != RSGDF_SCREEN_RIGOROUS && o.screening != RSGDF_SCREEN_LEARNED)
+    return fail(RSGDF_EINVAL, "unknown screening mode");
+  const bool learned = o.screening == RSGDF_SCREEN_LEARNED && !logging;
+  if (learned && !o.mlp_weights) return fail(RSGDF_EUNSUPPORTED, "learned screening needs mlp_weights");
+  if (logging) o.parts = RSGDF_PART_SR;
 
   hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
   HostPlan hp;
@@ -615,7 +645,9 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
   // output buffer (device)
   DBuf d_outbuf;
   double *d_out = nullptr;
-  if (out->on_device) {
+  if (logging) {
+    d_out = nullptr;  // magnitude logging writes no output
+  } else if (out->on_device) {
     d_out = reinterpret_cast<double *>(out->data);
   } else {
     HIPCHK(d_outbuf.alloc((size_t)need));
@@ -774,6 +806,17 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       if ((rcmax + r12max + 2.0 * diam) * hp.lt.bn[d] / (2.0 * kPi) + L.n[d] + 2 > 500.0)
         return fail(RSGDF_EUNSUPPORTED, "screening radius too large for the packed image coordinates");
   }
+  // ---- learned-screening candidates: (triplet t, pair image ii) has index
+  // cand_off[t] + ii, ii over all images of the pair
+  std::vector<int64_t> cand_off;
+  int64_t ncand = 0;
+  if (learned || logging) {
+    cand_off.resize(ntrip);
+    for (int64_t t = 0; t < ntrip; ++t) {
+      cand_off[t] = ncand;
+      ncand += hp.cls_off[(size_t)trips[t].pair * (nk + 1) + nk];
+    }
+  }
   // ---- SR work list: a cost estimate per item (primitive triplets x pair
   // images x lattice vectors in the R_c ball x per-term operations) decides how
   // many waves share it, first by BvK cell ranges (disjoint outputs), then by
@@ -909,6 +952,55 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     }
   } evg2{evf, evj};
 
+  SRParams base{};
+  base.ao = d_ao.as<Shell>();
+  base.ax = d_ax.as<Shell>();
+  base.ao_exp = d_aoe.as<double>();
+  base.ao_coef = d_aoc.as<double>();
+  base.ax_exp = d_axe.as<double>();
+  base.ax_coef = d_axc.as<double>();
+  base.ao_c1s = d_aoc1.as<double>();
+  base.ax_c1s = d_axc1.as<double>();
+  base.pairs = d_pairs.as<Pair>();
+  base.cls_off = d_coff.as<int32_t>();
+  base.nsr = d_nsr.as<int32_t>();
+  base.img = d_img.as<double>();
+  base.trip = d_trip.as<Triplet>();
+  base.work = d_work.as<SRWork>();
+  base.part = d_part.as<double>();
+  base.lat = L;
+  base.omega = omega;
+  base.eps = thresh;
+  base.dR = hp.scr.dR;
+  base.ncell_nf = hp.scr.ncell_nf;
+  base.ncell_r0 = hp.scr.r0;
+  base.boys = d_boys.as<double>();
+  base.nao = (int32_t)nao;
+  base.counts = d_cnt.as<long long>();
+  DBuf d_coffc, d_mask, d_mlp, d_nskip, d_logmag;
+  if (do_sr && (learned || logging)) {
+    HIPCHK(upload(d_coffc, cand_off, st));
+    base.cand_off = d_coffc.as<int64_t>();
+  }
+  if (do_sr && learned) {
+    // keep mask from the network: drop iff inside the training range and
+    // prediction + margin < log10(thresh)
+    HIPCHK(d_mask.alloc((size_t)std::max<int64_t>(ncand, 1)));
+    HIPCHK(d_mlp.alloc(kMlpNParam * sizeof(float)));
+    HIPCHK(hipMemcpyAsync(d_mlp.p, o.mlp_weights, kMlpNParam * sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHK(d_nskip.alloc(sizeof(long long)));
+    HIPCHK(hipMemsetAsync(d_nskip.p, 0, sizeof(long long), st));
+    const float cut = (float)(std::log10(thresh) - o.mlp_margin);
+    HIPCHK(launch_mlp_mask(base, (int)ntrip, ncand, d_mlp.as<float>(), cut, d_mask.as<uint8_t>(),
+                           d_nskip.as<long long>(), st));
+    base.mask = d_mask.as<uint8_t>();
+  }
+  if (do_sr && logging) {
+    HIPCHK(d_logmag.alloc((size_t)std::max<int64_t>(ncand, 1) * nk * sizeof(float)));
+    HIPCHK(hipMemsetAsync(d_logmag.p, 0xff, (size_t)std::max<int64_t>(ncand, 1) * nk * sizeof(float), st));  // NaN
+    base.logmag = d_logmag.as<float>();
+  }
+
   float t_sr = 0.f, t_fold = 0.f;
   for (int b = 0; b < nbatch; ++b) {
     int64_t f0 = hp.ax[batch_start[b]].foff, nf = 0;
@@ -917,34 +1009,10 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     if (do_sr) {
       HIPCHK(hipMemsetAsync(d_X.p, 0, (size_t)nf * nb * nao2 * sizeof(double), st));
       if (part_total > 0) HIPCHK(hipMemsetAsync(d_part.p, 0, (size_t)part_total * sizeof(double), st));
-      SRParams prm{};
-      prm.ao = d_ao.as<Shell>();
-      prm.ax = d_ax.as<Shell>();
-      prm.ao_exp = d_aoe.as<double>();
-      prm.ao_coef = d_aoc.as<double>();
-      prm.ax_exp = d_axe.as<double>();
-      prm.ax_coef = d_axc.as<double>();
-      prm.ao_c1s = d_aoc1.as<double>();
-      prm.ax_c1s = d_axc1.as<double>();
-      prm.pairs = d_pairs.as<Pair>();
-      prm.cls_off = d_coff.as<int32_t>();
-      prm.nsr = d_nsr.as<int32_t>();
-      prm.img = d_img.as<double>();
-      prm.trip = d_trip.as<Triplet>();
-      prm.work = d_work.as<SRWork>();
-      prm.part = d_part.as<double>();
-      prm.lat = L;
-      prm.omega = omega;
-      prm.eps = thresh;
-      prm.dR = hp.scr.dR;
-      prm.ncell_nf = hp.scr.ncell_nf;
-      prm.ncell_r0 = hp.scr.r0;
-      prm.boys = d_boys.as<double>();
+      SRParams prm = base;
       prm.X = d_X.as<double>();
       prm.aux_f0 = (int32_t)f0;
       prm.naux_b = (int32_t)nf;
-      prm.nao = (int32_t)nao;
-      prm.counts = d_cnt.as<long long>();
       // fork: classes in decreasing cost order, round-robin over the side streams
       HIPCHK(hipEventRecord(evf, st));
       for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, evf, 0));
@@ -974,6 +1042,13 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
       }
     }
     HIPCHK(hipEventRecord(ev[2], st));
+    if (logging) {
+      HIPCHK(hipEventSynchronize(ev[2]));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
+      t_sr += ms;
+      continue;
+    }
     FoldParams fp{};
     fp.phi = d_phi.as<double>();
     fp.X = do_sr ? d_X.as<double>() : nullptr;
@@ -1154,10 +1229,46 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     HIPCHK(hipEventElapsedTime(&t_lr, ev[4], ev[5]));
   }
 
-  if (!out->on_device) {
+  if (!logging && !out->on_device) {
     HIPCHK(hipMemcpyAsync(out->data, d_out, (size_t)need, hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
+
+  // ---------------------------------------------------------- learned screening
+  long long nskip = 0;
+  if (learned && do_sr) HIPCHK(hipMemcpy(&nskip, d_nskip.p, sizeof(long long), hipMemcpyDeviceToHost));
+  if (ctl) {
+    ctl->ncand = ncand;
+    ctl->nskip = nskip;
+  }
+  if (logging && do_sr && ncand > 0) {
+    // targets of the candidates the image loop reached, a seeded sample of
+    // them, and their features
+    DBuf d_tgt;
+    HIPCHK(d_tgt.alloc((size_t)ncand * sizeof(float)));
+    // below log10(thresh) - 4 every candidate is equally negligible
+    HIPCHK(launch_log_target(d_logmag.as<float>(), nk, ncand, (float)(std::log10(thresh) - 4.0), d_tgt.as<float>(),
+                             st));
+    std::vector<float> tgt(ncand);
+    HIPCHK(hipMemcpyAsync(tgt.data(), d_tgt.p, (size_t)ncand * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int64_t> sel;
+    const uint64_t lim = (ctl->sample_frac >= 1.0) ? ~0ull : (uint64_t)(ctl->sample_frac * 18446744073709551616.0);
+    for (int64_t c = 0; c < ncand; ++c)
+      if (std::isfinite(tgt[c]) && splitmix64(ctl->seed ^ (uint64_t)c) <= lim) sel.push_back(c);
+    ctl->tgt.resize(sel.size());
+    for (size_t i = 0; i < sel.size(); ++i) ctl->tgt[i] = tgt[sel[i]];
+    ctl->feat.resize(sel.size() * kMlpF);
+    if (!sel.empty()) {
+      DBuf d_sel, d_feat;
+      HIPCHK(upload(d_sel, sel, st));
+      HIPCHK(d_feat.alloc(sel.size() * kMlpF * sizeof(float)));
+      HIPCHK(launch_features(base, (int)ntrip, d_sel.as<int64_t>(), (int64_t)sel.size(), d_feat.as<float>(), st));
+      HIPCHK(hipMemcpyAsync(ctl->feat.data(), d_feat.p, sel.size() * kMlpF * sizeof(float), hipMemcpyDeviceToHost,
+                            st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
 
   // ---------------------------------------------------------- stats
   out->nkpair = nkp;
@@ -1174,6 +1285,8 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     s.t_lr_gemm_ms = t_lr_gemm;
     s.lr_gemm_flops = lr_flops;
     s.n_g_total = n_g;
+    s.n_screen_candidates = ncand;
+    s.n_screen_skipped = nskip;
     s.n_triplets = ntrip;
     s.n_aux_batches = nbatch;
     s.bytes_out = need;
@@ -1219,6 +1332,193 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
     }
     s.t_total_ms = ms_since(t_start);
   }
+  return RSGDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                       const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                       rsgdf_out *out) {
+  return build_impl(cell, basis, auxbasis, kmesh, omega, thresh, opt, out, nullptr);
+}
+
+int rsgdf_screen_log(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                     const int32_t kmesh[3], double omega, double thresh, double sample_frac, uint64_t seed,
+                     float *feat, float *target, int64_t capacity, int64_t *n_out, void *stream) {
+  g_err.clear();
+  if (!n_out) return fail(RSGDF_EINVAL, "null n_out");
+  if (!(sample_frac > 0.0) || sample_frac > 1.0) return fail(RSGDF_EINVAL, "sample_frac must be in (0, 1]");
+  if (capacity < 0 || (capacity > 0 && (!feat || !target))) return fail(RSGDF_EINVAL, "null feature/target buffer");
+  LearnCtl ctl;
+  ctl.log = true;
+  ctl.sample_frac = sample_frac;
+  ctl.seed = seed;
+  rsgdf_out out{};
+  out.stream = stream;
+  out.on_device = 1;
+  rsgdf_options o{};
+  o.g_thresh = -1.0;
+  o.parts = RSGDF_PART_SR;
+  const int rc = build_impl(cell, basis, auxbasis, kmesh, omega, thresh, &o, &out, &ctl);
+  if (rc) return rc;
+  const int64_t n = (int64_t)ctl.tgt.size();
+  *n_out = n;
+  if (n > capacity) return fail(RSGDF_ESIZE, "capacity below the number of logged candidates");
+  std::memcpy(feat, ctl.feat.data(), (size_t)n * kMlpF * sizeof(float));
+  std::memcpy(target, ctl.tgt.data(), (size_t)n * sizeof(float));
+  return RSGDF_OK;
+}
+
+// full-data loss (and gradient) of the network on device-resident samples
+static int mlp_eval(float *d_params, const float *d_X, const float *d_y, const int64_t *d_iota, int64_t n,
+                    float kappa, DBuf &gpart, DBuf &lpart, float *grad_host, float *loss_host, hipStream_t st) {
+  DBuf d_grad;
+  if (grad_host) HIPCHK(d_grad.alloc(kMlpNTrain * sizeof(float)));
+  HIPCHK(launch_mlp_step(d_params, d_X, d_y, d_iota, n, kappa, gpart.as<float>(), lpart.as<float>(),
+                         grad_host ? d_grad.as<float>() : nullptr, nullptr, nullptr, 0.f, 0, st));
+  const int nblk = (int)((n + 63) / 64);
+  std::vector<float> lp(nblk);
+  HIPCHK(hipMemcpyAsync(lp.data(), lpart.p, nblk * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (grad_host) HIPCHK(hipMemcpyAsync(grad_host, d_grad.p, kMlpNTrain * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double l = 0.0;
+  for (float v : lp) l += v;
+  if (loss_host) *loss_host = (float)l;
+  return RSGDF_OK;
+}
+
+int rsgdf_mlp_train(float *params, const float *X, const float *y, int64_t n, int32_t epochs, int32_t batch,
+                    float lr, float kappa, uint64_t seed, int32_t init, float *loss_history, void *stream) {
+  g_err.clear();
+  if (!params || !X || !y || n < 1 || epochs < 0 || batch < 1 || !(lr > 0.f) || !(kappa >= 1.f))
+    return fail(RSGDF_EINVAL, "invalid training arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (init) {
+    // standardisation and training range from the data, He-initialised weights
+    for (int k = 0; k < kMlpF; ++k) {
+      double s = 0.0, s2 = 0.0, lo = 1e300, hi = -1e300;
+      for (int64_t i = 0; i < n; ++i) {
+        const double v = X[i * kMlpF + k];
+        s += v;
+        s2 += v * v;
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+      }
+      const double mean = s / n, var = std::max(s2 / n - mean * mean, 0.0);
+      params[kMlpOffMean + k] = (float)mean;
+      params[kMlpOffIstd + k] = var > 1e-20 ? (float)(1.0 / std::sqrt(var)) : 0.f;
+      const double pad = 0.02 * (hi - lo) + 1e-6;
+      params[kMlpOffLo + k] = (float)(lo - pad);
+      params[kMlpOffHi + k] = (float)(hi + pad);
+    }
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int i = 0; i < kMlpH * kMlpF; ++i) params[kMlpOffW1 + i] = (float)(nd(rng) * std::sqrt(2.0 / kMlpF));
+    for (int i = 0; i < kMlpH * kMlpH; ++i) params[kMlpOffW2 + i] = (float)(nd(rng) * std::sqrt(2.0 / kMlpH));
+    for (int i = 0; i < kMlpH; ++i) {
+      params[kMlpOffB1 + i] = 0.f;
+      params[kMlpOffB2 + i] = 0.f;
+      params[kMlpOffW3 + i] = (float)(nd(rng) * std::sqrt(1.0 / kMlpH));
+    }
+    double ym = 0.0;
+    for (int64_t i = 0; i < n; ++i) ym += y[i];
+    params[kMlpOffB3] = (float)(ym / n);
+  }
+  DBuf d_p, d_X, d_y, d_idx, d_iota, d_m, d_v, d_gpart, d_lpart;
+  HIPCHK(d_p.alloc(kMlpNParam * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_p.p, params, kMlpNParam * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_X.alloc((size_t)n * kMlpF * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_X.p, X, (size_t)n * kMlpF * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_y.alloc((size_t)n * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_y.p, y, (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> perm(n);
+  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+  HIPCHK(upload(d_iota, perm, st));
+  HIPCHK(d_idx.alloc((size_t)n * sizeof(int64_t)));
+  HIPCHK(d_m.alloc(kMlpNTrain * sizeof(float)));
+  HIPCHK(d_v.alloc(kMlpNTrain * sizeof(float)));
+  HIPCHK(hipMemsetAsync(d_m.p, 0, kMlpNTrain * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(d_v.p, 0, kMlpNTrain * sizeof(float), st));
+  const int64_t nblk_max = (n + 63) / 64;
+  HIPCHK(d_gpart.alloc((size_t)nblk_max * kMlpNTrain * sizeof(float)));
+  HIPCHK(d_lpart.alloc((size_t)nblk_max * sizeof(float)));
+  std::mt19937_64 rng(seed ^ 0x5bd1e995ull);
+  int step = 0;
+  for (int e = 0; e < epochs; ++e) {
+    std::shuffle(perm.begin(), perm.end(), rng);
+    HIPCHK(hipMemcpyAsync(d_idx.p, perm.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    for (int64_t s0 = 0; s0 < n; s0 += batch) {
+      const int64_t nb = std::min<int64_t>(batch, n - s0);
+      HIPCHK(launch_mlp_step(d_p.as<float>(), d_X.as<float>(), d_y.as<float>(), d_idx.as<int64_t>() + s0, nb, kappa,
+                             d_gpart.as<float>(), d_lpart.as<float>(), nullptr, d_m.as<float>(), d_v.as<float>(), lr,
+                             ++step, st));
+    }
+    if (loss_history) {
+      const int rc = mlp_eval(d_p.as<float>(), d_X.as<float>(), d_y.as<float>(), d_iota.as<int64_t>(), n, kappa,
+                              d_gpart, d_lpart, nullptr, &loss_history[e], st);
+      if (rc) return rc;
+    } else {
+      HIPCHK(hipStreamSynchronize(st));  // perm is rewritten next epoch
+    }
+  }
+  HIPCHK(hipMemcpyAsync(params, d_p.p, kMlpNParam * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RSGDF_OK;
+}
+
+int rsgdf_mlp_grad(const float *params, const float *X, const float *y, int64_t n, float kappa, float *grad,
+                   float *loss, void *stream) {
+  g_err.clear();
+  if (!params || !X || !y || n < 1 || !grad || !loss) return fail(RSGDF_EINVAL, "invalid gradient arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DBuf d_p, d_X, d_y, d_iota, d_gpart, d_lpart;
+  HIPCHK(d_p.alloc(kMlpNParam * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_p.p, params, kMlpNParam * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_X.alloc((size_t)n * kMlpF * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_X.p, X, (size_t)n * kMlpF * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_y.alloc((size_t)n * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_y.p, y, (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> iota(n);
+  for (int64_t i = 0; i < n; ++i) iota[i] = i;
+  HIPCHK(upload(d_iota, iota, st));
+  const int64_t nblk = (n + 63) / 64;
+  HIPCHK(d_gpart.alloc((size_t)nblk * kMlpNTrain * sizeof(float)));
+  HIPCHK(d_lpart.alloc((size_t)nblk * sizeof(float)));
+  return mlp_eval(d_p.as<float>(), d_X.as<float>(), d_y.as<float>(), d_iota.as<int64_t>(), n, kappa, d_gpart, d_lpart,
+                  grad, loss, st);
+}
+
+int rsgdf_mlp_predict(const float *params, const float *X, int64_t n, int32_t mode, float *pred, void *stream) {
+  g_err.clear();
+  if (!params || !X || !pred || n < 1 || (mode != 0 && mode != 1)) return fail(RSGDF_EINVAL, "invalid predict arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DBuf d_p, d_X, d_pred;
+  HIPCHK(d_p.alloc(kMlpNParam * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_p.p, params, kMlpNParam * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_X.alloc((size_t)n * kMlpF * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(d_X.p, X, (size_t)n * kMlpF * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(d_pred.alloc((size_t)n * sizeof(float)));
+  HIPCHK(launch_mlp_predict(d_p.as<float>(), d_X.as<float>(), n, mode, d_pred.as<float>(), st));
+  HIPCHK(hipMemcpyAsync(pred, d_pred.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RSGDF_OK;
+}
+
+int rsgdf_mlp_margin(const float *params, const float *X, const float *y, int64_t n, double quantile,
+                     double *margin, void *stream) {
+  g_err.clear();
+  if (!margin || !(quantile > 0.0) || quantile > 1.0) return fail(RSGDF_EINVAL, "invalid margin arguments");
+  std::vector<float> pred(std::max<int64_t>(n, 1));
+  const int rc = rsgdf_mlp_predict(params, X, n, 1, pred.data(), stream);
+  if (rc) return rc;
+  std::vector<double> r(n);
+  for (int64_t i = 0; i < n; ++i) r[i] = (double)y[i] - (double)pred[i];
+  std::sort(r.begin(), r.end());
+  const int64_t k = std::min<int64_t>(n - 1, (int64_t)std::ceil(quantile * n) - 1);
+  *margin = std::max(0.0, r[std::max<int64_t>(k, 0)]);
   return RSGDF_OK;
 }
 

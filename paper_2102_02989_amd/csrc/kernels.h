@@ -93,4 +93,17 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,
                          hipStream_t stream);
 
+// learned screening (learned.hip)
+hipError_t launch_features(const SRParams &prm, int ntrip, const int64_t *idx, int64_t n, float *feat,
+                           hipStream_t stream);
+hipError_t launch_log_target(const float *logmag, int nk, int64_t ncand, float floor_, float *tgt,
+                             hipStream_t stream);
+hipError_t launch_mlp_step(float *params, const float *X, const float *y, const int64_t *idx, int64_t nb,
+                           float kappa, float *gpart, float *lpart, float *grad, float *m, float *v, float lr, int step,
+                           hipStream_t stream);
+hipError_t launch_mlp_mask(const SRParams &prm, int ntrip, int64_t ncand, const float *params, float cut,
+                           uint8_t *mask, long long *nskip, hipStream_t stream);
+hipError_t launch_mlp_predict(const float *params, const float *X, int64_t n, int mode, float *pred,
+                              hipStream_t stream);
+
 }  // namespace rsgdf

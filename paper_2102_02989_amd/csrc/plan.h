@@ -102,6 +102,10 @@ struct SRParams {
   double *X;                // [Nk][Nk][naux_b][nao][nao]
   int32_t aux_f0, naux_b, nao, pad;
   long long *counts;        // [work entry][4]: primitive terms, contractions, shell terms, 0
+  // learned screening: candidate (triplet, pair image ii) has index cand_off[trip] + ii
+  const int64_t *cand_off;  // [ntrip] (null when neither mask nor logmag is used)
+  const uint8_t *mask;      // keep flag per candidate, or null (rigorous screening only)
+  float *logmag;            // magnitude log: [candidate][Nk] max |block| per BvK cell c1, or null
 };
 
 }  // namespace rsgdf

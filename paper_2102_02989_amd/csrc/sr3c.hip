@@ -186,6 +186,8 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   }
   for (int i = lane; i < BLK; i += 64) s_blk[i] = 0.0;
   __syncthreads();
+  const bool logging = prm.logmag != nullptr;
+  const int64_t cbase = (prm.mask || logging) ? prm.cand_off[wk.trip] : 0;
   const double xstar = 1.0 / sqrt(2.0 * beta);
   const double gmax = xstar * exp(-0.5);
   const double inv_dR = 1.0 / dR;
@@ -260,6 +262,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
       // class of this image (the list is grouped by class)
       while (prm.cls_off[pr.cls_off + cls + 1] <= ii) ++cls;
       if (ii - prm.cls_off[pr.cls_off + cls] >= prm.nsr[pr.nsr_off + cls]) continue;  // beyond the SR radius
+      if (prm.mask && !prm.mask[cbase + ii]) continue;  // dropped by the learned screen
       const double *nv = prm.img + 3 * (size_t)(pr.img_off + ii);
       const double Bx = shB.x + nv[0], By = shB.y + nv[1], Bz = shB.z + nv[2];
       const double ABx = Ax - Bx, ABy = Ay - By, ABz = Az - Bz;
@@ -486,6 +489,19 @@ void sr3c_kernel(const SRParams prm, const int w0) {
         __syncthreads();
         if (!more) break;
         ++pass;
+      }
+      if (logging && blk_in_lds) {
+        // magnitude log: the accumulator holds only this pair image's block (it is
+        // flushed after every image in logging runs); max |block| per BvK cell c1,
+        // each (ii, c1) owned by one wave
+        if (grp_on) {
+          double mx = 0.0;
+          for (int comp = lig; comp < NBLK; comp += gs) mx = fmax(mx, fabs(s_blk[gl * NBLK + comp]));
+          for (int off = 1; off < gs; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+          if (lig == 0) prm.logmag[(cbase + ii) * nk + c1] = (float)mx;
+        }
+        flush(cur_cls);
+        __syncthreads();
       }
     }
     flush(cur_cls);

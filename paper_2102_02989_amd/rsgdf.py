@@ -20,6 +20,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 SCREEN_RIGOROUS, SCREEN_LEARNED = 0, 1
 PART_SR, PART_G0, PART_LR = 1, 2, 4
 PART_ALL = 7
+MLP_NFEAT, MLP_NPARAM = 16, 5377
 
 
 class RsgdfError(RuntimeError):
@@ -40,7 +41,7 @@ class BasisT(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("g_thresh", ctypes.c_double), ("lr_precision", ctypes.c_int32), ("screening", ctypes.c_int32),
-                ("parts", ctypes.c_int32), ("sr_slices", ctypes.c_int32), ("mlp_weights", ctypes.c_char_p),
+                ("parts", ctypes.c_int32), ("sr_slices", ctypes.c_int32), ("mlp_weights", ctypes.c_void_p),
                 ("mlp_margin", ctypes.c_double)]
 
 
@@ -50,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("n_sr_shell_terms", ctypes.c_int64), ("n_sr_candidates", ctypes.c_int64),
                 ("n_lr_terms", ctypes.c_int64), ("n_g_total", ctypes.c_int64), ("n_triplets", ctypes.c_int64),
                 ("n_aux_batches", ctypes.c_int64), ("bytes_out", ctypes.c_int64), ("sr_flops", ctypes.c_double),
-                ("t_lr_gemm_ms", ctypes.c_double), ("lr_gemm_flops", ctypes.c_double)]
+                ("t_lr_gemm_ms", ctypes.c_double), ("n_screen_candidates", ctypes.c_int64),
+                ("n_screen_skipped", ctypes.c_int64), ("lr_gemm_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +77,13 @@ def library():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise RsgdfError(-5, f"native library missing: {_LIB_PATH} (run __graft_entry__.build())")
+        # torch bundles a HIP runtime with the same soname (libamdhip64.so.7);
+        # loading it first makes the library bind to that one, so that the
+        # process holds a single HIP runtime whichever API is called first
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         L.rsgdf_j3c_nbytes.restype = ctypes.c_int64
@@ -86,6 +95,20 @@ def library():
         L.rsgdf_build_j3c_ex.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options),
                                          ctypes.POINTER(Out)]
+        F = ctypes.c_float
+        L.rsgdf_screen_log.restype = ctypes.c_int
+        L.rsgdf_screen_log.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, P, P,
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
+        L.rsgdf_mlp_train.restype = ctypes.c_int
+        L.rsgdf_mlp_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, F, F,
+                                      ctypes.c_uint64, ctypes.c_int32, P, P]
+        L.rsgdf_mlp_grad.restype = ctypes.c_int
+        L.rsgdf_mlp_grad.argtypes = [P, P, P, ctypes.c_int64, F, P, P, P]
+        L.rsgdf_mlp_predict.restype = ctypes.c_int
+        L.rsgdf_mlp_predict.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P]
+        L.rsgdf_mlp_margin.restype = ctypes.c_int
+        L.rsgdf_mlp_margin.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
         L.rsgdf_last_error.restype = ctypes.c_char_p
         L.rsgdf_version.restype = ctypes.c_char_p
         _lib = L
@@ -170,10 +193,86 @@ def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None
         sptr = stream.cuda_stream
     stats = Stats()
     o = Out(ptr, cap, int(on_device), sptr, 0, 0, 0, ctypes.pointer(stats))
+    w = None if mlp_weights is None else _f32(mlp_weights, MLP_NPARAM)
     opts = Options(-1.0 if g_thresh is None else float(g_thresh), int(lr_precision), int(screening), int(parts),
-                   int(sr_slices), None if mlp_weights is None else str(mlp_weights).encode(), float(mlp_margin))
+                   int(sr_slices), None if w is None else w.ctypes.data, float(mlp_margin))
     rc = library().rsgdf_build_j3c_ex(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
                                       m.kmesh.ctypes.data, float(omega), float(thresh), ctypes.byref(opts),
                                       ctypes.byref(o))
     _check(rc)
     return out, stats.as_dict()
+
+
+# ---- learned screening -------------------------------------------------------
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(a, np.float32)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream
+
+
+def screen_log(cell, basis, aux, kmesh, omega, thresh, *, sample_frac=1.0, seed=0, capacity=2_000_000, stream=None):
+    """rsgdf_screen_log: (features [n,16] float32, targets [n] float32)."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    n = ctypes.c_int64(0)
+    for _ in range(2):
+        feat = np.empty((max(capacity, 1), MLP_NFEAT), np.float32)
+        tgt = np.empty(max(capacity, 1), np.float32)
+        rc = library().rsgdf_screen_log(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                        m.kmesh.ctypes.data, float(omega), float(thresh), float(sample_frac),
+                                        int(seed), feat.ctypes.data, tgt.ctypes.data, int(capacity),
+                                        ctypes.byref(n), _stream_ptr(stream))
+        if rc == -2:
+            capacity = int(n.value)
+            continue
+        _check(rc)
+        return feat[:n.value].copy(), tgt[:n.value].copy()
+    _check(rc)
+
+
+def mlp_train(X, y, *, params=None, epochs=20, batch=4096, lr=1e-3, kappa=8.0, seed=0, stream=None):
+    """rsgdf_mlp_train: returns (params [MLP_NPARAM] float32, loss per epoch)."""
+    X, y = _f32(X), _f32(y)
+    init = params is None
+    p = np.zeros(MLP_NPARAM, np.float32) if init else _f32(params, MLP_NPARAM).copy()
+    hist = np.zeros(max(epochs, 1), np.float32)
+    _check(library().rsgdf_mlp_train(p.ctypes.data, X.ctypes.data, y.ctypes.data, len(y), int(epochs), int(batch),
+                                     float(lr), float(kappa), int(seed), int(init), hist.ctypes.data,
+                                     _stream_ptr(stream)))
+    return p, hist[:epochs]
+
+
+def mlp_grad(params, X, y, *, kappa=8.0, stream=None):
+    """rsgdf_mlp_grad: (loss, gradient over W1..b3 [5313])."""
+    p, X, y = _f32(params, MLP_NPARAM), _f32(X), _f32(y)
+    g = np.zeros(MLP_NPARAM - 64, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(library().rsgdf_mlp_grad(p.ctypes.data, X.ctypes.data, y.ctypes.data, len(y), float(kappa),
+                                    g.ctypes.data, loss.ctypes.data, _stream_ptr(stream)))
+    return float(loss[0]), g
+
+
+def mlp_predict(params, X, *, mode=1, stream=None):
+    """rsgdf_mlp_predict: mode 0 FP32, mode 1 FP16 matrix cores."""
+    p, X = _f32(params, MLP_NPARAM), _f32(X)
+    out = np.zeros(len(X), np.float32)
+    _check(library().rsgdf_mlp_predict(p.ctypes.data, X.ctypes.data, len(X), int(mode), out.ctypes.data,
+                                       _stream_ptr(stream)))
+    return out
+
+
+def mlp_margin(params, X, y, *, quantile=1.0, stream=None):
+    """rsgdf_mlp_margin."""
+    p, X, y = _f32(params, MLP_NPARAM), _f32(X), _f32(y)
+    m = ctypes.c_double(0.0)
+    _check(library().rsgdf_mlp_margin(p.ctypes.data, X.ctypes.data, y.ctypes.data, len(y), float(quantile),
+                                      ctypes.byref(m), _stream_ptr(stream)))
+    return m.value
