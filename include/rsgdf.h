@@ -103,6 +103,9 @@ typedef struct {
   int32_t sr_slices;     /* lanes cooperating on one (k-cell pair) unit; 0 -> automatic     */
   const float *mlp_weights; /* host, RSGDF_MLP_NPARAM floats (layout below), or NULL        */
   double mlp_margin;     /* log10 margin added to the learned prediction                    */
+  const float *sr_split; /* host [24] per-class work-split factors (rsgdf_autotune_sr), or NULL;
+                            class g = 6 l_P + pair class of (l_a, l_b) in order ss, ps, pp, ds,
+                            dp, dd                                                            */
 } rsgdf_options;
 
 typedef struct rsgdf_stats {
@@ -203,6 +206,33 @@ int rsgdf_mlp_predict(const float *params, const float *X, int64_t n, int32_t mo
  * the given samples, floored at 0. */
 int rsgdf_mlp_margin(const float *params, const float *X, const float *y, int64_t n, double quantile,
                      double *margin, void *stream);
+
+/* ---- batches of cells (a project addition).  All cells share omega, thresh
+ * and options; each has its own output (device memory, all on outs[0].stream).
+ * The short-range work items of all cells are merged into one launch per
+ * angular-momentum class; the whole device sequence is captured once into a
+ * HIP graph.  create: plans, allocates and captures (ENOMEM/EUNSUPPORTED if a
+ * cell would need aux-shell batching); run: replays the graph, fills each
+ * out's results and stats (t_total_ms = the whole batch); destroy frees. */
+typedef struct rsgdf_batch rsgdf_batch;
+int rsgdf_batch_create(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis *bases, const rsgdf_basis *auxes,
+                       const int32_t (*kmeshes)[3], double omega, double thresh, const rsgdf_options *opt,
+                       rsgdf_out *outs, rsgdf_batch **batch);
+int rsgdf_batch_run(rsgdf_batch *batch);
+void rsgdf_batch_destroy(rsgdf_batch *batch);
+/* create + run + destroy */
+int rsgdf_build_j3c_batch(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis *bases, const rsgdf_basis *auxes,
+                          const int32_t (*kmeshes)[3], double omega, double thresh, const rsgdf_options *opt,
+                          rsgdf_out *outs);
+
+/* Autotuner of the short-range work split: times every class of the given
+ * cell's short-range sum at uniform split factors {1/4, 1/2, 1, 2, 4} (the
+ * target work per wavefront relative to the default) and writes the fastest
+ * factor per class to split[24] (and its time in ms to class_ms[24] if not
+ * NULL), for rsgdf_options.sr_split. */
+int rsgdf_autotune_sr(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                      const int32_t kmesh[3], double omega, double thresh, float *split, double *class_ms,
+                      void *stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char *rsgdf_last_error(void);

@@ -12,6 +12,8 @@ from .rsgdf import (  # noqa: F401
     FP64,
     FP32,
     BF16X3,
+    Batch,
+    autotune_sr,
     MLP_NFEAT,
     MLP_NPARAM,
     SCREEN_LEARNED,

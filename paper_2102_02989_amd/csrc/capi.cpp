@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <random>
 #include <string>
 #include <thread>
@@ -582,52 +583,134 @@ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
-               const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt, rsgdf_out *out,
-               LearnCtl *ctl) {
+// four side streams per device for concurrent class launches (default priority)
+int side_streams(std::vector<hipStream_t> &ss) {
+  static thread_local std::vector<std::pair<int, hipStream_t>> pool;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  ss.clear();
+  for (auto &pr_ : pool)
+    if (pr_.first == dev) ss.push_back(pr_.second);
+  while (ss.size() < 4) {
+    hipStream_t s_;
+    HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    pool.push_back({dev, s_});
+    ss.push_back(s_);
+  }
+  return RSGDF_OK;
+}
+
+// One j3c build: host planning and every device allocation and upload in
+// prepare(); then device work only (no allocation, copy or wait, so that a
+// batch can be captured into a graph); results and statistics in finish().
+struct Job {
+  // ---- inputs
+  const rsgdf_cell *cell = nullptr;
+  const rsgdf_basis *basis = nullptr, *auxbasis = nullptr;
+  const int32_t *kmesh = nullptr;
+  double omega = 0, thresh = 0, g_thr = 0;
+  rsgdf_options o{};
+  rsgdf_out *out = nullptr;
+  LearnCtl *ctl = nullptr;
+  bool logging = false, learned = false, do_sr = false, do_g0 = false, do_lr = false;
+  bool tune = false;         // autotuner trial: short-range sums only, no output
+  std::vector<float> split;  // per-class work-split factors (24), empty = 1
+  // ---- plan
+  HostPlan hp;
+  int nk = 0, nkp = 0, npair = 0, nxs = 0, nb = 0;
+  int64_t nao = 0, naux = 0, nao2 = 0, need = 0;
+  double t_plan = 0.0;
+  DBuf d_ao, d_ax, d_aoe, d_aoc, d_aoc1, d_axe, d_axc, d_axc1, d_pairs, d_coff, d_nsr, d_img, d_boys;
+  DBuf d_outbuf;
+  double *d_out = nullptr;
+  std::vector<double> kph;
+  DBuf d_phi, d_kph, d_kdiag, d_SP, d_O, d_Smn;
+  // SR
+  std::vector<int> batch_start;
+  int nbatch = 0;
+  DBuf d_X, d_trip, d_cnt, d_work, d_part, d_pgrp, d_prm;
+  std::vector<Triplet> trips;
+  std::vector<int> tgrp_off, wgrp_off, pgrp_off;
+  std::vector<double> wgrp_cost;
+  std::vector<SRWork> work;
+  std::vector<SRPartGroup> pgroups;
+  int64_t ntrip = 0, nwork = 0, part_total = 0;
+  std::vector<int64_t> cand_off;
+  int64_t ncand = 0;
+  SRParams base{};
+  DBuf d_coffc, d_mask, d_mlp, d_nskip, d_logmag;
+  // LR
+  std::vector<int64_t> qoff{0};
+  int64_t nq_tot = 0, qchunk = 1;
+  std::vector<std::vector<int>> cls_kp;
+  std::vector<int64_t> kpl_off{0};
+  DBuf d_q, d_A, d_I, d_B, d_kp, d_ph, d_nterm, d_amax;
+  // results
+  float t_sr = 0.f, t_fold = 0.f, t_lr = 0.f, t_lr_gemm = 0.f;
+  long long n_lr = 0, nskip = 0;
+  double lr_flops = 0.0;
+  std::vector<long long> counts;  // per work item [4], filled by finish()
+
+  int prepare(hipStream_t st, double mem_frac);
+  SRParams batch_params(int b) const;
+  int enqueue_pre(hipStream_t st);
+  int enqueue_zero(int b, hipStream_t st);
+  int enqueue_sr(int b, hipStream_t st, const std::vector<hipStream_t> &ss, hipEvent_t evf, hipEvent_t *evj);
+  int enqueue_reduce(int b, hipStream_t st);
+  int enqueue_fold(int b, hipStream_t st);
+  int enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev);
+  int finish(hipStream_t st, const long long *cnt_host);
+};
+
+int Job::prepare(hipStream_t st, double mem_frac) {
   const auto t_start = std::chrono::steady_clock::now();
-  g_err.clear();
-  const bool logging = ctl && ctl->log;
+  logging = ctl && ctl->log;
   if (!out) return fail(RSGDF_EINVAL, "null output");
-  const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
+  need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
   if (need < 0) return (int)need;
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
   if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
   for (int i = 0; i < 3 * cell->natm; ++i)
     if (!std::isfinite(cell->coords[i])) return fail(RSGDF_EINVAL, "non-finite coordinates");
-  if (!logging) {
+  if (!logging && !tune) {
     if (!out->data) return fail(RSGDF_EINVAL, "null output buffer");
     if (out->capacity_bytes < need) return fail(RSGDF_ESIZE, "output capacity too small");
   }
-  rsgdf_options o{};
-  o.g_thresh = -1.0;
-  o.lr_precision = RSGDF_FP64;
-  o.screening = RSGDF_SCREEN_RIGOROUS;
-  o.parts = RSGDF_PART_ALL;
-  if (opt) o = *opt;
   if (o.parts == 0) o.parts = RSGDF_PART_ALL;
-  const double g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
+  g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
   if (o.lr_precision != RSGDF_FP64 && o.lr_precision != RSGDF_FP32 && o.lr_precision != RSGDF_BF16X3)
     return fail(RSGDF_EINVAL, "unknown lr_precision");
   if (o.screening != RSGDF_SCREEN_RIGOROUS && o.screening != RSGDF_SCREEN_LEARNED)
     return fail(RSGDF_EINVAL, "unknown screening mode");
-  const bool learned = o.screening == RSGDF_SCREEN_LEARNED && !logging;
+  learned = o.screening == RSGDF_SCREEN_LEARNED && !logging;
   if (learned && !o.mlp_weights) return fail(RSGDF_EUNSUPPORTED, "learned screening needs mlp_weights");
-  if (logging) o.parts = RSGDF_PART_SR;
+  if (logging || tune) o.parts = RSGDF_PART_SR;
+  do_sr = o.parts & RSGDF_PART_SR;
+  do_g0 = o.parts & RSGDF_PART_G0;
+  do_lr = o.parts & RSGDF_PART_LR;
+  if (o.sr_split) {
+    split.assign(o.sr_split, o.sr_split + 24);
+    for (float f : split)
+      if (!(f > 0.f) || !std::isfinite(f)) return fail(RSGDF_EINVAL, "sr_split factors must be > 0");
+  }
 
-  hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
-  HostPlan hp;
   int rc = build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
   if (rc) return rc;
+  // host sources of asynchronous uploads stay alive until the final synchronise
+  std::vector<SRParams> prms;
+  std::vector<double> qv, phl;
+  std::vector<int32_t> kpl;
   const Lattice &L = hp.lt.L;
-  const int nk = L.nk;
-  const int nkp = (int)hp.kp1.size();
-  const int64_t nao = hp.nao, naux = hp.naux, nao2 = nao * nao;
-  const int npair = (int)hp.pairs.size();
-  const int nxs = (int)hp.ax.size();
+  nk = L.nk;
+  nkp = (int)hp.kp1.size();
+  nao = hp.nao;
+  naux = hp.naux;
+  nao2 = nao * nao;
+  npair = (int)hp.pairs.size();
+  nxs = (int)hp.ax.size();
+  nb = nk * nk;  // rows of X: (c1, c2)
 
   // ---------------------------------------------------------- device tables
-  DBuf d_ao, d_ax, d_aoe, d_aoc, d_aoc1, d_axe, d_axc, d_axc1, d_pairs, d_coff, d_nsr, d_img, d_boys;
   HIPCHK(upload(d_ao, hp.ao, st));
   HIPCHK(upload(d_ax, hp.ax, st));
   HIPCHK(upload(d_aoe, hp.ao_exp, st));
@@ -640,21 +723,17 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
   HIPCHK(upload(d_coff, hp.cls_off, st));
   HIPCHK(upload(d_nsr, hp.nsr, st));
   HIPCHK(upload(d_img, hp.img, st));
-  HIPCHK(upload(d_boys, boys_poly_table(), st));
+  const std::vector<double> boys = boys_poly_table();
+  HIPCHK(upload(d_boys, boys, st));
 
-  // output buffer (device)
-  DBuf d_outbuf;
-  double *d_out = nullptr;
-  if (logging) {
-    d_out = nullptr;  // magnitude logging writes no output
+  if (logging || tune) {
+    d_out = nullptr;  // magnitude logging and tuning trials write no output
   } else if (out->on_device) {
     d_out = reinterpret_cast<double *>(out->data);
   } else {
     HIPCHK(d_outbuf.alloc((size_t)need));
     d_out = d_outbuf.as<double>();
   }
-
-  const int nb = nk * nk;  // rows of X: (c1, c2)
 
   // phase tables: Phi[kp][(c1,c2)] = e^{-i k1.L_c1} e^{+i k2.L_c2}; kphase[k][c] = e^{+i k.L_c}
   auto cell_ph = [&](int k, int c) {  // 2 pi sum_d j_d i_d / n_d
@@ -664,7 +743,8 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
     for (int d = 0; d < 3; ++d) s += (long double)(j[d] * i[d] % L.n[d]) / L.n[d];
     return (double)(2.0L * 3.14159265358979323846264338327950288L * s);
   };
-  std::vector<double> phi((size_t)2 * nkp * nb), kph((size_t)2 * nk * nk);
+  std::vector<double> phi((size_t)2 * nkp * nb);
+  kph.assign((size_t)2 * nk * nk, 0.0);
   for (int t = 0; t < nkp; ++t)
     for (int c1 = 0; c1 < nk; ++c1)
       for (int c2 = 0; c2 < nk; ++c2) {
@@ -703,42 +783,21 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
         SP[x.foff + ic] = v;
       }
   }
-  DBuf d_phi, d_kph, d_kdiag, d_SP, d_O, d_Smn;
   HIPCHK(upload(d_phi, phi, st));
   HIPCHK(upload(d_kph, kph, st));
   HIPCHK(upload(d_kdiag, kdiag, st));
   HIPCHK(upload(d_SP, SP, st));
-  const bool do_sr = o.parts & RSGDF_PART_SR, do_g0 = o.parts & RSGDF_PART_G0, do_lr = o.parts & RSGDF_PART_LR;
-
-  hipEvent_t ev[8];
-  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
-  struct EvGuard {
-    hipEvent_t *e;
-    ~EvGuard() {
-      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]);
-    }
-  } evg{ev};
-
-  const double t_plan = ms_since(t_start);
-  HIPCHK(hipEventRecord(ev[0], st));
-
-  // G = 0 overlaps
   if (do_g0) {
     HIPCHK(d_O.alloc((size_t)npair * nk * 36 * sizeof(double)));
     HIPCHK(d_Smn.alloc((size_t)nk * nao2 * 2 * sizeof(double)));
-    OvlParams op{d_ao.as<Shell>(), d_aoe.as<double>(), d_aoc.as<double>(), d_pairs.as<Pair>(),
-                 d_coff.as<int32_t>(), d_img.as<double>(), npair, nk, d_O.as<double>()};
-    SmnParams sp{d_ao.as<Shell>(), d_pairs.as<Pair>(), d_O.as<double>(), d_kph.as<double>(), npair, nk,
-                 (int32_t)nao, 0, d_Smn.as<double>()};
-    HIPCHK(launch_overlaps(op, sp, st));
   }
 
-  // ---------------------------------------------------------- SR + fold
+  // ---------------------------------------------------------- SR plan
   // aux batches bounded by the scratch budget of X
   size_t free_b = 0, total_b = 0;
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
-  const double budget = std::min(0.45 * (double)free_b, 64e9);
-  std::vector<int> batch_start{0};
+  const double budget = std::min(mem_frac * (double)free_b, 64e9);
+  batch_start.assign(1, 0);
   {
     int64_t nf = 0;
     for (int s = 0; s < nxs; ++s) {
@@ -751,7 +810,7 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
     }
     batch_start.push_back(nxs);
   }
-  const int nbatch = (int)batch_start.size() - 1;
+  nbatch = (int)batch_start.size() - 1;
   int64_t max_bf = 0;
   for (int b = 0; b < nbatch; ++b) {
     int64_t nf = 0;
@@ -760,17 +819,12 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
   }
   if (do_sr && (double)max_bf * nb * nao2 * 8.0 > 0.9 * (double)free_b)
     return fail(RSGDF_ENOMEM, "one aux shell's short-range scratch does not fit in device memory");
-  DBuf d_X, d_trip, d_cnt;
   if (do_sr) HIPCHK(d_X.alloc((size_t)max_bf * nb * nao2 * sizeof(double)));
 
   // triplets for all batches, grouped by (batch, lP, pair class)
-  std::vector<Triplet> trips;
-  std::vector<int> tgrp_off;  // [(nbatch) * 24 + 1]
-  std::vector<int> tgrp_L;
   {
     const Screen &S = hp.scr;
     std::vector<std::vector<Triplet>> grp((size_t)nbatch * 24);
-    std::vector<Triplet> all((size_t)nxs * npair);
     for (int64_t t = 0; t < (int64_t)nxs * npair; ++t) {
       Triplet tr{};
       tr.aux = (int32_t)(t / npair);
@@ -778,10 +832,6 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       tr.rc_cut = hp.rc_t[t];
       tr.amp = hp.amp_t[t];
       tr.nwin = std::max(1, (int)std::ceil(tr.rc_cut / S.dR));
-      all[t] = tr;
-    }
-    for (int64_t t = 0; t < (int64_t)nxs * npair; ++t) {
-      const Triplet &tr = all[t];
       if (tr.nwin > 256) return fail(RSGDF_EUNSUPPORTED, "R_c bound exceeds the window table (omega too small)");
       int b = 0;
       while (tr.aux >= batch_start[b + 1]) ++b;
@@ -789,13 +839,13 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       const int g = hp.ax[tr.aux].l * 6 + pair_class(hp.ao[p.sa].l, hp.ao[p.sb].l);
       grp[(size_t)b * 24 + g].push_back(tr);
     }
-    tgrp_off.push_back(0);
+    tgrp_off.assign(1, 0);
     for (auto &g : grp) {
       trips.insert(trips.end(), g.begin(), g.end());
       tgrp_off.push_back((int)trips.size());
     }
   }
-  const int64_t ntrip = (int64_t)trips.size();
+  ntrip = (int64_t)trips.size();
   {
     // the SR kernel packs lattice coordinates into 10-bit fields (|M| < 500)
     double rcmax = 0.0, r12max = 0.0, diam = 0.0;
@@ -806,10 +856,8 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       if ((rcmax + r12max + 2.0 * diam) * hp.lt.bn[d] / (2.0 * kPi) + L.n[d] + 2 > 500.0)
         return fail(RSGDF_EUNSUPPORTED, "screening radius too large for the packed image coordinates");
   }
-  // ---- learned-screening candidates: (triplet t, pair image ii) has index
+  // learned-screening candidates: (triplet t, pair image ii) has index
   // cand_off[t] + ii, ii over all images of the pair
-  std::vector<int64_t> cand_off;
-  int64_t ncand = 0;
   if (learned || logging) {
     cand_off.resize(ntrip);
     for (int64_t t = 0; t < ntrip; ++t) {
@@ -817,16 +865,12 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       ncand += hp.cls_off[(size_t)trips[t].pair * (nk + 1) + nk];
     }
   }
-  // ---- SR work list: a cost estimate per item (primitive triplets x pair
-  // images x lattice vectors in the R_c ball x per-term operations) decides how
-  // many waves share it, first by BvK cell ranges (disjoint outputs), then by
-  // interleaved pair-image slices with private partial blocks.
-  std::vector<SRWork> work;
-  std::vector<int> wgrp_off;        // [(nbatch) * 24 + 1]
-  std::vector<double> wgrp_cost;    // summed estimate per group
-  std::vector<SRPartGroup> pgroups;
-  std::vector<int> pgrp_off{0};     // per batch
-  int64_t part_total = 0;
+  // SR work list: a cost estimate per item (primitive triplets x pair images x
+  // lattice vectors in the R_c ball x per-term operations) decides how many
+  // waves share it, first by BvK cell ranges (disjoint outputs), then by
+  // interleaved pair-image slices with private partial blocks.  The per-class
+  // factors `split` (autotuner output) scale the target work per wave.
+  pgrp_off.assign(1, 0);
   {
     std::vector<double> est(ntrip);
     double tot = 0.0;
@@ -842,13 +886,14 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       tot += est[t];
     }
     // target cost per wave: 8 waves per SIMD over the build
-    const double target = std::max(tot / (8.0 * 1024.0), 1.0);
+    const double target0 = std::max(tot / (8.0 * 1024.0), 1.0);
     const double part_budget = 1.0e9;  // bytes of partial blocks
     double part_bytes = 0.0;
     std::vector<std::vector<SRWork>> grp((size_t)nbatch * 24);
     std::vector<std::vector<double>> gcost((size_t)nbatch * 24);
     for (int b = 0; b < nbatch; ++b) {
       for (int g = 0; g < 24; ++g) {
+        const double target = target0 * (split.empty() ? 1.0 : (double)split[g]);
         for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t) {
           const Triplet &tr = trips[t];
           const Pair &pp = hp.pairs[tr.pair];
@@ -882,6 +927,7 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
               w.ncb = (int16_t)ncb;
               w.slice = (int16_t)sl;
               w.nslice = (int16_t)nsl;
+              w.cell = 0;
               w.part = (nsl > 1) ? pbase + (int64_t)sl * ncb * nk * nblk : -1;
               grp[(size_t)b * 24 + g].push_back(w);
               gcost[(size_t)b * 24 + g].push_back(est[t] / ((double)nranges * nsl));
@@ -892,7 +938,7 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       pgrp_off.push_back((int)pgroups.size());
     }
     // heaviest waves first inside each class launch
-    wgrp_off.push_back(0);
+    wgrp_off.assign(1, 0);
     for (size_t g = 0; g < grp.size(); ++g) {
       std::vector<int> idx(grp[g].size());
       for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
@@ -917,42 +963,14 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       }
     }
   }
-  const int64_t nwork = (int64_t)work.size();
-  DBuf d_work, d_part, d_pgrp;
+  nwork = (int64_t)work.size();
   if (do_sr) {
     HIPCHK(upload(d_trip, trips, st));
     HIPCHK(upload(d_work, work, st));
     HIPCHK(upload(d_pgrp, pgroups, st));
     HIPCHK(d_part.alloc((size_t)std::max<int64_t>(part_total, 1) * sizeof(double)));
-    HIPCHK(d_cnt.alloc((size_t)nwork * 4 * sizeof(long long)));
-    HIPCHK(hipMemsetAsync(d_cnt.p, 0, (size_t)nwork * 4 * sizeof(long long), st));
+    HIPCHK(d_cnt.alloc((size_t)std::max<int64_t>(nwork, 1) * 4 * sizeof(long long)));
   }
-  // side streams for concurrent class launches (default priority)
-  static thread_local std::vector<std::pair<int, hipStream_t>> side_streams;
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  std::vector<hipStream_t> ss;
-  for (auto &pr_ : side_streams)
-    if (pr_.first == dev) ss.push_back(pr_.second);
-  while (ss.size() < 4) {
-    hipStream_t s_;
-    HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
-    side_streams.push_back({dev, s_});
-    ss.push_back(s_);
-  }
-  hipEvent_t evf, evj[4];
-  HIPCHK(hipEventCreateWithFlags(&evf, hipEventDisableTiming));
-  for (auto &e : evj) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  struct EvGuard2 {
-    hipEvent_t f;
-    hipEvent_t *j;
-    ~EvGuard2() {
-      (void)hipEventDestroy(f);
-      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(j[i]);
-    }
-  } evg2{evf, evj};
-
-  SRParams base{};
   base.ao = d_ao.as<Shell>();
   base.ax = d_ax.as<Shell>();
   base.ao_exp = d_aoe.as<double>();
@@ -966,7 +984,6 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
   base.nsr = d_nsr.as<int32_t>();
   base.img = d_img.as<double>();
   base.trip = d_trip.as<Triplet>();
-  base.work = d_work.as<SRWork>();
   base.part = d_part.as<double>();
   base.lat = L;
   base.omega = omega;
@@ -975,115 +992,34 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
   base.ncell_nf = hp.scr.ncell_nf;
   base.ncell_r0 = hp.scr.r0;
   base.boys = d_boys.as<double>();
+  base.X = d_X.as<double>();
   base.nao = (int32_t)nao;
-  base.counts = d_cnt.as<long long>();
-  DBuf d_coffc, d_mask, d_mlp, d_nskip, d_logmag;
   if (do_sr && (learned || logging)) {
     HIPCHK(upload(d_coffc, cand_off, st));
     base.cand_off = d_coffc.as<int64_t>();
   }
   if (do_sr && learned) {
-    // keep mask from the network: drop iff inside the training range and
-    // prediction + margin < log10(thresh)
     HIPCHK(d_mask.alloc((size_t)std::max<int64_t>(ncand, 1)));
     HIPCHK(d_mlp.alloc(kMlpNParam * sizeof(float)));
     HIPCHK(hipMemcpyAsync(d_mlp.p, o.mlp_weights, kMlpNParam * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(d_nskip.alloc(sizeof(long long)));
-    HIPCHK(hipMemsetAsync(d_nskip.p, 0, sizeof(long long), st));
-    const float cut = (float)(std::log10(thresh) - o.mlp_margin);
-    HIPCHK(launch_mlp_mask(base, (int)ntrip, ncand, d_mlp.as<float>(), cut, d_mask.as<uint8_t>(),
-                           d_nskip.as<long long>(), st));
     base.mask = d_mask.as<uint8_t>();
   }
   if (do_sr && logging) {
     HIPCHK(d_logmag.alloc((size_t)std::max<int64_t>(ncand, 1) * nk * sizeof(float)));
-    HIPCHK(hipMemsetAsync(d_logmag.p, 0xff, (size_t)std::max<int64_t>(ncand, 1) * nk * sizeof(float), st));  // NaN
     base.logmag = d_logmag.as<float>();
   }
-
-  float t_sr = 0.f, t_fold = 0.f;
-  for (int b = 0; b < nbatch; ++b) {
-    int64_t f0 = hp.ax[batch_start[b]].foff, nf = 0;
-    for (int s = batch_start[b]; s < batch_start[b + 1]; ++s) nf += ncart_h(hp.ax[s].l);
-    HIPCHK(hipEventRecord(ev[1], st));
-    if (do_sr) {
-      HIPCHK(hipMemsetAsync(d_X.p, 0, (size_t)nf * nb * nao2 * sizeof(double), st));
-      if (part_total > 0) HIPCHK(hipMemsetAsync(d_part.p, 0, (size_t)part_total * sizeof(double), st));
-      SRParams prm = base;
-      prm.X = d_X.as<double>();
-      prm.aux_f0 = (int32_t)f0;
-      prm.naux_b = (int32_t)nf;
-      // fork: classes in decreasing cost order, round-robin over the side streams
-      HIPCHK(hipEventRecord(evf, st));
-      for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, evf, 0));
-      std::vector<int> order(24);
-      for (int g = 0; g < 24; ++g) order[g] = g;
-      std::stable_sort(order.begin(), order.end(),
-                       [&](int x, int y) { return wgrp_cost[(size_t)b * 24 + x] > wgrp_cost[(size_t)b * 24 + y]; });
-      int k = 0;
-      for (int g : order) {
-        const int w0 = wgrp_off[(size_t)b * 24 + g], w1 = wgrp_off[(size_t)b * 24 + g + 1];
-        if (w1 == w0) continue;
-        HIPCHK(launch_sr3c(g / 6, g % 6, prm, w0, w1 - w0, ss[k % ss.size()]));
-        ++k;
-      }
-      for (size_t i = 0; i < ss.size(); ++i) {
-        HIPCHK(hipEventRecord(evj[i], ss[i]));
-        HIPCHK(hipStreamWaitEvent(st, evj[i], 0));
-      }
-      // sum split items into X
-      const int pg0 = pgrp_off[b], pg1 = pgrp_off[b + 1];
-      if (pg1 > pg0) {
-        const SRPartGroup &last = pgroups[pg1 - 1];
-        const Pair &pp = hp.pairs[trips[last.trip].pair];
-        const int nblk = ncart_h(hp.ax[trips[last.trip].aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
-        const int64_t nelem = last.elem_off + (int64_t)last.ncb * nk * nblk;
-        HIPCHK(launch_sr_reduce(prm, d_pgrp.as<SRPartGroup>() + pg0, pg1 - pg0, nelem, st));
-      }
-    }
-    HIPCHK(hipEventRecord(ev[2], st));
-    if (logging) {
-      HIPCHK(hipEventSynchronize(ev[2]));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
-      t_sr += ms;
-      continue;
-    }
-    FoldParams fp{};
-    fp.phi = d_phi.as<double>();
-    fp.X = do_sr ? d_X.as<double>() : nullptr;
-    fp.out = d_out;
-    fp.kdiag = d_kdiag.as<int32_t>();
-    fp.SP = d_SP.as<double>() + f0;
-    fp.Smn = do_g0 ? d_Smn.as<double>() : nullptr;
-    fp.g0fac = do_g0 ? kPi / (L.vol * omega * omega) : 0.0;
-    fp.ne = nf * nao2;
-    fp.out_off = f0 * nao2;
-    fp.plane = naux * nao2;
-    fp.nkp = nkp;
-    fp.nb = nb;
-    fp.nao2 = (int32_t)nao2;
-    HIPCHK(launch_fold(fp, st));
-    HIPCHK(hipEventRecord(ev[3], st));
-    HIPCHK(hipEventSynchronize(ev[3]));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, ev[1], ev[2]));
-    t_sr += ms;
-    HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
-    t_fold += ms;
+  // per-batch parameter blocks of the SR kernels (one cell)
+  if (do_sr) {
+    prms.resize(nbatch);
+    for (int b = 0; b < nbatch; ++b) prms[b] = batch_params(b);
+    HIPCHK(upload(d_prm, prms, st));
   }
 
-  // ---------------------------------------------------------- LR
-  float t_lr = 0.f, t_lr_gemm = 0.f;
-  long long n_lr = 0;
-  int64_t n_g = 0;
-  double lr_flops = 0.0;
+  // ---------------------------------------------------------- LR plan
   if (do_lr) {
-    HIPCHK(hipEventRecord(ev[4], st));
     // G sets per folded k12 class: q = G + k_c, q != 0, exp(-q^2/4w^2) >= g_thr
     const double q2max = -4.0 * omega * omega * std::log(g_thr);
-    std::vector<double> qv;
-    std::vector<int64_t> qoff{0};
     for (int c = 0; c < nk; ++c) {
       const double *kc = &hp.kvec[3 * c];
       const double qm = std::sqrt(std::max(q2max, 0.0)) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
@@ -1110,10 +1046,9 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       for (const auto &e : qc) qv.insert(qv.end(), e.begin() + 1, e.end());
       qoff.push_back((int64_t)qv.size() / 3);
     }
-    const int64_t nq_tot = qoff.back();
-    n_g = nq_tot;
+    nq_tot = qoff.back();
     // k-pairs per class
-    std::vector<std::vector<int>> cls_kp(nk);
+    cls_kp.assign(nk, {});
     for (int t = 0; t < nkp; ++t) {
       const int k1 = hp.kp1[t], k2 = hp.kp2[t];
       const int j1[3] = {k1 / (L.n[1] * L.n[2]), (k1 / L.n[2]) % L.n[1], k1 % L.n[2]};
@@ -1122,34 +1057,25 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       for (int d = 0; d < 3; ++d) c = c * L.n[d] + ((j2[d] - j1[d]) % L.n[d] + L.n[d]) % L.n[d];
       cls_kp[c].push_back(t);
     }
-    DBuf d_q, d_A;
     HIPCHK(upload(d_q, qv, st));
     HIPCHK(d_A.alloc((size_t)naux * std::max<int64_t>(nq_tot, 1) * 2 * sizeof(double)));
-    AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
-                   (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
-    HIPCHK(launch_auxft(ap, st));
-    // Per q chunk: pair transforms binned by BvK class (I, no Bloch phase),
-    // the k2 phases of the class's k-pairs (B), then the G-space contraction.
+    // per q chunk: pair transforms binned by BvK class (I), the k2 phases of
+    // the class's k-pairs (B), then the G-space contraction
     int max_kpi = 0;
     for (auto &v : cls_kp) max_kpi = std::max<int>(max_kpi, (int)v.size());
-    const double bbudget = std::min(0.25 * (double)free_b, 16e9);
-    int64_t qchunk = (int64_t)(bbudget / ((double)(nk + std::max(1, max_kpi)) * nao2 * 16.0));
+    const double bbudget = std::min(0.5 * mem_frac * (double)free_b, 16e9);
+    qchunk = (int64_t)(bbudget / ((double)(nk + std::max(1, max_kpi)) * nao2 * 16.0));
     qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 8192));
     int64_t max_nq = 0;
     for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, qoff[c + 1] - qoff[c]);
     qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
-    DBuf d_I, d_B, d_kp, d_ph, d_nterm, d_amax;
     HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
     HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
-    HIPCHK(d_kp.alloc((size_t)nkp * sizeof(int32_t)));
-    HIPCHK(d_ph.alloc((size_t)nkp * nk * 2 * sizeof(double)));
+    HIPCHK(d_kp.alloc((size_t)std::max(nkp, 1) * sizeof(int32_t)));
+    HIPCHK(d_ph.alloc((size_t)std::max(nkp, 1) * nk * 2 * sizeof(double)));
     HIPCHK(d_nterm.alloc(sizeof(long long)));
-    HIPCHK(hipMemsetAsync(d_nterm.p, 0, sizeof(long long), st));
-    // k-pair lists and e^{+i k2.L_c} rows of every class, uploaded once
-    std::vector<int32_t> kpl;
-    std::vector<double> phl;
-    std::vector<int64_t> kpl_off{0};
+    // k-pair lists and e^{+i k2.L_c} rows of every class
     for (int c = 0; c < nk; ++c) {
       for (int t : cls_kp[c]) {
         kpl.push_back(t);
@@ -1162,91 +1088,205 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       HIPCHK(hipMemcpyAsync(d_kp.p, kpl.data(), kpl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
       HIPCHK(hipMemcpyAsync(d_ph.p, phl.data(), phl.size() * sizeof(double), hipMemcpyHostToDevice, st));
     }
-    std::vector<hipEvent_t> gev;
-    const int lr_nq_hi = 32;
-    for (int c = 0; c < nk; ++c) {
-      const int nkpi = (int)cls_kp[c].size();
-      const int64_t nqc = qoff[c + 1] - qoff[c];
-      if (nkpi == 0 || nqc == 0) continue;
-      for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
-        const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
-        HIPCHK(launch_amax(d_A.as<double>() + 2 * (qoff[c] + q0), nq_tot, (int)naux, nq, d_amax.as<double>(), st));
-        PairFTParams pp{};
-        pp.ao = d_ao.as<Shell>();
-        pp.ao_exp = d_aoe.as<double>();
-        pp.ao_coef = d_aoc.as<double>();
-        pp.pairs = d_pairs.as<Pair>();
-        pp.cls_off = d_coff.as<int32_t>();
-        pp.img = d_img.as<double>();
-        pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);
-        pp.amax = d_amax.as<double>();
-        pp.npair = npair;
-        pp.nq = nq;
-        pp.nao = (int32_t)nao;
-        pp.nk = nk;
-        for (int d = 0; d < 3; ++d) pp.kn[d] = L.n[d];
-        pp.kcls[0] = c / (L.n[1] * L.n[2]);
-        pp.kcls[1] = (c / L.n[2]) % L.n[1];
-        pp.kcls[2] = c % L.n[2];
-        pp.eps = 1e-8 * thresh;
-        pp.B = d_I.as<double>();
-        pp.nterm = d_nterm.as<long long>();
-        HIPCHK(launch_pairft_binned(pp, st));
-        HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.as<double>(), nk, nkpi, nq,
-                             nao2, st));
-        LRGemmParams gp{};
-        gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
-        gp.lda = nq_tot;
-        gp.B = d_B.as<double>();
-        gp.out = d_out;
-        gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
-        gp.plane = naux * nao2;
-        gp.naux = (int32_t)naux;
-        gp.nq = nq;
-        gp.nmn = (int32_t)nao2;
-        gp.nq_hi = (q0 == 0) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
-        hipEvent_t e0, e1;
+  }
+  // uploads read host vectors that live in this object; make them complete
+  HIPCHK(hipStreamSynchronize(st));
+  t_plan = ms_since(t_start);
+  return RSGDF_OK;
+}
+
+SRParams Job::batch_params(int b) const {
+  SRParams p = base;
+  p.aux_f0 = (int32_t)hp.ax[batch_start[b]].foff;
+  int64_t nf = 0;
+  for (int s = batch_start[b]; s < batch_start[b + 1]; ++s) nf += ncart_h(hp.ax[s].l);
+  p.naux_b = (int32_t)nf;
+  return p;
+}
+
+// device work before the SR sums: G = 0 overlaps, learned keep mask, zeroed counters
+int Job::enqueue_pre(hipStream_t st) {
+  if (do_g0) {
+    OvlParams op{d_ao.as<Shell>(), d_aoe.as<double>(), d_aoc.as<double>(), d_pairs.as<Pair>(),
+                 d_coff.as<int32_t>(), d_img.as<double>(), npair, hp.lt.L.nk, d_O.as<double>()};
+    SmnParams sp{d_ao.as<Shell>(), d_pairs.as<Pair>(), d_O.as<double>(), d_kph.as<double>(), npair, nk,
+                 (int32_t)nao, 0, d_Smn.as<double>()};
+    HIPCHK(launch_overlaps(op, sp, st));
+  }
+  if (do_sr) {
+    HIPCHK(launch_zero(d_cnt.p, (size_t)std::max<int64_t>(nwork, 1) * 4 * sizeof(long long), st));
+    if (learned) {
+      // drop iff inside the training range and prediction + margin < log10(thresh)
+      HIPCHK(launch_zero(d_nskip.p, sizeof(long long), st));
+      const float cut = (float)(std::log10(thresh) - o.mlp_margin);
+      HIPCHK(launch_mlp_mask(base, (int)ntrip, ncand, d_mlp.as<float>(), cut, d_mask.as<uint8_t>(),
+                             d_nskip.as<long long>(), st));
+    }
+    if (logging)  // NaN marks candidates the image loop never reached
+      HIPCHK(hipMemsetAsync(d_logmag.p, 0xff, (size_t)std::max<int64_t>(ncand, 1) * nk * sizeof(float), st));
+  }
+  return RSGDF_OK;
+}
+
+// SR sums of aux batch b: zero X and the partial blocks, class launches in
+// decreasing cost order round-robin over the side streams, joined back to st
+int Job::enqueue_zero(int b, hipStream_t st) {
+  if (!do_sr) return RSGDF_OK;
+  const SRParams prm = batch_params(b);
+  HIPCHK(launch_zero(d_X.p, (size_t)prm.naux_b * nb * nao2 * sizeof(double), st));
+  if (part_total > 0) HIPCHK(launch_zero(d_part.p, (size_t)part_total * sizeof(double), st));
+  return RSGDF_OK;
+}
+
+int Job::enqueue_sr(int b, hipStream_t st, const std::vector<hipStream_t> &ss, hipEvent_t evf, hipEvent_t *evj) {
+  if (!do_sr) return RSGDF_OK;
+  int rc = enqueue_zero(b, st);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(evf, st));
+  for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, evf, 0));
+  std::vector<int> order(24);
+  for (int g = 0; g < 24; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return wgrp_cost[(size_t)b * 24 + x] > wgrp_cost[(size_t)b * 24 + y]; });
+  int k = 0;
+  for (int g : order) {
+    const int w0 = wgrp_off[(size_t)b * 24 + g], w1 = wgrp_off[(size_t)b * 24 + g + 1];
+    if (w1 == w0) continue;
+    HIPCHK(launch_sr3c(g / 6, g % 6, d_prm.as<SRParams>() + b, d_work.as<SRWork>(), d_cnt.as<long long>(), w0,
+                       w1 - w0, ss[k % ss.size()]));
+    ++k;
+  }
+  for (size_t i = 0; i < ss.size(); ++i) {
+    HIPCHK(hipEventRecord(evj[i], ss[i]));
+    HIPCHK(hipStreamWaitEvent(st, evj[i], 0));
+  }
+  return enqueue_reduce(b, st);
+}
+
+// sum the split items of batch b into X
+int Job::enqueue_reduce(int b, hipStream_t st) {
+  const int pg0 = pgrp_off[b], pg1 = pgrp_off[b + 1];
+  if (!do_sr || pg1 <= pg0) return RSGDF_OK;
+  const SRPartGroup &last = pgroups[pg1 - 1];
+  const Pair &pp = hp.pairs[trips[last.trip].pair];
+  const int nblk = ncart_h(hp.ax[trips[last.trip].aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+  const int64_t nelem = last.elem_off + (int64_t)last.ncb * nk * nblk;
+  HIPCHK(launch_sr_reduce(batch_params(b), d_pgrp.as<SRPartGroup>() + pg0, pg1 - pg0, nelem, st));
+  return RSGDF_OK;
+}
+
+// Bloch fold (+ G = 0 term) of aux batch b into the output
+int Job::enqueue_fold(int b, hipStream_t st) {
+  const SRParams prm = batch_params(b);
+  const int64_t f0 = prm.aux_f0, nf = prm.naux_b;
+  FoldParams fp{};
+  fp.phi = d_phi.as<double>();
+  fp.X = do_sr ? d_X.as<double>() : nullptr;
+  fp.out = d_out;
+  fp.kdiag = d_kdiag.as<int32_t>();
+  fp.SP = d_SP.as<double>() + f0;
+  fp.Smn = do_g0 ? d_Smn.as<double>() : nullptr;
+  fp.g0fac = do_g0 ? kPi / (hp.lt.L.vol * omega * omega) : 0.0;
+  fp.ne = nf * nao2;
+  fp.out_off = f0 * nao2;
+  fp.plane = naux * nao2;
+  fp.nkp = nkp;
+  fp.nb = nb;
+  fp.nao2 = (int32_t)nao2;
+  HIPCHK(launch_fold(fp, st));
+  return RSGDF_OK;
+}
+
+// long-range part, accumulated into the output; gev (optional) receives
+// event pairs around each contraction launch
+int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
+  if (!do_lr) return RSGDF_OK;
+  const Lattice &L = hp.lt.L;
+  HIPCHK(launch_zero(d_nterm.p, sizeof(long long), st));
+  AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
+                 (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
+  HIPCHK(launch_auxft(ap, st));
+  const int lr_nq_hi = 32;
+  for (int c = 0; c < nk; ++c) {
+    const int nkpi = (int)cls_kp[c].size();
+    const int64_t nqc = qoff[c + 1] - qoff[c];
+    if (nkpi == 0 || nqc == 0) continue;
+    for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
+      const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
+      HIPCHK(launch_amax(d_A.as<double>() + 2 * (qoff[c] + q0), nq_tot, (int)naux, nq, d_amax.as<double>(), st));
+      PairFTParams pp{};
+      pp.ao = d_ao.as<Shell>();
+      pp.ao_exp = d_aoe.as<double>();
+      pp.ao_coef = d_aoc.as<double>();
+      pp.pairs = d_pairs.as<Pair>();
+      pp.cls_off = d_coff.as<int32_t>();
+      pp.img = d_img.as<double>();
+      pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);
+      pp.amax = d_amax.as<double>();
+      pp.npair = npair;
+      pp.nq = nq;
+      pp.nao = (int32_t)nao;
+      pp.nk = nk;
+      for (int d = 0; d < 3; ++d) pp.kn[d] = L.n[d];
+      pp.kcls[0] = c / (L.n[1] * L.n[2]);
+      pp.kcls[1] = (c / L.n[2]) % L.n[1];
+      pp.kcls[2] = c % L.n[2];
+      pp.eps = 1e-8 * thresh;
+      pp.B = d_I.as<double>();
+      pp.nterm = d_nterm.as<long long>();
+      HIPCHK(launch_pairft_binned(pp, st));
+      HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.as<double>(), nk, nkpi, nq,
+                           nao2, st));
+      LRGemmParams gp{};
+      gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
+      gp.lda = nq_tot;
+      gp.B = d_B.as<double>();
+      gp.out = d_out;
+      gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
+      gp.plane = naux * nao2;
+      gp.naux = (int32_t)naux;
+      gp.nq = nq;
+      gp.nmn = (int32_t)nao2;
+      gp.nq_hi = (q0 == 0) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (gev) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        gev.push_back(e0);
-        gev.push_back(e1);
+        gev->push_back(e0);
+        gev->push_back(e1);
         HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(launch_lr_gemm_mfma(o.lr_precision, gp, nkpi, st));
-        HIPCHK(hipEventRecord(e1, st));
-        lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
       }
+      HIPCHK(launch_lr_gemm_mfma(o.lr_precision, gp, nkpi, st));
+      if (gev) HIPCHK(hipEventRecord(e1, st));
+      lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
     }
-    HIPCHK(hipMemcpyAsync(&n_lr, d_nterm.p, sizeof(long long), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (size_t i = 0; i < gev.size(); i += 2) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, gev[i], gev[i + 1]));
-      t_lr_gemm += ms;
-    }
-    for (hipEvent_t e : gev) (void)hipEventDestroy(e);
-    HIPCHK(hipEventRecord(ev[5], st));
-    HIPCHK(hipEventSynchronize(ev[5]));
-    HIPCHK(hipEventElapsedTime(&t_lr, ev[4], ev[5]));
   }
+  return RSGDF_OK;
+}
 
-  if (!logging && !out->on_device) {
+// read back counters (after the device work has completed) and fill stats;
+// cnt_host: per-work-item counters if already copied (batch), else read here
+int Job::finish(hipStream_t st, const long long *cnt_host) {
+  if (!logging && !tune && !out->on_device)
     HIPCHK(hipMemcpyAsync(out->data, d_out, (size_t)need, hipMemcpyDeviceToHost, st));
+  if (do_lr) HIPCHK(hipMemcpyAsync(&n_lr, d_nterm.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+  if (learned && do_sr) HIPCHK(hipMemcpyAsync(&nskip, d_nskip.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+  counts.assign((size_t)nwork * 4, 0);
+  if (do_sr && nwork > 0) {
+    if (cnt_host) std::copy(cnt_host, cnt_host + nwork * 4, counts.begin());
+    else HIPCHK(hipMemcpyAsync(counts.data(), d_cnt.p, counts.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
   }
   HIPCHK(hipStreamSynchronize(st));
-
-  // ---------------------------------------------------------- learned screening
-  long long nskip = 0;
-  if (learned && do_sr) HIPCHK(hipMemcpy(&nskip, d_nskip.p, sizeof(long long), hipMemcpyDeviceToHost));
   if (ctl) {
     ctl->ncand = ncand;
     ctl->nskip = nskip;
   }
   if (logging && do_sr && ncand > 0) {
     // targets of the candidates the image loop reached, a seeded sample of
-    // them, and their features
+    // them, and their features; below log10(thresh) - 4 every candidate is
+    // equally negligible
     DBuf d_tgt;
     HIPCHK(d_tgt.alloc((size_t)ncand * sizeof(float)));
-    // below log10(thresh) - 4 every candidate is equally negligible
     HIPCHK(launch_log_target(d_logmag.as<float>(), nk, ncand, (float)(std::log10(thresh) - 4.0), d_tgt.as<float>(),
                              st));
     std::vector<float> tgt(ncand);
@@ -1269,12 +1309,12 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       HIPCHK(hipStreamSynchronize(st));
     }
   }
-
-  // ---------------------------------------------------------- stats
-  out->nkpair = nkp;
-  out->naux = naux;
-  out->nao = nao;
-  if (out->stats) {
+  if (out) {
+    out->nkpair = nkp;
+    out->naux = naux;
+    out->nao = nao;
+  }
+  if (out && out->stats) {
     rsgdf_stats &s = *out->stats;
     std::memset(&s, 0, sizeof(s));
     s.t_plan_ms = t_plan;
@@ -1284,20 +1324,18 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
     s.n_lr_terms = n_lr;
     s.t_lr_gemm_ms = t_lr_gemm;
     s.lr_gemm_flops = lr_flops;
-    s.n_g_total = n_g;
-    s.n_screen_candidates = ncand;
-    s.n_screen_skipped = nskip;
+    s.n_g_total = nq_tot;
     s.n_triplets = ntrip;
     s.n_aux_batches = nbatch;
     s.bytes_out = need;
+    s.n_screen_candidates = ncand;
+    s.n_screen_skipped = nskip;
     if (do_sr && ntrip > 0) {
-      std::vector<long long> cnt((size_t)nwork * 4);
-      HIPCHK(hipMemcpy(cnt.data(), d_cnt.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
       std::vector<long long> tterms(ntrip, 0), tshell(ntrip, 0), tcontr(ntrip, 0);
       for (int64_t w = 0; w < nwork; ++w) {
-        tterms[work[w].trip] += cnt[(size_t)w * 4];
-        tcontr[work[w].trip] += cnt[(size_t)w * 4 + 1];
-        tshell[work[w].trip] += cnt[(size_t)w * 4 + 2];
+        tterms[work[w].trip] += counts[(size_t)w * 4];
+        tcontr[work[w].trip] += counts[(size_t)w * 4 + 1];
+        tshell[work[w].trip] += counts[(size_t)w * 4 + 2];
       }
       double flops = 0.0;
       for (int b = 0; b < nbatch; ++b)
@@ -1306,11 +1344,10 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
           static const int la_of[6] = {0, 1, 1, 2, 2, 2}, lb_of[6] = {0, 0, 1, 0, 1, 2};
           const int Lt = lP + la_of[pc] + lb_of[pc];
           long long nt = 0;
-          for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t)
-            {
-              nt += tterms[t];
-              s.n_sr_shell_terms += tshell[t];
-            }
+          for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t) {
+            nt += tterms[t];
+            s.n_sr_shell_terms += tshell[t];
+          }
           s.n_sr_terms += nt;
           flops += (double)nt * sr_term_flops(Lt);
         }
@@ -1320,22 +1357,341 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
       if (const char *fn = std::getenv("RSGDF_COUNTS_FILE")) {
         if (FILE *f = std::fopen(fn, "w")) {
           for (int64_t t = 0; t < ntrip; ++t) {
-            long long nt = 0;
-            nt = tterms[t];
             const Pair &pr = hp.pairs[trips[t].pair];
             std::fprintf(f, "%d %d %d %d %d %lld %lld %lld %.3f\n", trips[t].aux, trips[t].pair, hp.ax[trips[t].aux].l,
-                         hp.ao[pr.sa].l, hp.ao[pr.sb].l, nt, tcontr[t], tshell[t], trips[t].rc_cut);
+                         hp.ao[pr.sa].l, hp.ao[pr.sb].l, tterms[t], tcontr[t], tshell[t], trips[t].rc_cut);
           }
           std::fclose(f);
         }
       }
     }
-    s.t_total_ms = ms_since(t_start);
+  }
+  return RSGDF_OK;
+}
+
+struct EventSet {
+  std::vector<hipEvent_t> e;
+  ~EventSet() {
+    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+  }
+  int make(int n, unsigned flags) {
+    for (int i = 0; i < n; ++i) {
+      hipEvent_t x;
+      HIPCHK(hipEventCreateWithFlags(&x, flags));
+      e.push_back(x);
+    }
+    return RSGDF_OK;
+  }
+};
+
+// one build on one stream, timed per phase with events
+int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+               const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt, rsgdf_out *out,
+               LearnCtl *ctl) {
+  const auto t_start = std::chrono::steady_clock::now();
+  g_err.clear();
+  Job j;
+  j.cell = cell;
+  j.basis = basis;
+  j.auxbasis = auxbasis;
+  j.kmesh = kmesh;
+  j.omega = omega;
+  j.thresh = thresh;
+  j.out = out;
+  j.ctl = ctl;
+  j.o.g_thresh = -1.0;
+  j.o.lr_precision = RSGDF_FP64;
+  j.o.screening = RSGDF_SCREEN_RIGOROUS;
+  j.o.parts = RSGDF_PART_ALL;
+  if (opt) j.o = *opt;
+  hipStream_t st = out ? reinterpret_cast<hipStream_t>(out->stream) : nullptr;
+  int rc = j.prepare(st, 0.45);
+  if (rc) return rc;
+  std::vector<hipStream_t> ss;
+  if ((rc = side_streams(ss))) return rc;
+  EventSet ev, evs;
+  if ((rc = ev.make(6, 0))) return rc;
+  if ((rc = evs.make(5, hipEventDisableTiming))) return rc;
+  if ((rc = j.enqueue_pre(st))) return rc;
+  for (int b = 0; b < j.nbatch; ++b) {
+    HIPCHK(hipEventRecord(ev.e[0], st));
+    if ((rc = j.enqueue_sr(b, st, ss, evs.e[0], &evs.e[1]))) return rc;
+    HIPCHK(hipEventRecord(ev.e[1], st));
+    if (!j.logging && (rc = j.enqueue_fold(b, st))) return rc;
+    HIPCHK(hipEventRecord(ev.e[2], st));
+    HIPCHK(hipEventSynchronize(ev.e[2]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    j.t_sr += ms;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[1], ev.e[2]));
+    j.t_fold += ms;
+  }
+  if (j.do_lr) {
+    EventSet gev;
+    HIPCHK(hipEventRecord(ev.e[3], st));
+    if ((rc = j.enqueue_lr(st, &gev.e))) return rc;
+    HIPCHK(hipEventRecord(ev.e[4], st));
+    HIPCHK(hipEventSynchronize(ev.e[4]));
+    HIPCHK(hipEventElapsedTime(&j.t_lr, ev.e[3], ev.e[4]));
+    for (size_t i = 0; i < gev.e.size(); i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, gev.e[i], gev.e[i + 1]));
+      j.t_lr_gemm += ms;
+    }
+  }
+  if ((rc = j.finish(st, nullptr))) return rc;
+  if (out && out->stats) out->stats->t_total_ms = ms_since(t_start);
+  return RSGDF_OK;
+}
+
+
+// rigorous, short-range-only trial of one cell with uniform split factor f:
+// per-class kernel times, classes launched one after another on st
+int tune_trial(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis, const int32_t kmesh[3],
+               double omega, double thresh, float f, hipStream_t st, double *class_ms) {
+  Job j;
+  rsgdf_out dummy{};
+  dummy.stream = st;
+  std::vector<float> fs(24, f);
+  j.cell = cell;
+  j.basis = basis;
+  j.auxbasis = auxbasis;
+  j.kmesh = kmesh;
+  j.omega = omega;
+  j.thresh = thresh;
+  j.out = &dummy;
+  j.tune = true;
+  j.o.g_thresh = -1.0;
+  j.o.parts = RSGDF_PART_SR;
+  j.o.sr_split = fs.data();
+  int rc = j.prepare(st, 0.45);
+  if (rc) return rc;
+  if ((rc = j.enqueue_pre(st))) return rc;
+  EventSet ev;
+  if ((rc = ev.make(2 * 24, 0))) return rc;
+  for (int g = 0; g < 24; ++g) class_ms[g] = 0.0;
+  for (int b = 0; b < j.nbatch; ++b) {
+    if ((rc = j.enqueue_zero(b, st))) return rc;
+    for (int g = 0; g < 24; ++g) {
+      const int w0 = j.wgrp_off[(size_t)b * 24 + g], w1 = j.wgrp_off[(size_t)b * 24 + g + 1];
+      HIPCHK(hipEventRecord(ev.e[2 * g], st));
+      if (w1 > w0)
+        HIPCHK(launch_sr3c(g / 6, g % 6, j.d_prm.as<SRParams>() + b, j.d_work.as<SRWork>(), j.d_cnt.as<long long>(),
+                           w0, w1 - w0, st));
+      HIPCHK(hipEventRecord(ev.e[2 * g + 1], st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int g = 0; g < 24; ++g) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev.e[2 * g], ev.e[2 * g + 1]));
+      class_ms[g] += ms;
+    }
   }
   return RSGDF_OK;
 }
 
 }  // namespace
+
+// Batch of cells: the SR work items of all cells are merged into one launch
+// per angular-momentum class (a cost-sorted (cell, item) queue drained by the
+// hardware dispatcher); reduce, fold and the long-range part follow per cell.
+// The whole device sequence is captured once into a graph and replayed.
+struct rsgdf_batch {
+  std::vector<std::unique_ptr<Job>> jobs;
+  DBuf d_prm, d_work, d_cnt;
+  std::vector<int> cls_off;                   // [25] merged work offsets per class
+  std::vector<double> cls_cost;               // [24]
+  std::vector<std::pair<int, int64_t>> from;  // merged item -> (job, local item)
+  hipStream_t st = nullptr;      // the caller's stream: uploads and replays
+  hipStream_t cap = nullptr;     // library stream the sequence is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  EventSet evs;
+  ~rsgdf_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+int batch_capture(rsgdf_batch &B) {
+  // the caller's stream may be the null stream, which cannot be captured
+  HIPCHK(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+  hipStream_t st = B.cap;
+  std::vector<hipStream_t> ss;
+  int rc = side_streams(ss);
+  if (rc) return rc;
+  if ((rc = B.evs.make(5, hipEventDisableTiming))) return rc;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  auto body = [&]() -> int {
+    int r;
+    for (auto &j : B.jobs)
+      if ((r = j->enqueue_pre(st)) || (r = j->enqueue_zero(0, st))) return r;
+    HIPCHK(launch_zero(B.d_cnt.p, std::max<size_t>(B.from.size(), 1) * 4 * sizeof(long long), st));
+    HIPCHK(hipEventRecord(B.evs.e[0], st));
+    for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, B.evs.e[0], 0));
+    std::vector<int> order(24);
+    for (int g = 0; g < 24; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return B.cls_cost[x] > B.cls_cost[y]; });
+    int k = 0;
+    for (int g : order) {
+      const int w0 = B.cls_off[g], w1 = B.cls_off[g + 1];
+      if (w1 == w0) continue;
+      HIPCHK(launch_sr3c(g / 6, g % 6, B.d_prm.as<SRParams>(), B.d_work.as<SRWork>(), B.d_cnt.as<long long>(), w0,
+                         w1 - w0, ss[k % ss.size()]));
+      ++k;
+    }
+    for (size_t i = 0; i < ss.size(); ++i) {
+      HIPCHK(hipEventRecord(B.evs.e[1 + i], ss[i]));
+      HIPCHK(hipStreamWaitEvent(st, B.evs.e[1 + i], 0));
+    }
+    for (auto &j : B.jobs)
+      if ((r = j->enqueue_reduce(0, st)) || (r = j->enqueue_fold(0, st)) || (r = j->enqueue_lr(st, nullptr))) return r;
+    return RSGDF_OK;
+  };
+  rc = body();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(RSGDF_EHIP, std::string("HIP error: ") + hipGetErrorString(e) + " at capture");
+  B.graph = g;
+  HIPCHK(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+  return RSGDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsgdf_batch_create(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis *bases, const rsgdf_basis *auxes,
+                       const int32_t (*kmeshes)[3], double omega, double thresh, const rsgdf_options *opt,
+                       rsgdf_out *outs, rsgdf_batch **batch) {
+  g_err.clear();
+  if (!batch) return fail(RSGDF_EINVAL, "null batch handle");
+  *batch = nullptr;
+  if (ncell < 1 || !cells || !bases || !auxes || !kmeshes || !outs) return fail(RSGDF_EINVAL, "invalid batch arguments");
+  auto B = std::make_unique<rsgdf_batch>();
+  B->st = reinterpret_cast<hipStream_t>(outs[0].stream);
+  for (int i = 0; i < ncell; ++i) {
+    if (!outs[i].on_device) return fail(RSGDF_EINVAL, "batched outputs must be device memory");
+    if (outs[i].stream != outs[0].stream) return fail(RSGDF_EINVAL, "batched outputs must share one stream");
+    auto j = std::make_unique<Job>();
+    j->cell = &cells[i];
+    j->basis = &bases[i];
+    j->auxbasis = &auxes[i];
+    j->kmesh = kmeshes[i];
+    j->omega = omega;
+    j->thresh = thresh;
+    j->out = &outs[i];
+    j->o.g_thresh = -1.0;
+    j->o.parts = RSGDF_PART_ALL;
+    if (opt) j->o = *opt;
+    // all cells' short-range scratch is resident at once (one merged launch),
+    // so a cell may take what is left; one needing more is built alone
+    int rc = j->prepare(B->st, 0.9);
+    if (rc) return fail(rc, "cell " + std::to_string(i) + ": " + g_err);
+    if (j->do_sr && j->nbatch != 1)
+      return fail(RSGDF_EUNSUPPORTED, "cell " + std::to_string(i) + " needs aux batching; build it alone");
+    B->jobs.push_back(std::move(j));
+  }
+  // merged SR queue: per class, all cells' items, heaviest first
+  std::vector<SRParams> prms;
+  std::vector<SRWork> work;
+  B->cls_off.assign(1, 0);
+  B->cls_cost.assign(24, 0.0);
+  for (size_t c = 0; c < B->jobs.size(); ++c) prms.push_back(B->jobs[c]->batch_params(0));
+  for (int g = 0; g < 24; ++g) {
+    for (size_t c = 0; c < B->jobs.size(); ++c) {
+      Job &j = *B->jobs[c];
+      if (!j.do_sr) continue;
+      for (int w = j.wgrp_off[g]; w < j.wgrp_off[g + 1]; ++w) {
+        SRWork x = j.work[w];
+        x.cell = (int32_t)c;
+        work.push_back(x);
+        B->from.push_back({(int)c, (int64_t)w});
+      }
+      B->cls_cost[g] += j.wgrp_cost[g];
+    }
+    B->cls_off.push_back((int)work.size());
+  }
+  HIPCHK(upload(B->d_prm, prms, B->st));
+  HIPCHK(upload(B->d_work, work, B->st));
+  HIPCHK(B->d_cnt.alloc(std::max<size_t>(work.size(), 1) * 4 * sizeof(long long)));
+  HIPCHK(hipStreamSynchronize(B->st));
+  int rc = batch_capture(*B);
+  if (rc) return rc;
+  *batch = B.release();
+  return RSGDF_OK;
+}
+
+int rsgdf_batch_run(rsgdf_batch *batch) {
+  g_err.clear();
+  if (!batch || !batch->exec) return fail(RSGDF_EINVAL, "invalid batch handle");
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipGraphLaunch(batch->exec, batch->st));
+  HIPCHK(hipStreamSynchronize(batch->st));
+  const double ms = ms_since(t0);
+  std::vector<long long> cnt(std::max<size_t>(batch->from.size(), 1) * 4);
+  HIPCHK(hipMemcpy(cnt.data(), batch->d_cnt.p, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  std::vector<std::vector<long long>> per(batch->jobs.size());
+  for (size_t c = 0; c < batch->jobs.size(); ++c) per[c].assign((size_t)batch->jobs[c]->nwork * 4 + 4, 0);
+  for (size_t m = 0; m < batch->from.size(); ++m)
+    for (int q = 0; q < 4; ++q) per[batch->from[m].first][(size_t)batch->from[m].second * 4 + q] = cnt[m * 4 + q];
+  for (size_t c = 0; c < batch->jobs.size(); ++c) {
+    Job &j = *batch->jobs[c];
+    int rc = j.finish(batch->st, per[c].data());
+    if (rc) return rc;
+    if (j.out->stats) j.out->stats->t_total_ms = ms;  // the whole batch
+  }
+  return RSGDF_OK;
+}
+
+void rsgdf_batch_destroy(rsgdf_batch *batch) { delete batch; }
+
+int rsgdf_build_j3c_batch(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis *bases, const rsgdf_basis *auxes,
+                          const int32_t (*kmeshes)[3], double omega, double thresh, const rsgdf_options *opt,
+                          rsgdf_out *outs) {
+  rsgdf_batch *b = nullptr;
+  int rc = rsgdf_batch_create(ncell, cells, bases, auxes, kmeshes, omega, thresh, opt, outs, &b);
+  if (rc) return rc;
+  rc = rsgdf_batch_run(b);
+  rsgdf_batch_destroy(b);
+  return rc;
+}
+
+int rsgdf_autotune_sr(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                      const int32_t kmesh[3], double omega, double thresh, float *split, double *class_ms,
+                      void *stream) {
+  g_err.clear();
+  if (!split) return fail(RSGDF_EINVAL, "null split table");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  static const float cand[5] = {0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
+  double best[24];
+  for (int g = 0; g < 24; ++g) {
+    best[g] = 1e300;
+    split[g] = 1.0f;
+  }
+  for (float f : cand) {
+    double ms[24];
+    int rc = tune_trial(cell, basis, auxbasis, kmesh, omega, thresh, f, st, ms);
+    if (rc) return rc;
+    for (int g = 0; g < 24; ++g)
+      if (ms[g] < best[g]) {
+        best[g] = ms[g];
+        split[g] = f;
+      }
+  }
+  if (class_ms)
+    for (int g = 0; g < 24; ++g) class_ms[g] = best[g];
+  return RSGDF_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -180,4 +180,24 @@ hipError_t launch_overlaps(const OvlParams &op, const SmnParams &sp, hipStream_t
   return hipGetLastError();
 }
 
+// Zero fill with a kernel (no memset node, so the sequence can be captured
+// into a graph and replayed): 16-byte stores, then the byte tail.
+__global__ void zero_kernel(uint4 *__restrict__ p, size_t n16, unsigned char *__restrict__ tail, int ntail) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t j = i; j < n16; j += stride) p[j] = make_uint4(0u, 0u, 0u, 0u);
+  if (i < (size_t)ntail) tail[i] = 0;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
+  if (bytes == 0 || !p) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const int ntail = (int)(bytes - n16 * 16);
+  size_t blocks = (n16 + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks);
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, reinterpret_cast<uint4 *>(p), n16,
+                     reinterpret_cast<unsigned char *>(p) + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
 }  // namespace rsgdf

@@ -81,7 +81,9 @@ struct LRGemmParams {
 int pair_class(int la, int lb);
 int sr_term_flops(int L);
 int sr_cells_per_wave(int nblk);
-hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int w0, int nwork, hipStream_t stream);
+hipError_t launch_sr3c(int lP, int pc, const SRParams *prms, const SRWork *works, long long *counts, int w0,
+                       int nwork, hipStream_t stream);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
 hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int ngroups, int64_t nelem,
                             hipStream_t stream);
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream);

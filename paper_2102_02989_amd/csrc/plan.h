@@ -53,15 +53,15 @@ struct Triplet {
   double amp;        // 1s-model amplitude A of Eq. S4 (primitive amplitudes summed)
 };
 
-// One wavefront's share of a work item: BvK cells c1 in [cb0, cb0 + ncb) and
-// pair images with list index = slice (mod nslice).  part >= 0: the wave
+// One wavefront's share of a work item of cell `cell`: BvK cells c1 in
+// [cb0, cb0 + ncb) and pair images with list index = slice (mod nslice).  part >= 0: the wave
 // writes its sums to a private partial block [ncb][Nk][nblk] at that offset
 // (summed into X afterwards in a fixed order); part < 0: it adds into X.
 struct SRWork {
   int32_t trip;
   int16_t cb0, ncb;
   int16_t slice, nslice;
-  int32_t pad;
+  int32_t cell;      // index into the per-cell parameter table of the launch
   int64_t part;
 };
 
@@ -93,7 +93,6 @@ struct SRParams {
   const int32_t *nsr;       // per pair: Nk counts
   const double *img;        // image vectors, 3 doubles each
   const Triplet *trip;
-  const SRWork *work;
   double *part;             // partial blocks of split work items
   Lattice lat;
   double omega, eps, dR;
@@ -101,7 +100,6 @@ struct SRParams {
   const double *boys;       // [L = 0..kMaxL][kBoysIntervals][kBoysPolyDeg + 1]
   double *X;                // [Nk][Nk][naux_b][nao][nao]
   int32_t aux_f0, naux_b, nao, pad;
-  long long *counts;        // [work entry][4]: primitive terms, contractions, shell terms, 0
   // learned screening: candidate (triplet, pair image ii) has index cand_off[trip] + ii
   const int64_t *cand_off;  // [ntrip] (null when neither mask nor logmag is used)
   const uint8_t *mask;      // keep flag per candidate, or null (rigorous screening only)

@@ -134,7 +134,8 @@ __host__ __device__ constexpr int sr_waves(int L) { return L >= 4 ? 1 : 2; }
 
 template <int LP, int LA, int LB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sr_waves(LP + LA + LB))))
-void sr3c_kernel(const SRParams prm, const int w0) {
+void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ works, long long *__restrict__ counts,
+                 const int w0) {
   constexpr int NCP = ncart(LP), NCA = ncart(LA), NCB = ncart(LB);
   constexpr int NBLK = NCP * NCA * NCB;
   constexpr int LAB = LA + LB, L = LAB + LP;
@@ -152,7 +153,8 @@ void sr3c_kernel(const SRParams prm, const int w0) {
   __shared__ double s_EP[(LP + 1) * (LP + 1)];
 
   const int lane = threadIdx.x;
-  const SRWork wk = prm.work[w0 + blockIdx.x];
+  const SRWork wk = works[w0 + blockIdx.x];
+  const SRParams &prm = prms[wk.cell];
   const int S = wk.nslice;
   const int slice = wk.slice;
   const Triplet tr = prm.trip[wk.trip];
@@ -515,7 +517,7 @@ void sr3c_kernel(const SRParams prm, const int w0) {
     n_shell += __shfl_xor(n_shell, off, 64);
   }
   if (lane == 0) {
-    long long *dst = prm.counts + 4 * ((size_t)w0 + blockIdx.x);
+    long long *dst = counts + 4 * ((size_t)w0 + blockIdx.x);
     dst[0] = n_terms;
     dst[1] = n_contr;
     dst[2] = n_shell;
@@ -573,7 +575,7 @@ hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int 
   return hipGetLastError();
 }
 
-typedef void (*sr_kernel_t)(const SRParams, const int);
+typedef void (*sr_kernel_t)(const SRParams *, const SRWork *, long long *, const int);
 
 #define RSGDF_SR_ENTRY(LP, LA, LB) &sr3c_kernel<LP, LA, LB>
 static const sr_kernel_t kSRTable[4][6] = {
@@ -593,9 +595,10 @@ int pair_class(int la, int lb) {
   return t[la][lb];
 }
 
-hipError_t launch_sr3c(int lP, int pc, const SRParams &prm, int w0, int nwork, hipStream_t stream) {
+hipError_t launch_sr3c(int lP, int pc, const SRParams *prms, const SRWork *works, long long *counts, int w0,
+                       int nwork, hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kSRTable[lP][pc], dim3((unsigned)nwork), dim3(64), 0, stream, prm, w0);
+  hipLaunchKernelGGL(kSRTable[lP][pc], dim3((unsigned)nwork), dim3(64), 0, stream, prms, works, counts, w0);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ class BasisT(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("g_thresh", ctypes.c_double), ("lr_precision", ctypes.c_int32), ("screening", ctypes.c_int32),
                 ("parts", ctypes.c_int32), ("sr_slices", ctypes.c_int32), ("mlp_weights", ctypes.c_void_p),
-                ("mlp_margin", ctypes.c_double)]
+                ("mlp_margin", ctypes.c_double), ("sr_split", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -109,6 +109,19 @@ def library():
         L.rsgdf_mlp_predict.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P]
         L.rsgdf_mlp_margin.restype = ctypes.c_int
         L.rsgdf_mlp_margin.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_double), P]
+        L.rsgdf_batch_create.restype = ctypes.c_int
+        L.rsgdf_batch_create.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(Options), P, ctypes.POINTER(ctypes.c_void_p)]
+        L.rsgdf_batch_run.restype = ctypes.c_int
+        L.rsgdf_batch_run.argtypes = [ctypes.c_void_p]
+        L.rsgdf_batch_destroy.restype = None
+        L.rsgdf_batch_destroy.argtypes = [ctypes.c_void_p]
+        L.rsgdf_build_j3c_batch.restype = ctypes.c_int
+        L.rsgdf_build_j3c_batch.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                            ctypes.POINTER(Options), P]
+        L.rsgdf_autotune_sr.restype = ctypes.c_int
+        L.rsgdf_autotune_sr.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                        ctypes.c_double, ctypes.c_double, P, P, P]
         L.rsgdf_last_error.restype = ctypes.c_char_p
         L.rsgdf_version.restype = ctypes.c_char_p
         _lib = L
@@ -160,9 +173,18 @@ def nkpairs(kmesh) -> int:
     return nk * (nk + 1) // 2
 
 
+def _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep):
+    w = None if mlp_weights is None else _f32(mlp_weights, MLP_NPARAM)
+    sp = None if sr_split is None else _f32(sr_split, 24)
+    keep += [w, sp]
+    return Options(-1.0 if g_thresh is None else float(g_thresh), int(lr_precision), int(screening), int(parts),
+                   int(sr_slices), None if w is None else w.ctypes.data, float(mlp_margin),
+                   None if sp is None else sp.ctypes.data)
+
+
 def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None, lr_precision=FP64,
               screening=SCREEN_RIGOROUS, parts=PART_ALL, sr_slices=0, mlp_weights=None, mlp_margin=0.0,
-              stream=None):
+              sr_split=None, stream=None):
     """Run rsgdf_build_j3c_ex.
 
     ``out``: a contiguous complex128 torch tensor on the GPU of shape
@@ -193,9 +215,8 @@ def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None
         sptr = stream.cuda_stream
     stats = Stats()
     o = Out(ptr, cap, int(on_device), sptr, 0, 0, 0, ctypes.pointer(stats))
-    w = None if mlp_weights is None else _f32(mlp_weights, MLP_NPARAM)
-    opts = Options(-1.0 if g_thresh is None else float(g_thresh), int(lr_precision), int(screening), int(parts),
-                   int(sr_slices), None if w is None else w.ctypes.data, float(mlp_margin))
+    keep = []
+    opts = _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep)
     rc = library().rsgdf_build_j3c_ex(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
                                       m.kmesh.ctypes.data, float(omega), float(thresh), ctypes.byref(opts),
                                       ctypes.byref(o))
@@ -276,3 +297,68 @@ def mlp_margin(params, X, y, *, quantile=1.0, stream=None):
     _check(library().rsgdf_mlp_margin(p.ctypes.data, X.ctypes.data, y.ctypes.data, len(y), float(quantile),
                                       ctypes.byref(m), _stream_ptr(stream)))
     return m.value
+
+
+# ---- batches and the work-split autotuner ------------------------------------
+
+class Batch:
+    """rsgdf_batch_create / run / destroy over a list of (cell, basis, aux,
+    kmesh) with one shared omega, thresh and option set; outputs are device
+    tensors allocated here (or passed in ``outs``).  ``run()`` replays the
+    captured graph and returns the per-cell stats."""
+
+    def __init__(self, systems, omega, thresh, *, outs=None, g_thresh=None, lr_precision=FP64,
+                 screening=SCREEN_RIGOROUS, mlp_weights=None, mlp_margin=0.0, sr_split=None, stream=None):
+        import torch
+        self._keep = []
+        n = len(systems)
+        ms = [_Marshal(*s) for s in systems]
+        self._keep.append(ms)
+        self.cells = (Cell * n)(*[m.cell for m in ms])
+        self.bases = (BasisT * n)(*[m.basis for m in ms])
+        self.auxes = (BasisT * n)(*[m.aux for m in ms])
+        km = np.ascontiguousarray([list(s[3]) for s in systems], np.int32).reshape(n, 3)
+        self._keep.append(km)
+        if outs is None:
+            outs = [torch.empty((nkpairs(s[3]), s[2].nfunc, s[1].nfunc, s[1].nfunc), dtype=torch.complex128,
+                                device="cuda") for s in systems]
+        self.outs = outs
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stats = [Stats() for _ in range(n)]
+        self.o = (Out * n)(*[Out(t.data_ptr(), t.numel() * 16, 1, stream.cuda_stream, 0, 0, 0,
+                                 ctypes.pointer(self.stats[i])) for i, t in enumerate(outs)])
+        self.opts = _options(g_thresh, lr_precision, screening, PART_ALL, 0, mlp_weights, mlp_margin, sr_split,
+                             self._keep)
+        h = ctypes.c_void_p(None)
+        _check(library().rsgdf_batch_create(n, ctypes.addressof(self.cells), ctypes.addressof(self.bases),
+                                            ctypes.addressof(self.auxes), km.ctypes.data, float(omega),
+                                            float(thresh), ctypes.byref(self.opts), ctypes.addressof(self.o),
+                                            ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        _check(library().rsgdf_batch_run(self._h))
+        return [s.as_dict() for s in self.stats]
+
+    def close(self):
+        if self._h:
+            library().rsgdf_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_sr(cell, basis, aux, kmesh, omega, thresh, *, stream=None):
+    """rsgdf_autotune_sr: (split factors [24] float32, class times ms [24])."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    split = np.ones(24, np.float32)
+    ms = np.zeros(24, np.float64)
+    _check(library().rsgdf_autotune_sr(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                       m.kmesh.ctypes.data, float(omega), float(thresh), split.ctypes.data,
+                                       ms.ctypes.data, _stream_ptr(stream)))
+    return split, ms
