@@ -40,6 +40,37 @@ constexpr int kCandCap = 1536;    // lattice-vector candidates held in LDS per w
 constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators in LDS
 constexpr int kSRWinCap = 256;    // screening windows held in LDS
 constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
+constexpr int kTripCap = 40;         // primitive triples whose constants are held in LDS
+constexpr int kTripC = 10;           // constants per primitive triple
+
+// Constants of a primitive triple (AO a, AO b, aux c) that do not depend on
+// the pair image: t[0] 1/p, t[1] g_b/p (P = A + t[1] (B - A)), t[2] g_a g_b/p
+// (K_ab = e^{-t[2] R12^2}), t[3] rho, t[4] theta^2, t[5] theta, t[6] the
+// signed contraction prefactor c_c c_a c_b 2 pi^{5/2}/(p g_c sqrt(p + g_c)),
+// t[7] the 1s screening estimate per unit K_ab and lattice vector
+// (Eqs. S4-S9 with the erfc attenuation), t[8] 1/(2 g_c), t[9] unused.
+template <int LP>
+__device__ __forceinline__ void triple_consts(double ga, double gb, double gc, double ca, double cb, double cc,
+                                              double ca1, double cb1, double cc1, double omega, double *t) {
+  const double p = ga + gb, oop = 1.0 / p;
+  const double rpc = 1.0 / (p + gc);
+  const double rho = p * gc * rpc;
+  const double om2 = omega * omega;
+  const double th2 = om2 / (om2 + rho);
+  const double e1 = sqrt(rho);
+  const double e2 = 1.0 / sqrt(1.0 / rho + 1.0 / om2);
+  t[0] = oop;
+  t[1] = gb * oop;
+  t[2] = ga * gb * oop;
+  t[3] = rho;
+  t[4] = th2;
+  t[5] = sqrt(th2);
+  t[6] = ((LP & 1) ? -1.0 : 1.0) * cc * ca * cb * 2.0 * kPi * kPi * sqrt(kPi) * sqrt(rpc) / (p * gc);
+  t[7] = kPi * kPi * kPi * cc1 * ca1 * cb1 / (gc * p * sqrt(gc * p)) * 2.0 * (e1 - e2) *
+         0.564189583547756286948079451561;
+  t[8] = 0.5 / gc;
+  t[9] = 0.0;
+}
 
 // cells per wave for which the Cartesian accumulators of a class fit in LDS
 __host__ __device__ constexpr int sr_max_cells(int nblk) {
@@ -78,14 +109,21 @@ __device__ __forceinline__ void cart_decode(int l, int i, int &x, int &y, int &z
 // F_L(T) for 0 <= T < kBoysSwitch from the per-L polynomial table (Taylor
 // expansion of degree kBoysPolyDeg about each unit interval's centre), then the
 // downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1).
+// The polynomial is evaluated by Estrin's scheme (pairs, then powers u^2,
+// u^4, u^8): dependency depth 5 instead of 12 for Horner's rule, which is what
+// bounds this loop at one or two wavefronts per SIMD.
+static_assert(kBoysPolyDeg == 12, "Estrin evaluation below is written for degree 12");
 template <int L>
 __device__ __forceinline__ void boys_poly(double T, const double *__restrict__ tab, double (&F)[L + 1]) {
   const int i = (int)T;
   const double u = T - (i + 0.5);
   const double *c = tab + i * (kBoysPolyDeg + 1);
-  double s = c[kBoysPolyDeg];
-#pragma unroll
-  for (int j = kBoysPolyDeg - 1; j >= 0; --j) s = fma(s, u, c[j]);
+  const double u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
+  const double a0 = fma(c[1], u, c[0]), a1 = fma(c[3], u, c[2]), a2 = fma(c[5], u, c[4]);
+  const double a3 = fma(c[7], u, c[6]), a4 = fma(c[9], u, c[8]), a5 = fma(c[11], u, c[10]);
+  const double b0 = fma(a1, u2, a0), b1 = fma(a3, u2, a2), b2 = fma(a5, u2, a4);
+  const double d0 = fma(b1, u4, b0), d1 = fma(c[12], u4, b2);
+  const double s = fma(d1, u8, d0);
   F[L] = s;
   if (L > 0) {
     const double e = exp(-T);
@@ -151,6 +189,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   __shared__ double s_W[NCP * NHAB];
   __shared__ double s_E[3 * EA];
   __shared__ double s_EP[(LP + 1) * (LP + 1)];
+  __shared__ double s_tc[kTripCap * kTripC];
 
   const int lane = threadIdx.x;
   const SRWork wk = works[w0 + blockIdx.x];
@@ -170,6 +209,17 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   // ---- per-item tables in LDS: Boys polynomials of order L, screening windows
   for (int i = lane; i < kBoysIntervals * (kBoysPolyDeg + 1); i += 64)
     s_boys[i] = prm.boys[L * kBoysIntervals * (kBoysPolyDeg + 1) + i];
+  const int nta = shA.nprim, ntb = shB.nprim, ntcp = shP.nprim;
+  const int ntrip_p = nta * ntb * ntcp;
+  const bool tc_lds = ntrip_p <= kTripCap;
+  if (tc_lds)
+    for (int t = lane; t < ntrip_p; t += 64) {
+      const int kc = t % ntcp, kab = t / ntcp, kb = kab % ntb, ka = kab / ntb;
+      triple_consts<LP>(prm.ao_exp[shA.pptr + ka], prm.ao_exp[shB.pptr + kb], prm.ax_exp[shP.pptr + kc],
+                        prm.ao_coef[shA.pptr + ka], prm.ao_coef[shB.pptr + kb], prm.ax_coef[shP.pptr + kc],
+                        prm.ao_c1s[shA.pptr + ka], prm.ao_c1s[shB.pptr + kb], prm.ax_c1s[shP.pptr + kc], prm.omega,
+                        s_tc + t * kTripC);
+    }
   const double pd = shA.a_d + shB.a_d;
   const double beta = shA.a_d * shB.a_d / pd;
   const double eta1 = sqrt(shP.a_d * pd / (shP.a_d + pd));
@@ -341,34 +391,37 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
         const int total = cnt;
         const int navail = min(max(total - base, 0), capb);
         if (pass == 0 && lig == 0 && grp_on) n_shell += total;
+        // groups (bit gl * gs) holding lattice vectors in this pass; empty ones
+        // contribute nothing and skip their contraction
+        const unsigned long long gnz = __ballot(grp_on && lig == 0 && navail > 0);
         __syncthreads();
 
-        // ---- primitive pairs: image-summed Hermite integrals, then contraction
-        for (int ka = 0; ka < shA.nprim; ++ka) {
-          const double ga = prm.ao_exp[shA.pptr + ka], ca = prm.ao_coef[shA.pptr + ka];
-          const double ca1 = prm.ao_c1s[shA.pptr + ka];
-          for (int kb = 0; kb < shB.nprim; ++kb) {
-            const double gb = prm.ao_exp[shB.pptr + kb], cb = prm.ao_coef[shB.pptr + kb];
-            const double cb1 = prm.ao_c1s[shB.pptr + kb];
-            const double p = ga + gb, oop = 1.0 / p;
-            const double Kab = exp(-ga * gb * oop * r12sq);
-            const double Px = (ga * Ax + gb * Bx) * oop, Py = (ga * Ay + gb * By) * oop, Pz = (ga * Az + gb * Bz) * oop;
-            // offset of this primitive pair's centre from the aux centre at m = 0
-            const double dPx = Px - Pdx + X0x, dPy = Py - Pdy + X0y, dPz = Pz - Pdz + X0z;
-            for (int kc = 0; kc < shP.nprim; ++kc) {
-              const double gc = prm.ax_exp[shP.pptr + kc], cc = prm.ax_coef[shP.pptr + kc];
-              const double cc1 = prm.ax_c1s[shP.pptr + kc];
-              // primitive screen: image-summed 1s estimate for this n' far below
-              // the target precision
-              const double e1 = sqrt(gc * p / (gc + p));
-              const double e2 = 1.0 / sqrt(1.0 / (e1 * e1) + 1.0 / (omega * omega));
-              const double nm = 4.18879020478639098 * rmax2 * rmax / lat.vol + 1.0;
-              const double est = kPi * kPi * kPi * cc1 * ca1 * cb1 / (gc * p * sqrt(gc * p)) * Kab * 2.0 * (e1 - e2) *
-                                 0.564189583547756286948079451561 * nm;
-              if (est < 1e-4 * eps) continue;
-              const double rho = p * gc / (p + gc);
-              const double th2 = omega * omega / (omega * omega + rho);
-              const double th = sqrt(th2);
+        // ---- primitive triples: image-summed Hermite integrals, then contraction
+        const double nm = 4.18879020478639098 * rmax2 * rmax / lat.vol + 1.0;
+        for (int tt = 0; tt < (gnz ? ntrip_p : 0); ++tt) {
+          double tcl[kTripC];
+          if (tc_lds) {
+#pragma unroll
+            for (int q = 0; q < kTripC; ++q) tcl[q] = s_tc[tt * kTripC + q];
+          } else {
+            const int kc = tt % ntcp, kab = tt / ntcp, kb = kab % ntb, ka = kab / ntb;
+            triple_consts<LP>(prm.ao_exp[shA.pptr + ka], prm.ao_exp[shB.pptr + kb], prm.ax_exp[shP.pptr + kc],
+                              prm.ao_coef[shA.pptr + ka], prm.ao_coef[shB.pptr + kb], prm.ax_coef[shP.pptr + kc],
+                              prm.ao_c1s[shA.pptr + ka], prm.ao_c1s[shB.pptr + kb], prm.ax_c1s[shP.pptr + kc],
+                              omega, tcl);
+          }
+          const double oop = tcl[0];
+          const double Kab = exp(-tcl[2] * r12sq);
+          // primitive screen: image-summed 1s estimate for this n' far below
+          // the target precision
+          if (tcl[7] * Kab * nm < 1e-4 * eps) continue;
+          const double Px = Ax + tcl[1] * (Bx - Ax), Py = Ay + tcl[1] * (By - Ay), Pz = Az + tcl[1] * (Bz - Az);
+          // offset of this primitive pair's centre from the aux centre at m = 0
+          const double dPx = Px - Pdx + X0x, dPy = Py - Pdy + X0y, dPz = Pz - Pdz + X0z;
+          {
+              const double rho = tcl[3];
+              const double th2 = tcl[4];
+              const double th = tcl[5];
               const double m2rho = -2.0 * rho;
               double Rb[NH];
 #pragma unroll
@@ -416,16 +469,16 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                     for (int t = 0; t <= LAB; ++t) s_E[lane * EA + (i * (LB + 1) + j) * (LAB + 1) + t] = E1[i][j][t];
               } else if (lane == 3) {
                 double E2[LP + 1][LP + 1];
-                hermite_E1<LP>(0.5 / gc, E2);
+                hermite_E1<LP>(tcl[8], E2);
 #pragma unroll
                 for (int i = 0; i <= LP; ++i)
 #pragma unroll
                   for (int t = 0; t <= LP; ++t) s_EP[i * (LP + 1) + t] = E2[i][t];
               }
               __syncthreads();
-              const double pref = 2.0 * kPi * kPi * sqrt(kPi) / (p * gc * sqrt(p + gc));
-              const double coef = ((LP & 1) ? -1.0 : 1.0) * cc * ca * cb * Kab * pref;
+              const double coef = tcl[6] * Kab;
               for (int g = 0; g < ngrp; ++g) {
+                if (!((gnz >> (g * gs)) & 1ull)) continue;  // uniform over the wave
                 // W[ic][h] = sum_{tau nu phi} E^c R_{h + (tau nu phi)}
                 for (int idx = lane; idx < NCP * NHAB; idx += 64) {
                   const int ic = idx / NHAB, h = idx - (idx / NHAB) * NHAB;
@@ -482,7 +535,6 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 __syncthreads();
               }
               ++n_contr;
-            }
           }
         }
         // more candidates than one pass holds?
