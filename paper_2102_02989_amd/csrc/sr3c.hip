@@ -185,8 +185,13 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
   __shared__ int s_cand[kCandCap];
   __shared__ double s_blk[BLK];
-  __shared__ double s_R[kMaxCellsPerWave * NH];
+  // one group's image-summed R_tuv in a zero-padded cube, so that every read
+  // of the aux contraction is a base plus a compile-time offset
+  constexpr int D = L + 2;
+  __shared__ double s_R3[D * D * D];
   __shared__ double s_W[NCP * NHAB];
+  __shared__ int s_wtab[NCP * NHAB];  // W entry (ic, h): cube base | cx << 16 | cy << 18 | cz << 20
+  __shared__ int s_ctab[NBLK];        // component: ic | (ax,bx) << 8 | (ay,by) << 16 | (az,bz) << 24
   __shared__ double s_E[3 * EA];
   __shared__ double s_EP[(LP + 1) * (LP + 1)];
   __shared__ double s_tc[kTripCap * kTripC];
@@ -237,6 +242,22 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
     }
   }
   for (int i = lane; i < BLK; i += 64) s_blk[i] = 0.0;
+  for (int i = lane; i < D * D * D; i += 64) s_R3[i] = 0.0;
+  for (int idx = lane; idx < NCP * NHAB; idx += 64) {
+    const int ic = idx / NHAB, h = idx % NHAB;
+    int t, u, v, cx, cy, cz;
+    herm_decode(h, t, u, v);
+    cart_decode(LP, ic, cx, cy, cz);
+    const int base = (t + (cx & 1)) * D * D + (u + (cy & 1)) * D + (v + (cz & 1));
+    s_wtab[idx] = base | (cx << 16) | (cy << 18) | (cz << 20);
+  }
+  for (int comp = lane; comp < NBLK; comp += 64) {
+    const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
+    int ax_, ay_, az_, bx_, by_, bz_;
+    cart_decode(LA, ia, ax_, ay_, az_);
+    cart_decode(LB, ib, bx_, by_, bz_);
+    s_ctab[comp] = ic | ((ax_ * (LB + 1) + bx_) << 8) | ((ay_ * (LB + 1) + by_) << 16) | ((az_ * (LB + 1) + bz_) << 24);
+  }
   __syncthreads();
   const bool logging = prm.logmag != nullptr;
   const int64_t cbase = (prm.mask || logging) ? prm.cand_off[wk.trip] : 0;
@@ -449,13 +470,9 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
 #pragma unroll
                 for (int i = 0; i < NH; ++i) Rb[i] += __shfl_xor(Rb[i], off, 64);
               }
-              // ---- contraction with the Hermite expansion coefficients: the
-              // group sums go to LDS and the whole wave contracts one group at
-              // a time, output components spread over the 64 lanes.
-              if (lig == 0 && grp_on) {
-#pragma unroll
-                for (int i = 0; i < NH; ++i) s_R[gl * NH + i] = Rb[i];
-              }
+              // ---- contraction with the Hermite expansion coefficients: one
+              // group at a time, its sums in the LDS cube, output components
+              // spread over the 64 lanes; every loop bound is compile-time
               if (lane < 3) {
                 double E1[LA + 1][LB + 1][LAB + 1];
                 const double PAd = (lane == 0) ? Px - Ax : (lane == 1 ? Py - Ay : Pz - Az);
@@ -475,22 +492,45 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
 #pragma unroll
                   for (int t = 0; t <= LP; ++t) s_EP[i * (LP + 1) + t] = E2[i][t];
               }
-              __syncthreads();
               const double coef = tcl[6] * Kab;
+              constexpr int KX = LP / 2;  // aux Hermite orders tau = (c & 1) + 2k, k <= KX
               for (int g = 0; g < ngrp; ++g) {
                 if (!((gnz >> (g * gs)) & 1ull)) continue;  // uniform over the wave
-                // W[ic][h] = sum_{tau nu phi} E^c R_{h + (tau nu phi)}
+                if (gl == g && lig == 0) {
+                  int h = 0;
+#pragma unroll
+                  for (int sh = 0; sh <= L; ++sh)
+#pragma unroll
+                    for (int r = 0; r <= sh; ++r)
+#pragma unroll
+                      for (int v = 0; v <= r; ++v) {
+                        s_R3[(sh - r) * D * D + (r - v) * D + v] = Rb[h];
+                        ++h;
+                      }
+                }
+                __syncthreads();
+                // W[ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R_{h + (tau nu phi)}
                 for (int idx = lane; idx < NCP * NHAB; idx += 64) {
-                  const int ic = idx / NHAB, h = idx - (idx / NHAB) * NHAB;
-                  int t, u, v, cx, cy, cz;
-                  herm_decode(h, t, u, v);
-                  cart_decode(LP, ic, cx, cy, cz);
+                  const int w = s_wtab[idx];
+                  const int base = w & 0xffff, cx = (w >> 16) & 3, cy = (w >> 18) & 3, cz = (w >> 20) & 3;
+                  double ex[KX + 1], ey[KX + 1], ez[KX + 1];
+#pragma unroll
+                  for (int k = 0; k <= KX; ++k) {
+                    const int tx = (cx & 1) + 2 * k, ty = (cy & 1) + 2 * k, tz = (cz & 1) + 2 * k;
+                    ex[k] = (tx <= cx) ? s_EP[cx * (LP + 1) + min(tx, LP)] : 0.0;
+                    ey[k] = (ty <= cy) ? s_EP[cy * (LP + 1) + min(ty, LP)] : 0.0;
+                    ez[k] = (tz <= cz) ? s_EP[cz * (LP + 1) + min(tz, LP)] : 0.0;
+                  }
                   double sw = 0.0;
-                  for (int tau = cx & 1; tau <= cx; tau += 2)
-                    for (int nu = cy & 1; nu <= cy; nu += 2)
-                      for (int phi = cz & 1; phi <= cz; phi += 2)
-                        sw += s_EP[cx * (LP + 1) + tau] * s_EP[cy * (LP + 1) + nu] * s_EP[cz * (LP + 1) + phi] *
-                              s_R[g * NH + hidx(t + tau, u + nu, v + phi)];
+#pragma unroll
+                  for (int kx = 0; kx <= KX; ++kx)
+#pragma unroll
+                    for (int ky = 0; ky <= KX; ++ky) {
+                      double sz = 0.0;
+#pragma unroll
+                      for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * s_R3[base + 2 * kx * D * D + 2 * ky * D + 2 * kz];
+                      sw += ex[kx] * ey[ky] * sz;
+                    }
                   s_W[idx] = sw;
                 }
                 __syncthreads();
@@ -505,28 +545,34 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   X21 = prm.X + (size_t)(c2 * nk + cg) * xplane;
                   if (part) pb = part + ((size_t)g * nk + c2) * NBLK;
                 }
+                // component (ic, ia, ib) = sum_{tuv} E^x_t E^y_u E^z_v W[ic][tuv]
                 for (int comp = lane; comp < NBLK; comp += 64) {
-                  const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
-                  int ax_, ay_, az_, bx_, by_, bz_, q0, q1, q2;
-                  cart_decode(LA, ia, ax_, ay_, az_);
-                  cart_decode(LB, ib, bx_, by_, bz_);
-                  (void)q0; (void)q1; (void)q2;
-                  const double *ex = s_E + 0 * EA + (ax_ * (LB + 1) + bx_) * (LAB + 1);
-                  const double *ey = s_E + 1 * EA + (ay_ * (LB + 1) + by_) * (LAB + 1);
-                  const double *ez = s_E + 2 * EA + (az_ * (LB + 1) + bz_) * (LAB + 1);
+                  const int c = s_ctab[comp];
+                  const int ic = c & 0xff;
+                  const double *ex = s_E + 0 * EA + ((c >> 8) & 0xff) * (LAB + 1);
+                  const double *ey = s_E + 1 * EA + ((c >> 16) & 0xff) * (LAB + 1);
+                  const double *ez = s_E + 2 * EA + ((c >> 24) & 0xff) * (LAB + 1);
                   const double *wr = s_W + ic * NHAB;
                   double so = 0.0;
-                  for (int t = 0; t <= ax_ + bx_; ++t)
-                    for (int u = 0; u <= ay_ + by_; ++u) {
-                      const double exy = ex[t] * ey[u];
-                      for (int v = 0; v <= az_ + bz_; ++v) so += exy * ez[v] * wr[hidx(t, u, v)];
+#pragma unroll
+                  for (int t = 0; t <= LAB; ++t) {
+                    double st = 0.0;
+#pragma unroll
+                    for (int u = 0; u <= LAB - t; ++u) {
+                      double su = 0.0;
+#pragma unroll
+                      for (int v = 0; v <= LAB - t - u; ++v) su += ez[v] * wr[hidx(t, u, v)];
+                      st += ey[u] * su;
                     }
+                    so += ex[t] * st;
+                  }
                   const double val = coef * so;
                   if (blk_in_lds) {
                     s_blk[g * NBLK + comp] += val;
                   } else if (pb) {
                     pb[comp] += val;
                   } else {
+                    const int ia = (comp / NCB) % NCA, ib = comp % NCB;
                     const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
                     X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += val;
                     if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
