@@ -188,7 +188,11 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   // one group's image-summed R_tuv in a zero-padded cube, so that every read
   // of the aux contraction is a base plus a compile-time offset
   constexpr int D = L + 2;
+  constexpr int CH = 8;  // Hermite entries per step of the group reduction
   __shared__ double s_R3[D * D * D];
+  __shared__ double s_T[64 * CH];                        // reduction scratch: lane x entry
+  __shared__ double s_R[sr_max_cells(NBLK) * NH];        // group sums (tetrahedral order)
+  __shared__ int s_hcube[NH];                            // tetrahedral index -> cube index
   __shared__ double s_W[NCP * NHAB];
   __shared__ int s_wtab[NCP * NHAB];  // W entry (ic, h): cube base | cx << 16 | cy << 18 | cz << 20
   __shared__ int s_ctab[NBLK];        // component: ic | (ax,bx) << 8 | (ay,by) << 16 | (az,bz) << 24
@@ -243,6 +247,11 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   }
   for (int i = lane; i < BLK; i += 64) s_blk[i] = 0.0;
   for (int i = lane; i < D * D * D; i += 64) s_R3[i] = 0.0;
+  for (int h = lane; h < NH; h += 64) {
+    int t, u, v;
+    herm_decode(h, t, u, v);
+    s_hcube[h] = t * D * D + u * D + v;
+  }
   for (int idx = lane; idx < NCP * NHAB; idx += 64) {
     const int ic = idx / NHAB, h = idx % NHAB;
     int t, u, v, cx, cy, cz;
@@ -465,10 +474,23 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 hermite_R_acc<L>(X, Y, Z, g, Rb);
                 ++n_terms;
               }
-              // group reduction (fixed xor butterfly: identical result on every lane)
-              for (int off = 1; off < gs; off <<= 1) {
+              // group reduction, transposed through LDS in chunks of CH entries:
+              // each entry of a group is summed by one lane over the group's gs
+              // lanes in lane order (deterministic), into s_R[group][h]
 #pragma unroll
-                for (int i = 0; i < NH; ++i) Rb[i] += __shfl_xor(Rb[i], off, 64);
+              for (int c0 = 0; c0 < NH; c0 += CH) {
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+                  if (c0 + j < NH) s_T[lane * CH + j] = Rb[c0 + j];
+                __syncthreads();
+                if (grp_on) {
+                  for (int j = lig; j < CH && c0 + j < NH; j += gs) {
+                    double acc = 0.0;
+                    for (int r = 0; r < gs; ++r) acc += s_T[(gl * gs + r) * CH + j];
+                    s_R[gl * NH + c0 + j] = acc;
+                  }
+                }
+                __syncthreads();
               }
               // ---- contraction with the Hermite expansion coefficients: one
               // group at a time, its sums in the LDS cube, output components
@@ -496,18 +518,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
               constexpr int KX = LP / 2;  // aux Hermite orders tau = (c & 1) + 2k, k <= KX
               for (int g = 0; g < ngrp; ++g) {
                 if (!((gnz >> (g * gs)) & 1ull)) continue;  // uniform over the wave
-                if (gl == g && lig == 0) {
-                  int h = 0;
-#pragma unroll
-                  for (int sh = 0; sh <= L; ++sh)
-#pragma unroll
-                    for (int r = 0; r <= sh; ++r)
-#pragma unroll
-                      for (int v = 0; v <= r; ++v) {
-                        s_R3[(sh - r) * D * D + (r - v) * D + v] = Rb[h];
-                        ++h;
-                      }
-                }
+                for (int h = lane; h < NH; h += 64) s_R3[s_hcube[h]] = s_R[g * NH + h];
                 __syncthreads();
                 // W[ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R_{h + (tau nu phi)}
                 for (int idx = lane; idx < NCP * NHAB; idx += 64) {
