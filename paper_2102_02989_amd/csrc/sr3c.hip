@@ -187,15 +187,20 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   __shared__ double s_blk[BLK];
   // one group's image-summed R_tuv in a zero-padded cube, so that every read
   // of the aux contraction is a base plus a compile-time offset
-  constexpr int D = L + 2;
-  constexpr int CH = 8;  // Hermite entries per step of the group reduction
-  __shared__ double s_R3[D * D * D];
-  __shared__ double s_T[64 * CH];                        // reduction scratch: lane x entry
-  __shared__ double s_R[sr_max_cells(NBLK) * NH];        // group sums (tetrahedral order)
-  __shared__ int s_hcube[NH];                            // tetrahedral index -> cube index
-  __shared__ double s_W[NCP * NHAB];
-  __shared__ int s_wtab[NCP * NHAB];  // W entry (ic, h): cube base | cx << 16 | cy << 18 | cz << 20
-  __shared__ int s_ctab[NBLK];        // component: ic | (ax,bx) << 8 | (ay,by) << 16 | (az,bz) << 24
+  // contraction of all lane groups at once: W[g][ic][h] from the group sums
+  // R[g][h'] through a table of Hermite indices (NH marks an invalid aux
+  // order and reads the zero slot), then the components from W
+  constexpr int CH = 8;                    // Hermite entries per step of the group reduction
+  constexpr int KX = LP / 2;               // aux Hermite orders tau = (c & 1) + 2k, k <= KX
+  constexpr int NK = (KX + 1) * (KX + 1) * (KX + 1);
+  constexpr int NW = NCP * NHAB;           // W entries per group
+  constexpr int MG = sr_max_cells(NBLK);   // groups per wave
+  __shared__ double s_T[64 * CH];          // reduction scratch: lane x entry
+  __shared__ double s_R[MG * (NH + 1)];    // group sums (tetrahedral order) + a zero slot
+  __shared__ double s_W[MG * NW];
+  __shared__ int s_wtab[NW];               // W entry (ic, h): cx | cy << 2 | cz << 4
+  __shared__ short s_widx[NW * NK];        // Hermite index of h + (tau nu phi), or NH
+  __shared__ int s_ctab[NBLK];             // component: ic | (ax,bx) << 8 | (ay,by) << 16 | (az,bz) << 24
   __shared__ double s_E[3 * EA];
   __shared__ double s_EP[(LP + 1) * (LP + 1)];
   __shared__ double s_tc[kTripCap * kTripC];
@@ -246,19 +251,18 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
     }
   }
   for (int i = lane; i < BLK; i += 64) s_blk[i] = 0.0;
-  for (int i = lane; i < D * D * D; i += 64) s_R3[i] = 0.0;
-  for (int h = lane; h < NH; h += 64) {
-    int t, u, v;
-    herm_decode(h, t, u, v);
-    s_hcube[h] = t * D * D + u * D + v;
-  }
-  for (int idx = lane; idx < NCP * NHAB; idx += 64) {
+  for (int i = lane; i < MG * (NH + 1); i += 64) s_R[i] = 0.0;
+  for (int idx = lane; idx < NW; idx += 64) {
     const int ic = idx / NHAB, h = idx % NHAB;
     int t, u, v, cx, cy, cz;
     herm_decode(h, t, u, v);
     cart_decode(LP, ic, cx, cy, cz);
-    const int base = (t + (cx & 1)) * D * D + (u + (cy & 1)) * D + (v + (cz & 1));
-    s_wtab[idx] = base | (cx << 16) | (cy << 18) | (cz << 20);
+    s_wtab[idx] = cx | (cy << 2) | (cz << 4);
+    for (int k = 0; k < NK; ++k) {
+      const int kx = k / ((KX + 1) * (KX + 1)), ky = (k / (KX + 1)) % (KX + 1), kz = k % (KX + 1);
+      const int tx = (cx & 1) + 2 * kx, ty = (cy & 1) + 2 * ky, tz = (cz & 1) + 2 * kz;
+      s_widx[idx * NK + k] = (tx <= cx && ty <= cy && tz <= cz) ? (short)hidx(t + tx, u + ty, v + tz) : (short)NH;
+    }
   }
   for (int comp = lane; comp < NBLK; comp += 64) {
     const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
@@ -487,7 +491,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   for (int j = lig; j < CH && c0 + j < NH; j += gs) {
                     double acc = 0.0;
                     for (int r = 0; r < gs; ++r) acc += s_T[(gl * gs + r) * CH + j];
-                    s_R[gl * NH + c0 + j] = acc;
+                    s_R[gl * (NH + 1) + c0 + j] = acc;
                   }
                 }
                 __syncthreads();
@@ -515,82 +519,80 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   for (int t = 0; t <= LP; ++t) s_EP[i * (LP + 1) + t] = E2[i][t];
               }
               const double coef = tcl[6] * Kab;
-              constexpr int KX = LP / 2;  // aux Hermite orders tau = (c & 1) + 2k, k <= KX
-              for (int g = 0; g < ngrp; ++g) {
-                if (!((gnz >> (g * gs)) & 1ull)) continue;  // uniform over the wave
-                for (int h = lane; h < NH; h += 64) s_R3[s_hcube[h]] = s_R[g * NH + h];
-                __syncthreads();
-                // W[ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R_{h + (tau nu phi)}
-                for (int idx = lane; idx < NCP * NHAB; idx += 64) {
-                  const int w = s_wtab[idx];
-                  const int base = w & 0xffff, cx = (w >> 16) & 3, cy = (w >> 18) & 3, cz = (w >> 20) & 3;
-                  double ex[KX + 1], ey[KX + 1], ez[KX + 1];
+              __syncthreads();  // E coefficients and group sums visible to every lane
+              // W[g][ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R[g][h + (tau nu phi)]
+              for (int e = lane; e < ngrp * NW; e += 64) {
+                const int g = e / NW, idx = e - g * NW;
+                if (!((gnz >> (g * gs)) & 1ull)) continue;
+                const int w = s_wtab[idx];
+                const int cx = w & 3, cy = (w >> 2) & 3, cz = (w >> 4) & 3;
+                double ex[KX + 1], ey[KX + 1], ez[KX + 1];
 #pragma unroll
-                  for (int k = 0; k <= KX; ++k) {
-                    const int tx = (cx & 1) + 2 * k, ty = (cy & 1) + 2 * k, tz = (cz & 1) + 2 * k;
-                    ex[k] = (tx <= cx) ? s_EP[cx * (LP + 1) + min(tx, LP)] : 0.0;
-                    ey[k] = (ty <= cy) ? s_EP[cy * (LP + 1) + min(ty, LP)] : 0.0;
-                    ez[k] = (tz <= cz) ? s_EP[cz * (LP + 1) + min(tz, LP)] : 0.0;
-                  }
-                  double sw = 0.0;
-#pragma unroll
-                  for (int kx = 0; kx <= KX; ++kx)
-#pragma unroll
-                    for (int ky = 0; ky <= KX; ++ky) {
-                      double sz = 0.0;
-#pragma unroll
-                      for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * s_R3[base + 2 * kx * D * D + 2 * ky * D + 2 * kz];
-                      sw += ex[kx] * ey[ky] * sz;
-                    }
-                  s_W[idx] = sw;
+                for (int k = 0; k <= KX; ++k) {
+                  const int tx = (cx & 1) + 2 * k, ty = (cy & 1) + 2 * k, tz = (cz & 1) + 2 * k;
+                  ex[k] = (tx <= cx) ? s_EP[cx * (LP + 1) + min(tx, LP)] : 0.0;
+                  ey[k] = (ty <= cy) ? s_EP[cy * (LP + 1) + min(ty, LP)] : 0.0;
+                  ez[k] = (tz <= cz) ? s_EP[cz * (LP + 1) + min(tz, LP)] : 0.0;
                 }
-                __syncthreads();
-                double *X12 = nullptr, *X21 = nullptr, *pb = nullptr;
-                if (!blk_in_lds) {
+                const double *rg = s_R + g * (NH + 1);
+                const short *wi = s_widx + idx * NK;
+                double sw = 0.0;
+#pragma unroll
+                for (int kx = 0; kx <= KX; ++kx)
+#pragma unroll
+                  for (int ky = 0; ky <= KX; ++ky) {
+                    double sz = 0.0;
+#pragma unroll
+                    for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rg[wi[(kx * (KX + 1) + ky) * (KX + 1) + kz]];
+                    sw += ex[kx] * ey[ky] * sz;
+                  }
+                s_W[g * NW + idx] = sw;
+              }
+              __syncthreads();
+              // component (ic, ia, ib) of group g = sum_{tuv} E^x_t E^y_u E^z_v W[g][ic][tuv]
+              for (int e = lane; e < ngrp * NBLK; e += 64) {
+                const int g = e / NBLK, comp = e - g * NBLK;
+                if (!((gnz >> (g * gs)) & 1ull)) continue;
+                const int c = s_ctab[comp];
+                const int ic = c & 0xff;
+                const double *ex = s_E + 0 * EA + ((c >> 8) & 0xff) * (LAB + 1);
+                const double *ey = s_E + 1 * EA + ((c >> 16) & 0xff) * (LAB + 1);
+                const double *ez = s_E + 2 * EA + ((c >> 24) & 0xff) * (LAB + 1);
+                const double *wr = s_W + g * NW + ic * NHAB;
+                double so = 0.0;
+#pragma unroll
+                for (int t = 0; t <= LAB; ++t) {
+                  double st = 0.0;
+#pragma unroll
+                  for (int u = 0; u <= LAB - t; ++u) {
+                    double su = 0.0;
+#pragma unroll
+                    for (int v = 0; v <= LAB - t - u; ++v) su += ez[v] * wr[hidx(t, u, v)];
+                    st += ey[u] * su;
+                  }
+                  so += ex[t] * st;
+                }
+                const double val = coef * so;
+                if (blk_in_lds) {
+                  s_blk[g * NBLK + comp] += val;
+                } else {
                   const int cg = wk.cb0 + g;
                   const int ig0 = cg / (lat.n[1] * lat.n[2]), ig1 = (cg / lat.n[2]) % lat.n[1], ig2 = cg % lat.n[2];
                   const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
                   const int c2 = (((ig0 + dc0) % lat.n[0]) * lat.n[1] + (ig1 + dc1) % lat.n[1]) * lat.n[2] +
                                  (ig2 + dc2) % lat.n[2];
-                  X12 = prm.X + (size_t)(cg * nk + c2) * xplane;
-                  X21 = prm.X + (size_t)(c2 * nk + cg) * xplane;
-                  if (part) pb = part + ((size_t)g * nk + c2) * NBLK;
-                }
-                // component (ic, ia, ib) = sum_{tuv} E^x_t E^y_u E^z_v W[ic][tuv]
-                for (int comp = lane; comp < NBLK; comp += 64) {
-                  const int c = s_ctab[comp];
-                  const int ic = c & 0xff;
-                  const double *ex = s_E + 0 * EA + ((c >> 8) & 0xff) * (LAB + 1);
-                  const double *ey = s_E + 1 * EA + ((c >> 16) & 0xff) * (LAB + 1);
-                  const double *ez = s_E + 2 * EA + ((c >> 24) & 0xff) * (LAB + 1);
-                  const double *wr = s_W + ic * NHAB;
-                  double so = 0.0;
-#pragma unroll
-                  for (int t = 0; t <= LAB; ++t) {
-                    double st = 0.0;
-#pragma unroll
-                    for (int u = 0; u <= LAB - t; ++u) {
-                      double su = 0.0;
-#pragma unroll
-                      for (int v = 0; v <= LAB - t - u; ++v) su += ez[v] * wr[hidx(t, u, v)];
-                      st += ey[u] * su;
-                    }
-                    so += ex[t] * st;
-                  }
-                  const double val = coef * so;
-                  if (blk_in_lds) {
-                    s_blk[g * NBLK + comp] += val;
-                  } else if (pb) {
-                    pb[comp] += val;
+                  if (part) {
+                    part[((size_t)g * nk + c2) * NBLK + comp] += val;
                   } else {
                     const int ia = (comp / NCB) % NCA, ib = comp % NCB;
                     const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
-                    X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += val;
-                    if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
+                    prm.X[(size_t)(cg * nk + c2) * xplane + (rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += val;
+                    if (!pr.diag)
+                      prm.X[(size_t)(c2 * nk + cg) * xplane + (rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
                   }
                 }
-                __syncthreads();
               }
+              __syncthreads();
               ++n_contr;
           }
         }
