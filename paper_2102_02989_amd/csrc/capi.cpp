@@ -1256,7 +1256,7 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
         gev->push_back(e1);
         HIPCHK(hipEventRecord(e0, st));
       }
-      HIPCHK(launch_lr_gemm_mfma(o.lr_precision, gp, nkpi, st));
+      HIPCHK(launch_lr_gemm_tiled(o.lr_precision, gp, 0, nkpi, st));
       if (gev) HIPCHK(hipEventRecord(e1, st));
       lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
     }

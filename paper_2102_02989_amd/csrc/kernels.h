@@ -89,7 +89,7 @@ hipError_t launch_sr_reduce(const SRParams &prm, const SRPartGroup *groups, int 
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream);
 hipError_t launch_overlaps(const OvlParams &op, const SmnParams &sp, hipStream_t stream);
 hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream);
-hipError_t launch_lr_gemm_mfma(int mode, const LRGemmParams &gp, int nkpi, hipStream_t stream);
+hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream);
 hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream);
 hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *amax, hipStream_t stream);
 hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,

@@ -352,7 +352,6 @@ hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk
 // 16-q partial is then added to FP64 registers, and the first nq_hi columns
 // (the smallest |q|, whose kernel weights 1/q^2 dominate) are taken in FP64
 // on the vector ALUs.
-// Workgroup tile 64 x 64 (4 waves, 32 x 32 each = 2 x 2 MFMA blocks).
 // Operand fragments (li = lane % 16, lg = lane / 16):
 //   16x16x4 (f64, f32): A[li][lg], B[lg][li]
 //   16x16x16 bf16:      A[li][4 lg + j], B[4 lg + j][li], j = 0..3 packed
@@ -368,216 +367,293 @@ __device__ __forceinline__ unsigned short lr_f2bf(float x) {  // round to neares
 }
 __device__ __forceinline__ float lr_bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
+// ---- tiled G-space contraction ----------------------------------------------
+// Workgroup output tile BM (aux rows) x 128 (pair columns): 2 x (BM/32)
+// wavefronts, wave (wm, wn) owning rows 32 wm .. +32 and columns 64 wn .. +64
+// (2 x 4 MFMA blocks).  Per step of 16 q the A and B tiles are read once,
+// converted to the form's operand format and staged in LDS (rows padded
+// against bank conflicts); the next step's tiles are loaded into registers
+// while the matrix cores work on the current one.  Modes 1 and 2 promote the
+// FP32 block sums to FP64 registers after every step, which needs twice the
+// registers: they run 4 waves (BM = 64, up to 512 registers per lane), mode 0
+// runs 8 (BM = 128).  Columns q in [q_lo, nq) of the launch.
+constexpr int TG_BN = 128, TG_BK = 16;
+__host__ __device__ constexpr int tg_bm(int mode) { return mode == 0 ? 128 : 64; }
+__host__ __device__ constexpr int tg_threads(int mode) { return 2 * (tg_bm(mode) / 32) * 64; }
+
 template <int MODE>
-__global__ __launch_bounds__(256) void lr_gemm_mfma_kernel(const LRGemmParams gp) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kpi = blockIdx.z;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
-  const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
+struct TgTile;
+template <>
+struct TgTile<0> {  // FP64 re / im planes
+  double ar[128][TG_BK + 1], ai[128][TG_BK + 1], br[TG_BN][TG_BK + 1], bi[TG_BN][TG_BK + 1];
+};
+template <>
+struct TgTile<1> {  // FP32 re / im planes
+  float ar[64][TG_BK + 1], ai[64][TG_BK + 1], br[TG_BN][TG_BK + 1], bi[TG_BN][TG_BK + 1];
+};
+template <>
+struct TgTile<2> {  // BF16 hi / lo of re / im; rows of 16 + 4 halves (8-byte aligned)
+  unsigned short a[4][64][TG_BK + 4], b[4][TG_BN][TG_BK + 4];  // planes: re_hi, re_lo, im_hi, im_lo
+};
+
+template <int MODE>
+__global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const LRGemmParams gp, int q_lo) {
+  constexpr int BM = tg_bm(MODE), NT = tg_threads(MODE);
+  constexpr int RA = BM * 4 / NT, RB = TG_BN * 4 / NT;  // staged rows per thread (4 threads x 4 q per row)
+  __shared__ TgTile<MODE> S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-
-  auto loadA = [&](int m, int k, double &re, double &im) {
-    if (m < gp.naux && k < gp.nq) {
-      const size_t o = (size_t)m * gp.lda + k;
-      re = gp.A[2 * o];
-      im = gp.A[2 * o + 1];
-    } else {
-      re = im = 0.0;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int kpi = blockIdx.z;
+  const int M0 = blockIdx.y * BM, N0 = blockIdx.x * TG_BN;
+  const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
+  const int sr0 = tid >> 2, sq = (tid & 3) * 4;
+  double ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + sq + j;
+      const bool okk = k < gp.nq;
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const int m = M0 + sr0 + r * (NT / 4);
+        if (okk && m < gp.naux) {
+          const size_t o = (size_t)m * gp.lda + k;
+          ga[r][2 * j] = gp.A[2 * o];
+          ga[r][2 * j + 1] = gp.A[2 * o + 1];
+        } else {
+          ga[r][2 * j] = ga[r][2 * j + 1] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int n = N0 + sr0 + r * (NT / 4);
+        if (okk && n < gp.nmn) {
+          const size_t o = (size_t)n * gp.nq + k;
+          gb[r][2 * j] = Bk[2 * o];
+          gb[r][2 * j + 1] = Bk[2 * o + 1];
+        } else {
+          gb[r][2 * j] = gb[r][2 * j + 1] = 0.0;
+        }
+      }
     }
   };
-  auto loadB = [&](int k, int n, double &re, double &im) {
-    if (n < gp.nmn && k < gp.nq) {
-      const size_t o = (size_t)n * gp.nq + k;
-      re = Bk[2 * o];
-      im = Bk[2 * o + 1];
-    } else {
-      re = im = 0.0;
+  auto sstore = [&]() {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const int row = sr0 + r * (NT / 4);
+        if constexpr (MODE == 0) {
+          S.ar[row][sq + j] = ga[r][2 * j];
+          S.ai[row][sq + j] = ga[r][2 * j + 1];
+        } else if constexpr (MODE == 1) {
+          S.ar[row][sq + j] = (float)ga[r][2 * j];
+          S.ai[row][sq + j] = (float)ga[r][2 * j + 1];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const float f = (float)ga[r][2 * j + c];
+            const unsigned short h = lr_f2bf(f);
+            S.a[2 * c][row][sq + j] = h;
+            S.a[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int row = sr0 + r * (NT / 4);
+        if constexpr (MODE == 0) {
+          S.br[row][sq + j] = gb[r][2 * j];
+          S.bi[row][sq + j] = gb[r][2 * j + 1];
+        } else if constexpr (MODE == 1) {
+          S.br[row][sq + j] = (float)gb[r][2 * j];
+          S.bi[row][sq + j] = (float)gb[r][2 * j + 1];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const float f = (float)gb[r][2 * j + c];
+            const unsigned short h = lr_f2bf(f);
+            S.b[2 * c][row][sq + j] = h;
+            S.b[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
+          }
+        }
+      }
     }
   };
 
-  // FP64 results in the f32 fragment order: element v <-> row 4 lg + v
-  double hre[2][2][4], him[2][2][4];
+  typedef typename std::conditional<MODE == 0, lr_d4, lr_f4>::type acc_t;
+  acc_t cre[2][4], cim[2][4];
+  double hre[2][4][4], him[2][4][4];  // FP64 sums of modes 1 and 2 (f32 fragment order)
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) hre[r][c][v] = him[r][c][v] = 0.0;
+      for (int v = 0; v < 4; ++v) {
+        cre[r][c][v] = cim[r][c][v] = 0;
+        hre[r][c][v] = him[r][c][v] = 0.0;
+      }
 
-  if constexpr (MODE == 0) {
-    lr_d4 cre[2][2], cim[2][2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cre[r][c][v] = cim[r][c][v] = 0.0;
-    for (int k0 = 0; k0 < gp.nq; k0 += 4) {
-      const int k = k0 + lg;
-      double ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) loadA(m0 + r * 16 + li, k, ar[r], ai[r]);
-#pragma unroll
-      for (int c = 0; c < 2; ++c) loadB(k, n0 + c * 16 + li, br[c], bi[c]);
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], br[c], cre[r][c], 0, 0, 0);
-          cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[r], bi[c], cre[r][c], 0, 0, 0);
-          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], bi[c], cim[r][c], 0, 0, 0);
-          cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[r], br[c], cim[r][c], 0, 0, 0);
-        }
-    }
-    // f64 fragment (row lg + 4 v) -> output
-    const size_t kp = gp.kp_of[kpi];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = m0 + r * 16 + lg + 4 * v, n = n0 + c * 16 + li;
-          if (m < gp.naux && n < gp.nmn) {
-            const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
-            gp.out[2 * o] += cre[r][c][v];
-            gp.out[2 * o + 1] += cim[r][c][v];
-          }
-        }
-    return;
-  } else {
-    // innermost q shell in FP64 on the vector ALUs
+  // modes 1 and 2: the innermost q shell (first nq_hi columns) in FP64 on the
+  // vector ALUs, rows in the f32 fragment order
+  int kstart = q_lo;
+  if constexpr (MODE != 0) {
     const int khi = gp.nq_hi < gp.nq ? gp.nq_hi : gp.nq;
-    for (int k = 0; k < khi; ++k) {
-      double br[2], bi[2];
+    for (int k = q_lo; k < khi; ++k) {
+      double br[4], bi[4];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) loadB(k, n0 + c * 16 + li, br[c], bi[c]);
+      for (int c = 0; c < 4; ++c) {
+        const int n = N0 + wn * 64 + c * 16 + li;
+        const size_t o = (size_t)n * gp.nq + k;
+        br[c] = (n < gp.nmn) ? Bk[2 * o] : 0.0;
+        bi[c] = (n < gp.nmn) ? Bk[2 * o + 1] : 0.0;
+      }
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          double ar, ai;
-          loadA(m0 + r * 16 + 4 * lg + v, k, ar, ai);
+          const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
+          const size_t o = (size_t)m * gp.lda + k;
+          const double ar = (m < gp.naux) ? gp.A[2 * o] : 0.0, ai = (m < gp.naux) ? gp.A[2 * o + 1] : 0.0;
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
+          for (int c = 0; c < 4; ++c) {
             hre[r][c][v] += ar * br[c] - ai * bi[c];
             him[r][c][v] += ar * bi[c] + ai * br[c];
           }
         }
     }
-    for (int k0 = khi; k0 < gp.nq; k0 += 16) {
-      lr_f4 cre[2][2], cim[2][2];
+    kstart = khi > q_lo ? khi : q_lo;
+  }
+  gload(kstart);
+  for (int k0 = kstart; k0 < gp.nq; k0 += TG_BK) {
+    __syncthreads();  // previous step's fragments consumed
+    sstore();
+    __syncthreads();
+    if (k0 + TG_BK < gp.nq) gload(k0 + TG_BK);  // in flight during the MFMAs
+    if constexpr (MODE == 0 || MODE == 1) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+      for (int ks = 0; ks < TG_BK / 4; ++ks) {
+        const int k = ks * 4 + lg;
+        typedef typename std::conditional<MODE == 0, double, float>::type op_t;
+        op_t ar[2], ai[2], br[4], bi[4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) cre[r][c][v] = cim[r][c][v] = 0.f;
-      if constexpr (MODE == 1) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = k0 + ks * 4 + lg;
-          double ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-          for (int r = 0; r < 2; ++r) loadA(m0 + r * 16 + li, k, ar[r], ai[r]);
-#pragma unroll
-          for (int c = 0; c < 2; ++c) loadB(k, n0 + c * 16 + li, br[c], bi[c]);
-#pragma unroll
-          for (int r = 0; r < 2; ++r)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const float far = (float)ar[r], fai = (float)ai[r], fbr = (float)br[c], fbi = (float)bi[c];
-              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(far, fbr, cre[r][c], 0, 0, 0);
-              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fai, fbi, cre[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(far, fbi, cim[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fai, fbr, cim[r][c], 0, 0, 0);
-            }
+        for (int r = 0; r < 2; ++r) {
+          ar[r] = S.ar[wm * 32 + r * 16 + li][k];
+          ai[r] = S.ai[wm * 32 + r * 16 + li][k];
         }
-      } else {
-        lr_s4 arh[2], arl[2], aih[2], ail[2], anh[2], anl[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          br[c] = S.br[wn * 64 + c * 16 + li][k];
+          bi[c] = S.bi[wn * 64 + c * 16 + li][k];
+        }
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            double re, im;
-            loadA(m0 + r * 16 + li, k0 + 4 * lg + j, re, im);
-            const float fr = (float)re, fi = (float)im;
-            const unsigned short hr = lr_f2bf(fr), hi = lr_f2bf(fi);
-            const unsigned short lr_ = lr_f2bf(fr - lr_bf2f(hr)), li_ = lr_f2bf(fi - lr_bf2f(hi));
-            arh[r][j] = (short)hr;
-            arl[r][j] = (short)lr_;
-            aih[r][j] = (short)hi;
-            ail[r][j] = (short)li_;
-            anh[r][j] = (short)(hi ^ 0x8000u);  // -a_im
-            anl[r][j] = (short)(li_ ^ 0x8000u);
-          }
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            double re, im;
-            loadB(k0 + 4 * lg + j, n0 + c * 16 + li, re, im);
-            const float fr = (float)re, fi = (float)im;
-            const unsigned short hr = lr_f2bf(fr), hi = lr_f2bf(fi);
-            brh[c][j] = (short)hr;
-            brl[c][j] = (short)lr_f2bf(fr - lr_bf2f(hr));
-            bih[c][j] = (short)hi;
-            bil[c][j] = (short)lr_f2bf(fi - lr_bf2f(hi));
-          }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            lr_f4 x = cre[r][c], y = cim[r][c];
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh[r], brh[c], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh[r], brl[c], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arl[r], brh[c], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(anh[r], bih[c], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(anh[r], bil[c], x, 0, 0, 0);
-            x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(anl[r], bih[c], x, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh[r], bih[c], y, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh[r], bil[c], y, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arl[r], bih[c], y, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aih[r], brh[c], y, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aih[r], brl[c], y, 0, 0, 0);
-            y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ail[r], brh[c], y, 0, 0, 0);
-            cre[r][c] = x;
-            cim[r][c] = y;
+          for (int c = 0; c < 4; ++c) {
+            if constexpr (MODE == 0) {
+              cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], br[c], cre[r][c], 0, 0, 0);
+              cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[r], bi[c], cre[r][c], 0, 0, 0);
+              cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], bi[c], cim[r][c], 0, 0, 0);
+              cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[r], br[c], cim[r][c], 0, 0, 0);
+            } else {
+              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], br[c], cre[r][c], 0, 0, 0);
+              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[r], bi[c], cre[r][c], 0, 0, 0);
+              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], bi[c], cim[r][c], 0, 0, 0);
+              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[r], br[c], cim[r][c], 0, 0, 0);
+            }
           }
       }
+    } else {
+      lr_s4 a[2][4], an[2][2], b[4][4];  // a: re_hi, re_lo, im_hi, im_lo; an: -im_hi, -im_lo
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int pl = 0; pl < 4; ++pl) {
+          const unsigned short *src = &S.a[pl][wm * 32 + r * 16 + li][4 * lg];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) a[r][pl][j] = (short)src[j];
+        }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          an[r][0][j] = (short)((unsigned short)a[r][2][j] ^ 0x8000u);
+          an[r][1][j] = (short)((unsigned short)a[r][3][j] ^ 0x8000u);
+        }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl) {
+          const unsigned short *src = &S.b[pl][wn * 64 + c * 16 + li][4 * lg];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[c][pl][j] = (short)src[j];
+        }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          lr_f4 x = cre[r][c], y = cim[r][c];
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][0], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][1], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][1], b[c][0], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][0], b[c][2], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][0], b[c][3], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][1], b[c][2], x, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][2], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][3], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][1], b[c][2], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][2], b[c][0], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][2], b[c][1], y, 0, 0, 0);
+          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][3], b[c][0], y, 0, 0, 0);
+          cre[r][c] = x;
+          cim[r][c] = y;
+        }
+    }
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             hre[r][c][v] += (double)cre[r][c][v];
             him[r][c][v] += (double)cim[r][c][v];
+            cre[r][c][v] = 0.f;
+            cim[r][c][v] = 0.f;
           }
     }
-    const size_t kp = gp.kp_of[kpi];
+  }
+  // epilogue: f64 fragment row = lg + 4 v, f32 fragment row = 4 lg + v
+  const size_t kp = gp.kp_of[kpi];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = m0 + r * 16 + 4 * lg + v, n = n0 + c * 16 + li;
-          if (m < gp.naux && n < gp.nmn) {
-            const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
+      for (int v = 0; v < 4; ++v) {
+        const int m = M0 + wm * 32 + r * 16 + ((MODE == 0) ? (lg + 4 * v) : (4 * lg + v));
+        const int n = N0 + wn * 64 + c * 16 + li;
+        if (m < gp.naux && n < gp.nmn) {
+          const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
+          if constexpr (MODE == 0) {
+            gp.out[2 * o] += cre[r][c][v];
+            gp.out[2 * o + 1] += cim[r][c][v];
+          } else {
             gp.out[2 * o] += hre[r][c][v];
             gp.out[2 * o + 1] += him[r][c][v];
           }
         }
-  }
+      }
 }
 
-hipError_t launch_lr_gemm_mfma(int mode, const LRGemmParams &gp, int nkpi, hipStream_t stream) {
-  dim3 grid((gp.nmn + 63) / 64, (gp.naux + 63) / 64, nkpi);
-  if (mode == 0) hipLaunchKernelGGL(lr_gemm_mfma_kernel<0>, grid, dim3(256), 0, stream, gp);
-  else if (mode == 1) hipLaunchKernelGGL(lr_gemm_mfma_kernel<1>, grid, dim3(256), 0, stream, gp);
-  else hipLaunchKernelGGL(lr_gemm_mfma_kernel<2>, grid, dim3(256), 0, stream, gp);
+hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream) {
+  if (q_lo >= gp.nq) return hipSuccess;
+  const int bm = tg_bm(mode);
+  dim3 grid((gp.nmn + TG_BN - 1) / TG_BN, (gp.naux + bm - 1) / bm, nkpi);
+  if (mode == 0) hipLaunchKernelGGL(lr_gemm_tiled_kernel<0>, grid, dim3(tg_threads(0)), 0, stream, gp, q_lo);
+  else if (mode == 1) hipLaunchKernelGGL(lr_gemm_tiled_kernel<1>, grid, dim3(tg_threads(1)), 0, stream, gp, q_lo);
+  else hipLaunchKernelGGL(lr_gemm_tiled_kernel<2>, grid, dim3(tg_threads(2)), 0, stream, gp, q_lo);
   return hipGetLastError();
 }
 
