@@ -313,29 +313,42 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 }
 
 // B[kpi][mn][q] = sum_c phase[kpi][c] I[c][mn][q], phase = e^{+i k2.L_c}; one
-// thread per (mn, q) element.
-__global__ void kphase_kernel(const double *__restrict__ I, const double *__restrict__ phase, double *__restrict__ B,
-                              int nk, int nkpi, int nq, int64_t nmn) {
+// thread per (mn, q) element.  The k-pairs are taken 16 at a time with their
+// sums in registers, so each I value is read once per 16 k-pairs; the phases
+// are uniform over the wave (scalar loads).
+constexpr int KPH_KB = 16;
+__global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ I, const double *__restrict__ phase,
+                                                     double *__restrict__ B, int nk, int nkpi, int nq, int64_t nmn) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ne = (int64_t)nq * nmn;
   if (gid >= ne) return;
-  for (int k = 0; k < nkpi; ++k) {
-    double sr = 0.0, si = 0.0;
+  for (int k0 = 0; k0 < nkpi; k0 += KPH_KB) {
+    double sr[KPH_KB], si[KPH_KB];
+#pragma unroll
+    for (int kk = 0; kk < KPH_KB; ++kk) sr[kk] = si[kk] = 0.0;
     for (int c = 0; c < nk; ++c) {
       const double ir = I[2 * ((int64_t)c * ne + gid)], ii = I[2 * ((int64_t)c * ne + gid) + 1];
-      const double pr = phase[2 * (k * nk + c)], pi = phase[2 * (k * nk + c) + 1];
-      sr += pr * ir - pi * ii;
-      si += pr * ii + pi * ir;
+#pragma unroll
+      for (int kk = 0; kk < KPH_KB; ++kk) {
+        const int k = (k0 + kk < nkpi) ? k0 + kk : nkpi - 1;  // clamped: in-bounds, result unused
+        const double pr = phase[2 * (k * nk + c)], pi = phase[2 * (k * nk + c) + 1];
+        sr[kk] += pr * ir - pi * ii;
+        si[kk] += pr * ii + pi * ir;
+      }
     }
-    B[2 * ((int64_t)k * ne + gid)] = sr;
-    B[2 * ((int64_t)k * ne + gid) + 1] = si;
+#pragma unroll
+    for (int kk = 0; kk < KPH_KB; ++kk)
+      if (k0 + kk < nkpi) {
+        B[2 * ((int64_t)(k0 + kk) * ne + gid)] = sr[kk];
+        B[2 * ((int64_t)(k0 + kk) * ne + gid) + 1] = si[kk];
+      }
   }
 }
 
 hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,
                          hipStream_t stream) {
   const int64_t ne = (int64_t)nq * nmn;
-  if (ne == 0) return hipSuccess;
+  if (ne == 0 || nkpi == 0) return hipSuccess;
   hipLaunchKernelGGL(kphase_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, I, phase, B, nk, nkpi,
                      nq, nmn);
   return hipGetLastError();
