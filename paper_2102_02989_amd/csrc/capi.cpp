@@ -620,7 +620,8 @@ struct Job {
   int nk = 0, nkp = 0, npair = 0, nxs = 0, nb = 0;
   int64_t nao = 0, naux = 0, nao2 = 0, need = 0;
   double t_plan = 0.0;
-  DBuf d_ao, d_ax, d_aoe, d_aoc, d_aoc1, d_axe, d_axc, d_axc1, d_pairs, d_coff, d_nsr, d_img, d_boys;
+  DBuf d_ao, d_ax, d_aoe, d_aoc, d_aoc1, d_axe, d_axc, d_axc1, d_pairs, d_coff, d_nsr, d_img, d_boys, d_plist;
+  int32_t plist_grp[7] = {};  // d_plist offsets of the (l(sa), l(sb)) groups dd, dp, ds, pp, ps, ss
   DBuf d_outbuf;
   double *d_out = nullptr;
   std::vector<double> kph;
@@ -720,6 +721,22 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   HIPCHK(upload(d_axc, hp.ax_coef, st));
   HIPCHK(upload(d_axc1, hp.ax_c1s, st));
   HIPCHK(upload(d_pairs, hp.pairs, st));
+  {  // pair indices grouped by angular momenta for the per-group transform kernels
+    static const int key_of_grp[6] = {8, 7, 6, 4, 3, 0};  // 3 l(sa) + l(sb)
+    std::vector<int32_t> plist;
+    for (int g = 0; g < 6; ++g) {
+      plist_grp[g] = (int32_t)plist.size();
+      for (int ip = 0; ip < npair; ++ip) {
+        const Pair &p = hp.pairs[ip];
+        const int la = hp.ao[p.sa].l, lb = hp.ao[p.sb].l;
+        if (la > 2 || lb > la) return fail(RSGDF_EINVAL, "internal: AO pair not oriented with l(sa) >= l(sb)");
+        if (3 * la + lb == key_of_grp[g]) plist.push_back(ip);
+      }
+    }
+    plist_grp[6] = (int32_t)plist.size();
+    if (plist_grp[6] != npair) return fail(RSGDF_EINVAL, "internal: AO pair outside the angular groups");
+    HIPCHK(upload(d_plist, plist, st));
+  }
   HIPCHK(upload(d_coff, hp.cls_off, st));
   HIPCHK(upload(d_nsr, hp.nsr, st));
   HIPCHK(upload(d_img, hp.img, st));
@@ -1219,6 +1236,8 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
       pp.ao_exp = d_aoe.as<double>();
       pp.ao_coef = d_aoc.as<double>();
       pp.pairs = d_pairs.as<Pair>();
+      pp.plist = d_plist.as<int32_t>();
+      for (int g = 0; g < 7; ++g) pp.pgrp[g] = plist_grp[g];
       pp.cls_off = d_coff.as<int32_t>();
       pp.img = d_img.as<double>();
       pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);

@@ -55,6 +55,8 @@ struct PairFTParams {
   const Shell *ao;
   const double *ao_exp, *ao_coef;
   const Pair *pairs;
+  const int32_t *plist;   // pair indices grouped by (l(sa), l(sb)): d-d, d-p, d-s, p-p, p-s, s-s
+  int32_t pgrp[7];        // plist offsets of the six groups (host-side launch split)
   const int32_t *cls_off;
   const double *img;
   const double *q;        // [nq][3] chunk, all q = G + k_cls of one class

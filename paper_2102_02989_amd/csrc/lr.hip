@@ -118,10 +118,20 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
   const Pair pr = pp.pairs[ip];
   const Shell s1 = pp.ao[pr.sa];
   const Shell s2 = pp.ao[pr.sb];
-  const double qx = pp.q[3 * iq], qy = pp.q[3 * iq + 1], qz = pp.q[3 * iq + 2];
+  const bool live = iq < pp.nq;
+  const int iqc = live ? iq : pp.nq - 1;  // idle lanes of the last block follow a valid q, write nothing
+  const double qx = pp.q[3 * iqc], qy = pp.q[3 * iqc + 1], qz = pp.q[3 * iqc + 2];
+  // The skip tests use the wave's extreme values (largest amax and |q|,
+  // smallest q^2), so they bound every lane's terms and every lane takes the
+  // same branch.
   const double q2 = qx * qx + qy * qy + qz * qz;
-  const double qn = sqrt(q2);
-  const double am = pp.amax[iq];
+  double am = pp.amax[iqc], q2w = q2, qnw = sqrt(q2);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    am = fmax(am, __shfl_xor(am, o, 64));
+    q2w = fmin(q2w, __shfl_xor(q2w, o, 64));
+    qnw = fmax(qnw, __shfl_xor(qnw, o, 64));
+  }
   const double cut = am > 0.0 ? pp.eps / am : 1e300;
   // (-i q_d)^t = qr[d][t] + i qi[d][t]
   double qr[3][LT + 1], qi[3][LT + 1];
@@ -150,15 +160,14 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
       const double p = ga + gb, oop = 1.0 / p, beta = ga * gb * oop;
       const double cc = pp.ao_coef[s1.pptr + ka] * pp.ao_coef[s2.pptr + kb];
       const double pre = kPi * oop * sqrt(kPi * oop);
-      const double eq = exp(-q2 * 0.25 * oop);
-      const double cq = 1.0 + 0.5 * qn * oop + sqrt(0.5 * LT * oop);
+      const double cq = 1.0 + 0.5 * qnw * oop + sqrt(0.5 * LT * oop);
       const double rstar = 0.5 * (sqrt(cq * cq + 2.0 * LT / beta) - cq);
-      const double amp0 = fabs(cc) * pre * eq;
+      const double amp0 = fabs(cc) * pre * exp(-q2w * 0.25 * oop);
       double fmax = amp0 * exp(-beta * rstar * rstar);
 #pragma unroll
       for (int t = 0; t < LT; ++t) fmax *= (cq + rstar);
       if (fmax < cut) continue;
-      const double camp = cc * pre * eq;
+      const double camp = cc * pre * exp(-q2 * 0.25 * oop);
       for (int ii = beg; ii < end; ++ii) {
         const double *nv = pp.img + 3 * (size_t)(pr.img_off + ii);
         const double Bx = s2.x + nv[0], By = s2.y + nv[1], Bz = s2.z + nv[2];
@@ -173,7 +182,7 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
           if (rr > rstar) break;
           continue;
         }
-        ++cnt;
+        cnt += live;
         // P - A = (gb/p) R, P - B = -(ga/p) R
         const double wa = gb * oop, wb = -ga * oop;
         const double Px = s1.x + wa * Rx, Py = s1.y + wa * Ry, Pz = s1.z + wa * Rz;
@@ -226,6 +235,7 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
           }
       }
     }
+  if (!live) return cnt;
   const int nao = pp.nao;
   const size_t nq = pp.nq;
   double *Ic = pp.B + 2 * ((size_t)c * nao * nao * nq);
@@ -261,24 +271,13 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
   return cnt;
 }
 
-// grid: x = (pair, class), y = 64-wide blocks of q
-__global__ __launch_bounds__(64) void pairft_binned_kernel(const PairFTParams pp) {
-  const int ip = (int)(blockIdx.x / pp.nk), c = (int)(blockIdx.x % pp.nk);
+// grid: x = (pair of one angular group, class), y = 64-wide blocks of q;
+// one kernel per (l(sa), l(sb)) so that each runs at its own register count
+template <int LA, int LB>
+__global__ __launch_bounds__(64) void pairft_binned_kernel(const PairFTParams pp, int pbeg) {
+  const int ip = pp.plist[pbeg + (int)(blockIdx.x / pp.nk)], c = (int)(blockIdx.x % pp.nk);
   const int iq = blockIdx.y * 64 + threadIdx.x;
-  long long cnt = 0;
-  if (iq < pp.nq) {
-    const Pair pr = pp.pairs[ip];
-    const int key = pp.ao[pr.sa].l * 3 + pp.ao[pr.sb].l;
-    switch (key) {  // pairs are oriented with l(sa) >= l(sb)
-      case 0: cnt = pairft_binned_one<0, 0>(pp, ip, c, iq); break;
-      case 3: cnt = pairft_binned_one<1, 0>(pp, ip, c, iq); break;
-      case 4: cnt = pairft_binned_one<1, 1>(pp, ip, c, iq); break;
-      case 6: cnt = pairft_binned_one<2, 0>(pp, ip, c, iq); break;
-      case 7: cnt = pairft_binned_one<2, 1>(pp, ip, c, iq); break;
-      case 8: cnt = pairft_binned_one<2, 2>(pp, ip, c, iq); break;
-      default: break;
-    }
-  }
+  long long cnt = pairft_binned_one<LA, LB>(pp, ip, c, iq);
   // wave sum of the evaluation counts, one integer atomic per wave
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
@@ -287,10 +286,17 @@ __global__ __launch_bounds__(64) void pairft_binned_kernel(const PairFTParams pp
 
 hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream) {
   if (pp.nq == 0 || pp.npair == 0) return hipSuccess;
-  const int64_t nx = (int64_t)pp.npair * pp.nk;
   const int64_t ny = (pp.nq + 63) / 64;
-  if (nx > 0x7fffffff || ny > 65535) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(pairft_binned_kernel, dim3((unsigned)nx, (unsigned)ny), dim3(64), 0, stream, pp);
+  if (ny > 65535) return hipErrorInvalidConfiguration;
+  typedef void (*K)(const PairFTParams, int);
+  const K ks[6] = {pairft_binned_kernel<2, 2>, pairft_binned_kernel<2, 1>, pairft_binned_kernel<2, 0>,
+                   pairft_binned_kernel<1, 1>, pairft_binned_kernel<1, 0>, pairft_binned_kernel<0, 0>};
+  for (int g = 0; g < 6; ++g) {
+    const int64_t nx = (int64_t)(pp.pgrp[g + 1] - pp.pgrp[g]) * pp.nk;
+    if (nx == 0) continue;
+    if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(ks[g], dim3((unsigned)nx, (unsigned)ny), dim3(64), 0, stream, pp, pp.pgrp[g]);
+  }
   return hipGetLastError();
 }
 
