@@ -106,15 +106,39 @@ __device__ __forceinline__ void cart_decode(int l, int i, int &x, int &y, int &z
   x = y = z = 0;
 }
 
+// e^{-T} for T >= 0 without the library's range reduction: T = (i + 1/2) + u
+// with i = floor(T), |u| <= 1/2, e^{-T} = e^{-(i+1/2)} e^{-u}; the first factor
+// comes from a table of kExpTab entries, the second from its Taylor series to
+// degree 14 (truncation below 3e-17 relative), evaluated by Estrin's scheme.
+// Zero beyond the table (e^{-64} < 2e-28).
+constexpr int kExpTab = 64;
+__device__ __forceinline__ double exp_neg_tab(double T, const double *__restrict__ etab) {
+  const int i = min((int)T, kExpTab - 1);
+  const double v = (i + 0.5) - fmin(T, (double)kExpTab);  // -u
+  const double v2 = v * v, v4 = v2 * v2, v8 = v4 * v4;
+  // 1/k!, k = 0..14
+  const double a0 = fma(v, 1.0, 1.0);
+  const double a1 = fma(v, 1.0 / 6.0, 1.0 / 2.0);
+  const double a2 = fma(v, 1.0 / 120.0, 1.0 / 24.0);
+  const double a3 = fma(v, 1.0 / 5040.0, 1.0 / 720.0);
+  const double a4 = fma(v, 1.0 / 362880.0, 1.0 / 40320.0);
+  const double a5 = fma(v, 1.0 / 39916800.0, 1.0 / 3628800.0);
+  const double a6 = fma(v, 1.0 / 6227020800.0, 1.0 / 479001600.0);
+  const double a7 = 1.0 / 87178291200.0;
+  const double b0 = fma(a1, v2, a0), b1 = fma(a3, v2, a2), b2 = fma(a5, v2, a4), b3 = fma(a7, v2, a6);
+  const double d0 = fma(b1, v4, b0), d1 = fma(b3, v4, b2);
+  const double e = etab[i] * fma(d1, v8, d0);
+  return T < (double)kExpTab ? e : 0.0;
+}
+
 // F_L(T) for 0 <= T < kBoysSwitch from the per-L polynomial table (Taylor
 // expansion of degree kBoysPolyDeg about each unit interval's centre), then the
-// downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1).
+// downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1), e = e^{-T} given.
 // The polynomial is evaluated by Estrin's scheme (pairs, then powers u^2,
-// u^4, u^8): dependency depth 5 instead of 12 for Horner's rule, which is what
-// bounds this loop at one or two wavefronts per SIMD.
+// u^4, u^8): dependency depth 5 instead of 12 for Horner's rule.
 static_assert(kBoysPolyDeg == 12, "Estrin evaluation below is written for degree 12");
 template <int L>
-__device__ __forceinline__ void boys_poly(double T, const double *__restrict__ tab, double (&F)[L + 1]) {
+__device__ __forceinline__ void boys_poly(double T, double e, const double *__restrict__ tab, double (&F)[L + 1]) {
   const int i = (int)T;
   const double u = T - (i + 0.5);
   const double *c = tab + i * (kBoysPolyDeg + 1);
@@ -123,14 +147,22 @@ __device__ __forceinline__ void boys_poly(double T, const double *__restrict__ t
   const double a3 = fma(c[7], u, c[6]), a4 = fma(c[9], u, c[8]), a5 = fma(c[11], u, c[10]);
   const double b0 = fma(a1, u2, a0), b1 = fma(a3, u2, a2), b2 = fma(a5, u2, a4);
   const double d0 = fma(b1, u4, b0), d1 = fma(c[12], u4, b2);
-  const double s = fma(d1, u8, d0);
-  F[L] = s;
-  if (L > 0) {
-    const double e = exp(-T);
-    const double t2 = 2.0 * T;
+  F[L] = fma(d1, u8, d0);
+  const double t2 = 2.0 * T;
 #pragma unroll
-    for (int n = L - 1; n >= 0; --n) F[n] = fma(t2, F[n + 1], e) * (1.0 / (2 * n + 1));
-  }
+  for (int n = L - 1; n >= 0; --n) F[n] = fma(t2, F[n + 1], e) * (1.0 / (2 * n + 1));
+}
+
+// F_n(T), n = 0..L, for T >= kBoysSwitch: F_0 = sqrt(pi/T)/2 and the upward
+// recursion F_{n+1} = ((2n+1) F_n - e^{-T}) / (2T), e = e^{-T} given; 1/sqrt(T)
+// from one reciprocal square root, 1/T as its square.
+template <int L>
+__device__ __forceinline__ void boys_large_e(double T, double e, double (&F)[L + 1]) {
+  const double r = rsqrt(T);
+  F[0] = 0.886226925452758013649083741671 * r; /* sqrt(pi)/2 */
+  const double h = 0.5 * r * r;
+#pragma unroll
+  for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
 }
 
 // G_n = F_n(T) - theta^{2n+1} F_n(theta^2 T) (erfc operator, see device_math.h);
@@ -138,7 +170,7 @@ __device__ __forceinline__ void boys_poly(double T, const double *__restrict__ t
 // within e^{-theta^2 T}).
 template <int L>
 __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const double *__restrict__ tab,
-                                         double (&G)[L + 1]) {
+                                         const double *__restrict__ etab, double (&G)[L + 1]) {
   const double x = th2 * T;
   if (x >= kBoysSwitch) {
 #pragma unroll
@@ -146,9 +178,10 @@ __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const 
     return;
   }
   double F1[L + 1], F2[L + 1];
-  if (T < kBoysSwitch) boys_poly<L>(T, tab, F1);
-  else boys_large<L>(T, F1);
-  boys_poly<L>(x, tab, F2);
+  const double eT = (L > 0) ? exp_neg_tab(T, etab) : 0.0;
+  if (T < kBoysSwitch) boys_poly<L>(T, eT, tab, F1);
+  else boys_large_e<L>(T, eT, F1);
+  boys_poly<L>(x, (L > 0) ? exp_neg_tab(x, etab) : 0.0, tab, F2);
   double f = th;
 #pragma unroll
   for (int n = 0; n <= L; ++n) {
@@ -183,6 +216,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   constexpr int BLK = NBLK * sr_max_cells(NBLK);
   __shared__ float s_nf[kSRWinCap];
   __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
+  __shared__ double s_etab[kExpTab];  // e^{-(i + 1/2)}
   __shared__ int s_cand[kCandCap];
   __shared__ double s_blk[BLK];
   // one group's image-summed R_tuv in a zero-padded cube, so that every read
@@ -223,6 +257,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   // ---- per-item tables in LDS: Boys polynomials of order L, screening windows
   for (int i = lane; i < kBoysIntervals * (kBoysPolyDeg + 1); i += 64)
     s_boys[i] = prm.boys[L * kBoysIntervals * (kBoysPolyDeg + 1) + i];
+  for (int i = lane; i < kExpTab; i += 64) s_etab[i] = exp(-(i + 0.5));
   const int nta = shA.nprim, ntb = shB.nprim, ntcp = shP.nprim;
   const int ntrip_p = nta * ntb * ntcp;
   const bool tc_lds = ntrip_p <= kTripCap;
@@ -468,7 +503,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 const double Z = dPz + M0 * a[2] + M1 * a[5] + M2 * a[8];
                 const double T = rho * (X * X + Y * Y + Z * Z);
                 double g[L + 1];
-                gvals_sr<L>(T, th2, th, s_boys, g);
+                gvals_sr<L>(T, th2, th, s_boys, s_etab, g);
                 double f = 1.0;
 #pragma unroll
                 for (int n = 1; n <= L; ++n) {
