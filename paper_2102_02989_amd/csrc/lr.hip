@@ -424,7 +424,16 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   const int li = lane & 15, lg = lane >> 4;
   const int wm = wave >> 1, wn = wave & 1;
   const int kpi = blockIdx.z;
-  const int M0 = blockIdx.y * BM, N0 = blockIdx.x * TG_BN;
+  // Tile order: the hardware deals workgroups to the 8 XCDs in turn (workgroup
+  // b to XCD b mod 8), and each XCD has its own L2.  Workgroups b, b + 8,
+  // b + 16, ... are renumbered consecutively, and consecutive tile numbers
+  // walk the aux rows first, so the row tiles that share one B tile (and
+  // stream the same q columns of A) run together on one XCD.
+  const int mt = (gp.naux + BM - 1) / BM, ntile = mt * ((gp.nmn + TG_BN - 1) / TG_BN);
+  const int per = (ntile + 7) / 8;  // the grid holds 8 per workgroups
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= ntile) return;
+  const int M0 = (t % mt) * BM, N0 = (t / mt) * TG_BN;
   const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
   const int sr0 = tid >> 2, sq = (tid & 3) * 4;
   double ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
@@ -669,7 +678,9 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream) {
   if (q_lo >= gp.nq) return hipSuccess;
   const int bm = tg_bm(mode);
-  dim3 grid((gp.nmn + TG_BN - 1) / TG_BN, (gp.naux + bm - 1) / bm, nkpi);
+  const int64_t ntile = (int64_t)((gp.nmn + TG_BN - 1) / TG_BN) * ((gp.naux + bm - 1) / bm);
+  if (ntile * 8 > 0x7fffffff) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(8 * ((ntile + 7) / 8)), 1, nkpi);
   if (mode == 0) hipLaunchKernelGGL(lr_gemm_tiled_kernel<0>, grid, dim3(tg_threads(0)), 0, stream, gp, q_lo);
   else if (mode == 1) hipLaunchKernelGGL(lr_gemm_tiled_kernel<1>, grid, dim3(tg_threads(1)), 0, stream, gp, q_lo);
   else hipLaunchKernelGGL(lr_gemm_tiled_kernel<2>, grid, dim3(tg_threads(2)), 0, stream, gp, q_lo);
