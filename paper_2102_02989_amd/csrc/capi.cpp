@@ -645,7 +645,7 @@ struct Job {
   int64_t nq_tot = 0, qchunk = 1;
   std::vector<std::vector<int>> cls_kp;
   std::vector<int64_t> kpl_off{0};
-  DBuf d_q, d_A, d_I, d_B, d_kp, d_ph, d_nterm, d_amax;
+  DBuf d_q, d_A, d_I, d_B, d_kp, d_ph, d_nterm, d_amax, d_A32, d_Bhi;
   // results
   float t_sr = 0.f, t_fold = 0.f, t_lr = 0.f, t_lr_gemm = 0.f;
   long long n_lr = 0, nskip = 0;
@@ -1089,6 +1089,10 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
     HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
+    if (o.lr_precision != RSGDF_FP64) {  // FP32 operands and the FP64 innermost columns
+      HIPCHK(d_A32.alloc((size_t)naux * std::max<int64_t>(nq_tot, 1) * 2 * sizeof(float)));
+      HIPCHK(d_Bhi.alloc((size_t)max_kpi * kLrNqHi * nao2 * 2 * sizeof(double)));
+    }
     HIPCHK(d_kp.alloc((size_t)std::max(nkp, 1) * sizeof(int32_t)));
     HIPCHK(d_ph.alloc((size_t)std::max(nkp, 1) * nk * 2 * sizeof(double)));
     HIPCHK(d_nterm.alloc(sizeof(long long)));
@@ -1223,7 +1227,9 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
   AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
                  (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
   HIPCHK(launch_auxft(ap, st));
-  const int lr_nq_hi = 32;
+  const bool f32 = o.lr_precision != RSGDF_FP64;
+  if (f32) HIPCHK(launch_to_f32(d_A.as<double>(), d_A32.as<float>(), naux * nq_tot * 2, st));
+  const int lr_nq_hi = kLrNqHi;
   for (int c = 0; c < nk; ++c) {
     const int nkpi = (int)cls_kp[c].size();
     const int64_t nqc = qoff[c + 1] - qoff[c];
@@ -1254,19 +1260,23 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
       pp.B = d_I.as<double>();
       pp.nterm = d_nterm.as<long long>();
       HIPCHK(launch_pairft_binned(pp, st));
-      HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.as<double>(), nk, nkpi, nq,
-                           nao2, st));
+      const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+      HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
+                           nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
       LRGemmParams gp{};
       gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
       gp.lda = nq_tot;
       gp.B = d_B.as<double>();
+      gp.A32 = f32 ? d_A32.as<float>() + 2 * (qoff[c] + q0) : nullptr;
+      gp.B32 = f32 ? d_B.as<float>() : nullptr;
+      gp.Bhi = nq_hi ? d_Bhi.as<double>() : nullptr;
       gp.out = d_out;
       gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
       gp.plane = naux * nao2;
       gp.naux = (int32_t)naux;
       gp.nq = nq;
       gp.nmn = (int32_t)nao2;
-      gp.nq_hi = (q0 == 0) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+      gp.nq_hi = nq_hi;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (gev) {
         HIPCHK(hipEventCreate(&e0));

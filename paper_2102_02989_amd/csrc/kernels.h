@@ -69,10 +69,17 @@ struct PairFTParams {
   long long *nterm;       // running count of transform evaluations
 };
 
+// leading q columns of each k12 class (the smallest |q|) that the reduced-precision
+// contraction forms take in FP64
+constexpr int kLrNqHi = 32;
+
 struct LRGemmParams {
   const double *A;        // complex, row P has stride lda (complex elements); columns q0.. of the class
   int64_t lda;
-  const double *B;        // complex [nkpi][nmn][nq]
+  const double *B;        // complex [nkpi][nmn][nq] (mode 0)
+  const float *A32;       // FP32 copy of A, same layout (modes 1, 2)
+  const float *B32;       // complex FP32 [nkpi][nmn][nq] (modes 1, 2)
+  const double *Bhi;      // complex FP64 [nkpi][nmn][nq_hi]: the FP64 columns of modes 1, 2
   double *out;            // complex [nkp][naux][nmn]
   const int32_t *kp_of;   // [nkpi] global k-pair index
   int64_t plane;          // naux * nmn
@@ -94,8 +101,9 @@ hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream);
 hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream);
 hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream);
 hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *amax, hipStream_t stream);
-hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,
-                         hipStream_t stream);
+hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
+                         int nkpi, int nq, int64_t nmn, hipStream_t stream);
+hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t stream);
 
 // learned screening (learned.hip)
 hipError_t launch_features(const SRParams &prm, int ntrip, const int64_t *idx, int64_t n, float *feat,

@@ -321,13 +321,20 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 // B[kpi][mn][q] = sum_c phase[kpi][c] I[c][mn][q], phase = e^{+i k2.L_c}; one
 // thread per (mn, q) element.  The k-pairs are taken 16 at a time with their
 // sums in registers, so each I value is read once per 16 k-pairs; the phases
-// are uniform over the wave (scalar loads).
+// are uniform over the wave (scalar loads).  F32: B is written as FP32 pairs
+// (the operand format of the reduced-precision contractions, half the bytes),
+// and the first nq_hi columns also in FP64 into Bhi[kpi][mn][nq_hi] (the
+// columns those forms contract in FP64).
 constexpr int KPH_KB = 16;
+template <bool F32>
 __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ I, const double *__restrict__ phase,
-                                                     double *__restrict__ B, int nk, int nkpi, int nq, int64_t nmn) {
+                                                     void *__restrict__ Bout, double *__restrict__ Bhi, int nq_hi,
+                                                     int nk, int nkpi, int nq, int64_t nmn) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ne = (int64_t)nq * nmn;
   if (gid >= ne) return;
+  const int q = (int)(gid % nq);
+  const int64_t mn = gid / nq;
   for (int k0 = 0; k0 < nkpi; k0 += KPH_KB) {
     double sr[KPH_KB], si[KPH_KB];
 #pragma unroll
@@ -345,18 +352,47 @@ __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ 
 #pragma unroll
     for (int kk = 0; kk < KPH_KB; ++kk)
       if (k0 + kk < nkpi) {
-        B[2 * ((int64_t)(k0 + kk) * ne + gid)] = sr[kk];
-        B[2 * ((int64_t)(k0 + kk) * ne + gid) + 1] = si[kk];
+        const int64_t o = (int64_t)(k0 + kk) * ne + gid;
+        if constexpr (F32) {
+          float *B = static_cast<float *>(Bout);
+          B[2 * o] = (float)sr[kk];
+          B[2 * o + 1] = (float)si[kk];
+          if (Bhi && q < nq_hi) {
+            const int64_t oh = ((int64_t)(k0 + kk) * nmn + mn) * nq_hi + q;
+            Bhi[2 * oh] = sr[kk];
+            Bhi[2 * oh + 1] = si[kk];
+          }
+        } else {
+          double *B = static_cast<double *>(Bout);
+          B[2 * o] = sr[kk];
+          B[2 * o + 1] = si[kk];
+        }
       }
   }
 }
 
-hipError_t launch_kphase(const double *I, const double *phase, double *B, int nk, int nkpi, int nq, int64_t nmn,
-                         hipStream_t stream) {
+hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
+                         int nkpi, int nq, int64_t nmn, hipStream_t stream) {
   const int64_t ne = (int64_t)nq * nmn;
   if (ne == 0 || nkpi == 0) return hipSuccess;
-  hipLaunchKernelGGL(kphase_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, I, phase, B, nk, nkpi,
-                     nq, nmn);
+  const dim3 grid((unsigned)((ne + 255) / 256));
+  if (f32)
+    hipLaunchKernelGGL(kphase_kernel<true>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+  else
+    hipLaunchKernelGGL(kphase_kernel<false>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+  return hipGetLastError();
+}
+
+// FP32 copy of an FP64 array (the aux operand of the reduced-precision forms)
+__global__ void to_f32_kernel(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  if ((n + 255) / 256 > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, y, n);
   return hipGetLastError();
 }
 
@@ -435,8 +471,11 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   if (t >= ntile) return;
   const int M0 = (t % mt) * BM, N0 = (t / mt) * TG_BN;
   const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
+  const float *Bk32 = gp.B32 + 2 * (size_t)kpi * gp.nq * gp.nmn;
   const int sr0 = tid >> 2, sq = (tid & 3) * 4;
-  double ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
+  // staged operands in their storage format: FP64 (mode 0) or FP32 (modes 1, 2)
+  typedef typename std::conditional<MODE == 0, double, float>::type ld_t;
+  ld_t ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
   auto gload = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -447,10 +486,15 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
         const int m = M0 + sr0 + r * (NT / 4);
         if (okk && m < gp.naux) {
           const size_t o = (size_t)m * gp.lda + k;
-          ga[r][2 * j] = gp.A[2 * o];
-          ga[r][2 * j + 1] = gp.A[2 * o + 1];
+          if constexpr (MODE == 0) {
+            ga[r][2 * j] = gp.A[2 * o];
+            ga[r][2 * j + 1] = gp.A[2 * o + 1];
+          } else {
+            ga[r][2 * j] = gp.A32[2 * o];
+            ga[r][2 * j + 1] = gp.A32[2 * o + 1];
+          }
         } else {
-          ga[r][2 * j] = ga[r][2 * j + 1] = 0.0;
+          ga[r][2 * j] = ga[r][2 * j + 1] = 0;
         }
       }
 #pragma unroll
@@ -458,10 +502,15 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
         const int n = N0 + sr0 + r * (NT / 4);
         if (okk && n < gp.nmn) {
           const size_t o = (size_t)n * gp.nq + k;
-          gb[r][2 * j] = Bk[2 * o];
-          gb[r][2 * j + 1] = Bk[2 * o + 1];
+          if constexpr (MODE == 0) {
+            gb[r][2 * j] = Bk[2 * o];
+            gb[r][2 * j + 1] = Bk[2 * o + 1];
+          } else {
+            gb[r][2 * j] = Bk32[2 * o];
+            gb[r][2 * j + 1] = Bk32[2 * o + 1];
+          }
         } else {
-          gb[r][2 * j] = gb[r][2 * j + 1] = 0.0;
+          gb[r][2 * j] = gb[r][2 * j + 1] = 0;
         }
       }
     }
@@ -476,12 +525,12 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
           S.ar[row][sq + j] = ga[r][2 * j];
           S.ai[row][sq + j] = ga[r][2 * j + 1];
         } else if constexpr (MODE == 1) {
-          S.ar[row][sq + j] = (float)ga[r][2 * j];
-          S.ai[row][sq + j] = (float)ga[r][2 * j + 1];
+          S.ar[row][sq + j] = ga[r][2 * j];
+          S.ai[row][sq + j] = ga[r][2 * j + 1];
         } else {
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const float f = (float)ga[r][2 * j + c];
+            const float f = ga[r][2 * j + c];
             const unsigned short h = lr_f2bf(f);
             S.a[2 * c][row][sq + j] = h;
             S.a[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
@@ -495,12 +544,12 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
           S.br[row][sq + j] = gb[r][2 * j];
           S.bi[row][sq + j] = gb[r][2 * j + 1];
         } else if constexpr (MODE == 1) {
-          S.br[row][sq + j] = (float)gb[r][2 * j];
-          S.bi[row][sq + j] = (float)gb[r][2 * j + 1];
+          S.br[row][sq + j] = gb[r][2 * j];
+          S.bi[row][sq + j] = gb[r][2 * j + 1];
         } else {
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
-            const float f = (float)gb[r][2 * j + c];
+            const float f = gb[r][2 * j + c];
             const unsigned short h = lr_f2bf(f);
             S.b[2 * c][row][sq + j] = h;
             S.b[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
@@ -533,9 +582,9 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int n = N0 + wn * 64 + c * 16 + li;
-        const size_t o = (size_t)n * gp.nq + k;
-        br[c] = (n < gp.nmn) ? Bk[2 * o] : 0.0;
-        bi[c] = (n < gp.nmn) ? Bk[2 * o + 1] : 0.0;
+        const size_t o = ((size_t)kpi * gp.nmn + n) * gp.nq_hi + k;
+        br[c] = (n < gp.nmn) ? gp.Bhi[2 * o] : 0.0;
+        bi[c] = (n < gp.nmn) ? gp.Bhi[2 * o + 1] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r)
