@@ -625,7 +625,9 @@ struct Job {
   DBuf d_outbuf;
   double *d_out = nullptr;
   std::vector<double> kph;
-  DBuf d_phi, d_kph, d_kdiag, d_SP, d_O, d_Smn;
+  DBuf d_kph, d_kdiag, d_SP, d_O, d_Smn, d_kp1, d_tk2, d_tkp, d_Y;
+  int ftiles = 0;         // k-pair tiles of the fold's second transform
+  int64_t fchunk = 1;     // output elements per fold pass
   // SR
   std::vector<int> batch_start;
   int nbatch = 0;
@@ -752,7 +754,8 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     d_out = d_outbuf.as<double>();
   }
 
-  // phase tables: Phi[kp][(c1,c2)] = e^{-i k1.L_c1} e^{+i k2.L_c2}; kphase[k][c] = e^{+i k.L_c}
+  // phase table kphase[k][c] = e^{+i k.L_c}; the fold's k-pair tiles: up to 16
+  // k-pairs (k1, k2) of one k2 each
   auto cell_ph = [&](int k, int c) {  // 2 pi sum_d j_d i_d / n_d
     const int j[3] = {k / (L.n[1] * L.n[2]), (k / L.n[2]) % L.n[1], k % L.n[2]};
     const int i[3] = {c / (L.n[1] * L.n[2]), (c / L.n[2]) % L.n[1], c % L.n[2]};
@@ -760,20 +763,27 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     for (int d = 0; d < 3; ++d) s += (long double)(j[d] * i[d] % L.n[d]) / L.n[d];
     return (double)(2.0L * 3.14159265358979323846264338327950288L * s);
   };
-  std::vector<double> phi((size_t)2 * nkp * nb);
   kph.assign((size_t)2 * nk * nk, 0.0);
-  for (int t = 0; t < nkp; ++t)
-    for (int c1 = 0; c1 < nk; ++c1)
-      for (int c2 = 0; c2 < nk; ++c2) {
-        const double ph = -cell_ph(hp.kp1[t], c1) + cell_ph(hp.kp2[t], c2);
-        phi[2 * ((size_t)t * nb + c1 * nk + c2)] = std::cos(ph);
-        phi[2 * ((size_t)t * nb + c1 * nk + c2) + 1] = std::sin(ph);
-      }
   for (int k = 0; k < nk; ++k)
     for (int c = 0; c < nk; ++c) {
       kph[2 * (k * nk + c)] = std::cos(cell_ph(k, c));
       kph[2 * (k * nk + c) + 1] = std::sin(cell_ph(k, c));
     }
+  {
+    std::vector<std::vector<int32_t>> by_k2(nk);
+    for (int t = 0; t < nkp; ++t) by_k2[hp.kp2[t]].push_back(t);
+    std::vector<int32_t> tk2, tkp;
+    for (int k2 = 0; k2 < nk; ++k2)
+      for (size_t i = 0; i < by_k2[k2].size(); i += 16) {
+        tk2.push_back(k2);
+        for (size_t j = i; j < i + 16; ++j) tkp.push_back(j < by_k2[k2].size() ? by_k2[k2][j] : -1);
+      }
+    ftiles = (int)tk2.size();
+    std::vector<int32_t> kp1(hp.kp1.begin(), hp.kp1.end());
+    HIPCHK(upload(d_tk2, tk2, st));
+    HIPCHK(upload(d_tkp, tkp, st));
+    HIPCHK(upload(d_kp1, kp1, st));
+  }
   std::vector<int32_t> kdiag(nkp);
   for (int t = 0; t < nkp; ++t) kdiag[t] = (hp.kp1[t] == hp.kp2[t]) ? hp.kp1[t] : -1;
   // S_P = int chi_P over all space (aux functions), Eq. M13b
@@ -800,7 +810,6 @@ int Job::prepare(hipStream_t st, double mem_frac) {
         SP[x.foff + ic] = v;
       }
   }
-  HIPCHK(upload(d_phi, phi, st));
   HIPCHK(upload(d_kph, kph, st));
   HIPCHK(upload(d_kdiag, kdiag, st));
   HIPCHK(upload(d_SP, SP, st));
@@ -837,6 +846,15 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   if (do_sr && (double)max_bf * nb * nao2 * 8.0 > 0.9 * (double)free_b)
     return fail(RSGDF_ENOMEM, "one aux shell's short-range scratch does not fit in device memory");
   if (do_sr) HIPCHK(d_X.alloc((size_t)max_bf * nb * nao2 * sizeof(double)));
+  if (do_sr) {  // the fold's intermediate Y: nk^2 complex values per element of a pass
+    size_t fr = 0, tt = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tt));
+    const double ybudget = std::min(0.25 * mem_frac * (double)fr, 8e9);
+    const int64_t per = (int64_t)nk * nk * 16;
+    fchunk = std::max<int64_t>(64, (int64_t)(ybudget / (double)per) / 64 * 64);
+    fchunk = std::min<int64_t>(fchunk, std::max<int64_t>(max_bf * nao2, 1));
+    HIPCHK(d_Y.alloc((size_t)fchunk * per));
+  }
 
   // triplets for all batches, grouped by (batch, lP, pair class)
   {
@@ -1201,19 +1219,25 @@ int Job::enqueue_fold(int b, hipStream_t st) {
   const SRParams prm = batch_params(b);
   const int64_t f0 = prm.aux_f0, nf = prm.naux_b;
   FoldParams fp{};
-  fp.phi = d_phi.as<double>();
+  fp.kph = d_kph.as<double>();
   fp.X = do_sr ? d_X.as<double>() : nullptr;
+  fp.Y = do_sr ? d_Y.as<double>() : nullptr;
   fp.out = d_out;
   fp.kdiag = d_kdiag.as<int32_t>();
+  fp.kp1 = d_kp1.as<int32_t>();
+  fp.tile_k2 = d_tk2.as<int32_t>();
+  fp.tile_kp = d_tkp.as<int32_t>();
   fp.SP = d_SP.as<double>() + f0;
   fp.Smn = do_g0 ? d_Smn.as<double>() : nullptr;
   fp.g0fac = do_g0 ? kPi / (hp.lt.L.vol * omega * omega) : 0.0;
   fp.ne = nf * nao2;
+  fp.echunk = do_sr ? fchunk : std::max<int64_t>(fp.ne, 1);
   fp.out_off = f0 * nao2;
   fp.plane = naux * nao2;
   fp.nkp = nkp;
-  fp.nb = nb;
+  fp.nk = nk;
   fp.nao2 = (int32_t)nao2;
+  fp.ntile = ftiles;
   HIPCHK(launch_fold(fp, st));
   return RSGDF_OK;
 }

@@ -2,11 +2,17 @@
 // G = 0 correction of Eq. (M12), and the lattice-summed overlaps S_{mu nu}(k)
 // of Eq. (M13c) it needs.
 //
-// The fold is a complex-by-real product
-//     out[kp][e] = sum_{b = (c1,c2)} Phi[kp][b] X[b][e],
-//     Phi[kp][(c1,c2)] = exp(-i k1.L_c1) exp(+i k2.L_c2),
-// over the output elements e = (P, mu, nu) of one aux batch, tiled through LDS.
-// Its epilogue subtracts pi/(Omega w^2) S_P S_{mu nu}(k) on the k1 == k2 pairs.
+// The phase of a BvK cell pair factorises, e^{-i k1.L_c1} e^{+i k2.L_c2}, so the
+// fold is two discrete Fourier transforms over the Nk cells instead of one
+// product over the Nk^2 cell pairs:
+//     Y[c1][k2][e]  = sum_c2 e^{+i k2.L_c2} X[c1][c2][e]          (real input)
+//     out[kp][e]    = sum_c1 e^{-i k1.L_c1} Y[c1][k2][e],  kp = (k1, k2), k1 <= k2
+// over the output elements e = (P, mu, nu) of one aux batch, taken in chunks of
+// E elements (Y holds Nk^2 complex values per element).  Both stages are tiled
+// through LDS: 64 elements x 16 transform outputs per workgroup, 32 cells per
+// stage.  Per element this is 2 Nk^3 + 4 Nk Nkp multiply-adds instead of
+// 2 Nk^2 Nkp.  The second stage's epilogue subtracts pi/(Omega w^2) S_P S_{mu nu}(k)
+// on the k1 == k2 pairs.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -15,67 +21,134 @@
 
 namespace rsgdf {
 
-constexpr int FOLD_TE = 64;   // elements per tile
-constexpr int FOLD_TK = 16;   // k-pairs per tile
-constexpr int FOLD_TB = 32;   // BvK cell pairs per LDS stage
+constexpr int FD_TE = 64;  // elements per tile
+constexpr int FD_TK = 16;  // transform outputs (k2, or k-pairs of one k2) per tile
+constexpr int FD_TC = 32;  // cells per LDS stage
 
-
-
-__global__ __launch_bounds__(256) void fold_kernel(const FoldParams fp) {
-  __shared__ double sX[FOLD_TB][FOLD_TE];
-  __shared__ double sPr[FOLD_TK][FOLD_TB], sPi[FOLD_TK][FOLD_TB];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // ty in [0,4): 4 k-pairs each
-  const int64_t e = (int64_t)blockIdx.x * FOLD_TE + tx;
-  const int kp0 = blockIdx.y * FOLD_TK;
+// stage 1: grid (element tiles of the chunk, k2 tiles, c1)
+__global__ __launch_bounds__(256) void fold_k2_kernel(const FoldParams fp, int64_t e0, int64_t E) {
+  __shared__ double sX[FD_TC][FD_TE];
+  __shared__ double sPr[FD_TK][FD_TC], sPi[FD_TK][FD_TC];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // ty in [0,4): 4 outputs each
+  const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
+  const int k20 = blockIdx.y * FD_TK, c1 = blockIdx.z, nk = fp.nk;
   double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-  if (fp.X) {
-    for (int b0 = 0; b0 < fp.nb; b0 += FOLD_TB) {
-      for (int i = threadIdx.x; i < FOLD_TB * FOLD_TE; i += 256) {
-        const int bb = i / FOLD_TE, ee = i % FOLD_TE;
-        const int64_t eg = (int64_t)blockIdx.x * FOLD_TE + ee;
-        sX[bb][ee] = (b0 + bb < fp.nb && eg < fp.ne) ? fp.X[(int64_t)(b0 + bb) * fp.ne + eg] : 0.0;
+  for (int c0 = 0; c0 < nk; c0 += FD_TC) {
+    for (int i = threadIdx.x; i < FD_TC * FD_TE; i += 256) {
+      const int cc = i / FD_TE, ee = i % FD_TE;
+      const int64_t eg = (int64_t)blockIdx.x * FD_TE + ee;
+      sX[cc][ee] = (c0 + cc < nk && eg < E) ? fp.X[(int64_t)(c1 * nk + c0 + cc) * fp.ne + e0 + eg] : 0.0;
+    }
+    for (int i = threadIdx.x; i < FD_TK * FD_TC; i += 256) {
+      const int kk = i / FD_TC, cc = i % FD_TC;
+      const bool ok = (k20 + kk < nk) && (c0 + cc < nk);
+      sPr[kk][cc] = ok ? fp.kph[2 * ((k20 + kk) * nk + c0 + cc)] : 0.0;
+      sPi[kk][cc] = ok ? fp.kph[2 * ((k20 + kk) * nk + c0 + cc) + 1] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int cc = 0; cc < FD_TC; ++cc) {
+      const double x = sX[cc][tx];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ar[j] += sPr[ty * 4 + j][cc] * x;
+        ai[j] += sPi[ty * 4 + j][cc] * x;
       }
-      for (int i = threadIdx.x; i < FOLD_TK * FOLD_TB; i += 256) {
-        const int kk = i / FOLD_TB, bb = i % FOLD_TB;
-        const bool ok = (kp0 + kk < fp.nkp) && (b0 + bb < fp.nb);
-        sPr[kk][bb] = ok ? fp.phi[2 * ((int64_t)(kp0 + kk) * fp.nb + b0 + bb)] : 0.0;
-        sPi[kk][bb] = ok ? fp.phi[2 * ((int64_t)(kp0 + kk) * fp.nb + b0 + bb) + 1] : 0.0;
+    }
+    __syncthreads();
+  }
+  if (e >= E) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k2 = k20 + ty * 4 + j;
+    if (k2 >= nk) continue;
+    const int64_t o = ((int64_t)c1 * nk + k2) * E + e;
+    fp.Y[2 * o] = ar[j];
+    fp.Y[2 * o + 1] = ai[j];
+  }
+}
+
+// stage 2: grid (element tiles of the chunk, k-pair tiles); a tile holds up to
+// 16 k-pairs (k1, k2) sharing k2, so the staged Y rows serve all of them
+__global__ __launch_bounds__(256) void fold_k1_kernel(const FoldParams fp, int64_t e0, int64_t E) {
+  __shared__ double sYr[FD_TC][FD_TE], sYi[FD_TC][FD_TE];
+  __shared__ double sPr[FD_TK][FD_TC], sPi[FD_TK][FD_TC];
+  __shared__ int sK1[FD_TK];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
+  const int tile = blockIdx.y, nk = fp.nk;
+  const int k2 = fp.tile_k2[tile];
+  if (threadIdx.x < FD_TK) {
+    const int kp = fp.tile_kp[tile * FD_TK + threadIdx.x];
+    sK1[threadIdx.x] = kp >= 0 ? fp.kp1[kp] : -1;
+  }
+  __syncthreads();
+  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  if (fp.Y) {
+    for (int c0 = 0; c0 < nk; c0 += FD_TC) {
+      for (int i = threadIdx.x; i < FD_TC * FD_TE; i += 256) {
+        const int cc = i / FD_TE, ee = i % FD_TE;
+        const int64_t eg = (int64_t)blockIdx.x * FD_TE + ee;
+        const bool ok = c0 + cc < nk && eg < E;
+        const int64_t o = ((int64_t)(c0 + cc) * nk + k2) * E + eg;
+        sYr[cc][ee] = ok ? fp.Y[2 * o] : 0.0;
+        sYi[cc][ee] = ok ? fp.Y[2 * o + 1] : 0.0;
+      }
+      for (int i = threadIdx.x; i < FD_TK * FD_TC; i += 256) {
+        const int kk = i / FD_TC, cc = i % FD_TC;
+        const int k1 = sK1[kk];
+        const bool ok = k1 >= 0 && c0 + cc < nk;  // e^{-i k1.L_c1} = conj of the table entry
+        sPr[kk][cc] = ok ? fp.kph[2 * (k1 * nk + c0 + cc)] : 0.0;
+        sPi[kk][cc] = ok ? -fp.kph[2 * (k1 * nk + c0 + cc) + 1] : 0.0;
       }
       __syncthreads();
 #pragma unroll 8
-      for (int bb = 0; bb < FOLD_TB; ++bb) {
-        const double x = sX[bb][tx];
+      for (int cc = 0; cc < FD_TC; ++cc) {
+        const double yr = sYr[cc][tx], yi = sYi[cc][tx];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          ar[j] += sPr[ty * 4 + j][bb] * x;
-          ai[j] += sPi[ty * 4 + j][bb] * x;
+          const double pr = sPr[ty * 4 + j][cc], pi = sPi[ty * 4 + j][cc];
+          ar[j] += pr * yr - pi * yi;
+          ai[j] += pr * yi + pi * yr;
         }
       }
       __syncthreads();
     }
   }
-  if (e >= fp.ne) return;
+  if (e >= E) return;
+  const int64_t eb = e0 + e;  // element index within the aux batch
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int kp = kp0 + ty * 4 + j;
-    if (kp >= fp.nkp) continue;
+    const int kp = fp.tile_kp[tile * FD_TK + ty * 4 + j];
+    if (kp < 0) continue;
     double vr = ar[j], vi = ai[j];
     const int k = fp.kdiag[kp];
     if (k >= 0 && fp.g0fac != 0.0) {
-      const int64_t P = e / fp.nao2, mn = e - P * fp.nao2;
+      const int64_t P = eb / fp.nao2, mn = eb - P * fp.nao2;
       const double s = fp.g0fac * fp.SP[P];
       vr -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn)];
       vi -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn) + 1];
     }
-    const int64_t o = (int64_t)kp * fp.plane + fp.out_off + e;
+    const int64_t o = (int64_t)kp * fp.plane + fp.out_off + eb;
     fp.out[2 * o] = vr;
     fp.out[2 * o + 1] = vi;
   }
 }
 
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream) {
-  dim3 grid((unsigned)((fp.ne + FOLD_TE - 1) / FOLD_TE), (unsigned)((fp.nkp + FOLD_TK - 1) / FOLD_TK));
-  hipLaunchKernelGGL(fold_kernel, grid, dim3(256), 0, stream, fp);
+  if (fp.ne == 0 || fp.ntile == 0) return hipSuccess;
+  if (fp.echunk < 1 || (fp.X && !fp.Y)) return hipErrorInvalidValue;
+  for (int64_t e0 = 0; e0 < fp.ne; e0 += fp.echunk) {
+    const int64_t E = fp.ne - e0 < fp.echunk ? fp.ne - e0 : fp.echunk;
+    const int64_t nt = (E + FD_TE - 1) / FD_TE;
+    if (nt > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if (fp.X)
+      hipLaunchKernelGGL(fold_k2_kernel, dim3((unsigned)nt, (unsigned)((fp.nk + FD_TK - 1) / FD_TK), (unsigned)fp.nk),
+                         dim3(256), 0, stream, fp, e0, E);
+    FoldParams f2 = fp;
+    if (!fp.X) f2.Y = nullptr;  // no short-range part: zeros plus the G = 0 term
+    hipLaunchKernelGGL(fold_k1_kernel, dim3((unsigned)nt, (unsigned)fp.ntile), dim3(256), 0, stream, f2, e0, E);
+  }
   return hipGetLastError();
 }
 

@@ -9,17 +9,22 @@
 namespace rsgdf {
 
 struct FoldParams {
-  const double *phi;      // complex [nkp][nb]
-  const double *X;        // real [nb][ne] (may be null: no SR part)
+  const double *kph;      // complex [nk][nk]: e^{+i k.L_c}
+  const double *X;        // real [nb = nk^2][ne] (may be null: no SR part)
+  double *Y;              // complex [nk][nk][echunk] scratch between the two transforms
   double *out;            // complex [nkp][naux][nao][nao]
   const int32_t *kdiag;   // [nkp]: k index if k1 == k2 else -1
+  const int32_t *kp1;     // [nkp]: k1 of each k-pair
+  const int32_t *tile_k2; // [ntile]: k2 of the tile's k-pairs
+  const int32_t *tile_kp; // [ntile][16]: k-pair indices of the tile, -1 padded
   const double *SP;       // [naux_b] lattice-free aux integrals int chi_P
   const double *Smn;      // complex [nk][nao*nao]
   double g0fac;           // pi / (Omega w^2), 0 disables the G = 0 term
   int64_t ne;             // naux_b * nao * nao
+  int64_t echunk;         // elements per pass (Y capacity)
   int64_t out_off;        // aux_f0 * nao * nao
   int64_t plane;          // naux * nao * nao
-  int32_t nkp, nb, nao2, pad;
+  int32_t nkp, nk, nao2, ntile;
 };
 
 struct OvlParams {
