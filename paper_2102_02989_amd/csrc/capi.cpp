@@ -584,14 +584,20 @@ uint64_t splitmix64(uint64_t x) {
 }
 
 // four side streams per device for concurrent class launches (default priority)
-int side_streams(std::vector<hipStream_t> &ss) {
+// n non-blocking side streams of the current device (created once per thread
+// and device, default priority).  The single-cell build forks its short-range
+// classes onto 3 of them: with the calling stream that is one stream per
+// hardware queue at HIP's default of 4 queues per process (measured on C2:
+// 3.04 s SR with 3, 3.24 s with 4, where two streams share a queue); graph
+// replays schedule their own nodes and use 4.
+int side_streams(std::vector<hipStream_t> &ss, size_t n) {
   static thread_local std::vector<std::pair<int, hipStream_t>> pool;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   ss.clear();
   for (auto &pr_ : pool)
-    if (pr_.first == dev) ss.push_back(pr_.second);
-  while (ss.size() < 4) {
+    if (pr_.first == dev && ss.size() < n) ss.push_back(pr_.second);
+  while (ss.size() < n) {
     hipStream_t s_;
     HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
     pool.push_back({dev, s_});
@@ -1461,10 +1467,10 @@ int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
   int rc = j.prepare(st, 0.45);
   if (rc) return rc;
   std::vector<hipStream_t> ss;
-  if ((rc = side_streams(ss))) return rc;
+  if ((rc = side_streams(ss, 3))) return rc;
   EventSet ev, evs;
   if ((rc = ev.make(6, 0))) return rc;
-  if ((rc = evs.make(5, hipEventDisableTiming))) return rc;
+  if ((rc = evs.make((int)ss.size() + 1, hipEventDisableTiming))) return rc;
   if ((rc = j.enqueue_pre(st))) return rc;
   for (int b = 0; b < j.nbatch; ++b) {
     HIPCHK(hipEventRecord(ev.e[0], st));
@@ -1574,9 +1580,9 @@ int batch_capture(rsgdf_batch &B) {
   HIPCHK(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
   hipStream_t st = B.cap;
   std::vector<hipStream_t> ss;
-  int rc = side_streams(ss);
+  int rc = side_streams(ss, 4);
   if (rc) return rc;
-  if ((rc = B.evs.make(5, hipEventDisableTiming))) return rc;
+  if ((rc = B.evs.make((int)ss.size() + 1, hipEventDisableTiming))) return rc;
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   auto body = [&]() -> int {
     int r;
