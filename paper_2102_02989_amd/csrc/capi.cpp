@@ -1193,13 +1193,15 @@ int Job::enqueue_sr(int b, hipStream_t st, const std::vector<hipStream_t> &ss, h
   for (int g = 0; g < 24; ++g) order[g] = g;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return wgrp_cost[(size_t)b * 24 + x] > wgrp_cost[(size_t)b * 24 + y]; });
-  int k = 0;
+  // heaviest class first, each onto the side stream with the least estimated work so far
+  std::vector<double> load(ss.size(), 0.0);
   for (int g : order) {
     const int w0 = wgrp_off[(size_t)b * 24 + g], w1 = wgrp_off[(size_t)b * 24 + g + 1];
     if (w1 == w0) continue;
+    const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[k] += wgrp_cost[(size_t)b * 24 + g];
     HIPCHK(launch_sr3c(g / 6, g % 6, d_prm.as<SRParams>() + b, d_work.as<SRWork>(), d_cnt.as<long long>(), w0,
-                       w1 - w0, ss[k % ss.size()]));
-    ++k;
+                       w1 - w0, ss[k]));
   }
   for (size_t i = 0; i < ss.size(); ++i) {
     HIPCHK(hipEventRecord(evj[i], ss[i]));
@@ -1594,13 +1596,14 @@ int batch_capture(rsgdf_batch &B) {
     std::vector<int> order(24);
     for (int g = 0; g < 24; ++g) order[g] = g;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return B.cls_cost[x] > B.cls_cost[y]; });
-    int k = 0;
+    std::vector<double> load(ss.size(), 0.0);  // least-loaded side stream first
     for (int g : order) {
       const int w0 = B.cls_off[g], w1 = B.cls_off[g + 1];
       if (w1 == w0) continue;
+      const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += B.cls_cost[g];
       HIPCHK(launch_sr3c(g / 6, g % 6, B.d_prm.as<SRParams>(), B.d_work.as<SRWork>(), B.d_cnt.as<long long>(), w0,
-                         w1 - w0, ss[k % ss.size()]));
-      ++k;
+                         w1 - w0, ss[k]));
     }
     for (size_t i = 0; i < ss.size(); ++i) {
       HIPCHK(hipEventRecord(B.evs.e[1 + i], ss[i]));
