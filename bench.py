@@ -188,7 +188,7 @@ def main():
                                              "n_triplets", "n_screen_candidates", "n_screen_skipped")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic,
-                     "kernel": "sr3c_kernel (the 24 angular-momentum classes of one plain build, on 4 streams)",
+                     "kernel": "sr3c_kernel (the 24 angular-momentum classes of one plain build, on 3 side streams)",
                      "flops_per_launch": flops, "avg_launch_ms": t_sr},
         "cpu_baseline": None,
     }
