@@ -59,7 +59,7 @@ def lib():
         L.orc_overlap.argtypes = [i, i, d, P, i, i, d, P]
         L.orc_j3c.restype = i
         L.orc_j3c.argtypes = [P, i, P, i, P, P, P, P, P, P, i, P, P, P, P, P, P, P, d, d, d, i, i, i, P, i, P,
-                              P, P]
+                              i, P, P, P]
         L.orc_num_threads.restype = i
         _lib = L
     return _lib
@@ -109,14 +109,14 @@ def nkpairs(kmesh, all_pairs=False):
 
 
 def j3c(problem, omega=None, cut=1e-15, g_thr=None, parts=PART_ALL, all_pairs=False, aux_shells=None,
-        pairs=None, return_counts=False):
+        pairs=None, kpairs=None, return_counts=False):
     """Oracle three-center integrals for ``problem`` (a ``synth.Problem``).
 
     Returns complex128 [nkpair][naux][nao][nao]; k-pairs are k1 <= k2 in
     row-major upper-triangle order (or all ordered pairs with all_pairs=True).
     ``cut`` is the oracle's own per-term truncation (1s model with polynomial
-    growth factors, see oracle.c); ``aux_shells``/``pairs`` restrict the work
-    (unselected entries stay zero)."""
+    growth factors, see oracle.c); ``aux_shells``/``pairs``/``kpairs`` (k-pair
+    indices) restrict the work (unselected entries stay zero)."""
     omega = problem.omega if omega is None else omega
     g_thr = problem.g_thr if g_thr is None else g_thr
     cell, bs, ax = problem.cell, problem.basis, problem.aux
@@ -131,6 +131,11 @@ def j3c(problem, omega=None, cut=1e-15, g_thr=None, parts=PART_ALL, all_pairs=Fa
     else:
         psel = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1))
         npsel = len(psel) // 2
+    if kpairs is None:
+        ksel, nksel = np.zeros(1, np.int32), -1
+    else:
+        ksel = np.ascontiguousarray(np.asarray(kpairs, np.int32).reshape(-1))
+        nksel = len(ksel)
     nkp = nkpairs(problem.kmesh, all_pairs)
     out = np.zeros((nkp, ax.nfunc, bs.nfunc, bs.nfunc), np.complex128)
     counts = np.zeros(2, np.int64)
@@ -139,8 +144,8 @@ def j3c(problem, omega=None, cut=1e-15, g_thr=None, parts=PART_ALL, all_pairs=Fa
     arrs = [np.ascontiguousarray(a) for a in arrs]
     rc = lib().orc_j3c(_ptr(lat), cell.natm, _ptr(crd), bs.nshell, *[_ptr(a) for a in arrs[:6]], ax.nshell,
                        *[_ptr(a) for a in arrs[6:]], _ptr(km), float(omega), float(cut), float(g_thr), int(parts),
-                       int(bool(all_pairs)), len(aux_shells), _ptr(aux_shells), npsel, _ptr(psel), _ptr(out),
-                       _ptr(counts))
+                       int(bool(all_pairs)), len(aux_shells), _ptr(aux_shells), npsel, _ptr(psel), nksel, _ptr(ksel),
+                       _ptr(out), _ptr(counts))
     if rc:
         raise RuntimeError(f"orc_j3c failed ({rc})")
     if return_counts:

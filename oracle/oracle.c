@@ -496,6 +496,7 @@ static void bvk_of(const int *mm, const int *kmesh, int *cidx) {
  *   naux_sel, aux_sel : aux shells to compute (others left zero),
  *   npair_sel, pair_sel[2*npair_sel] : AO shell pairs (mu, nu) to compute
  *                  (npair_sel < 0 means all),
+ *   nkp_sel, kp_sel[nkp_sel] : k-pair indices to compute (nkp_sel < 0 means all),
  *   out          : complex128 [nkpair][naux][nao][nao], interleaved re/im,
  *                  zero-filled by the caller,
  *   counts[2]    : SR primitive-triplet image terms, LR pair-FT evaluations.
@@ -505,8 +506,8 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
             const double *bs_coefs, int nax, const int32_t *ax_atom, const int32_t *ax_l,
             const int32_t *ax_nprim, const int32_t *ax_ptr, const double *ax_exps, const double *ax_coefs,
             const int32_t *kmesh, double omega, double cut, double g_thr, int parts, int all_pairs,
-            int naux_sel, const int32_t *aux_sel, int npair_sel, const int32_t *pair_sel, double *out,
-            int64_t *counts) {
+            int naux_sel, const int32_t *aux_sel, int npair_sel, const int32_t *pair_sel, int nkp_sel,
+            const int32_t *kp_sel, double *out, int64_t *counts) {
   orc_lat L;
   if (make_lattice(lattice, &L)) return -1;
   if (!(omega > 0.0) || !(cut > 0.0) || !(g_thr > 0.0)) return -1;
@@ -543,6 +544,13 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
         kp1[t] = k1; kp2[t] = k2; ++t;
       }
   }
+
+  /* k-pair selection mask (unselected k-pairs stay zero) */
+  char *kmask = (char *)calloc((size_t)nkp, 1);
+  if (nkp_sel < 0) memset(kmask, 1, (size_t)nkp);
+  else
+    for (int i = 0; i < nkp_sel; ++i)
+      if (kp_sel[i] >= 0 && kp_sel[i] < nkp) kmask[kp_sel[i]] = 1;
 
   /* pair selection mask */
   char *pmask = (char *)calloc((size_t)nbs * nbs, 1);
@@ -659,6 +667,7 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
               }
           /* direct double DFT over the BvK cells (Eq. M14) */
           for (int t = 0; t < nkp; ++t) {
+            if (!kmask[t]) continue;
             const int k1 = kp1[t], k2 = kp2[t];
             for (int cm = 0; cm < nk; ++cm)
               for (int cn = 0; cn < nk; ++cn) {
@@ -688,7 +697,7 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
         /* ---------------- G = 0 correction on k1 == k2 (Eq. M12, M13b-c) */
         if (parts & ORC_PART_G0) {
           for (int t = 0; t < nkp; ++t) {
-            if (kp1[t] != kp2[t]) continue;
+            if (kp1[t] != kp2[t] || !kmask[t]) continue;
             const double *k = kv + 3 * kp1[t];
             for (int ic = 0; ic < ncP; ++ic) {
               double SP = 0.0;
@@ -778,6 +787,7 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
       double *rho = (double *)malloc(sizeof(double) * 2 * nca * ncb);
       double *blk = (double *)malloc(sizeof(double) * 2 * nca * ncb);
       for (int t = 0; t < nkp; ++t) {
+        if (!kmask[t]) continue;
         const double *k1v = kv + 3 * kp1[t], *k2v = kv + 3 * kp2[t];
         double k12[3];
         for (int d = 0; d < 3; ++d) k12[d] = k2v[d] - k1v[d];
@@ -858,7 +868,7 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
     counts[0] = nsr;
     counts[1] = nlr;
   }
-  free(aoff); free(xoff); free(kv); free(kj); free(kp1); free(kp2); free(pmask);
+  free(aoff); free(xoff); free(kv); free(kj); free(kp1); free(kp2); free(pmask); free(kmask);
   return err ? -2 : 0;
 }
 

@@ -305,3 +305,19 @@ def test_table_s1_nk12_golden():
 def test_kpair_counts():
     assert oracle.nkpairs((2, 2, 2)) == 36
     assert [oracle.nkpairs((n, n, n)) for n in range(1, 6)] == [1, 36, 378, 2080, 7875]
+
+
+def test_selection_restricts_work_only():
+    """aux shell, AO pair and k-pair selections return exactly the full
+    result on the selected entries and zeros elsewhere."""
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.8, diffuse=False)
+    full = oracle.j3c(p)
+    aux, pairs, kps = [1, 3], [(0, 3), (1, 1)], [0, 2]
+    got = oracle.j3c(p, aux_shells=aux, pairs=pairs, kpairs=kps)
+    xo, bo = p.aux.offsets(), p.basis.offsets()
+    mask = np.zeros(full.shape, bool)
+    for P in aux:
+        for mu, nu in pairs:
+            mask[kps, xo[P]:xo[P + 1], bo[mu]:bo[mu + 1], bo[nu]:bo[nu + 1]] = True
+    assert np.array_equal(got[mask], full[mask])
+    assert not np.any(got[~mask])
