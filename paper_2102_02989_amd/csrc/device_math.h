@@ -1,6 +1,6 @@
 // device_math.h -- gfx950 device building blocks of the three-center
-// integrals: attenuated Boys values, McMurchie-Davidson Hermite expansion
-// coefficients and Hermite Coulomb integrals R_tuv.
+// integrals: McMurchie-Davidson Hermite expansion coefficients and Hermite
+// Coulomb integrals R_tuv (the Boys values are in sr3c.hip).
 //
 // Everything is templated on angular momenta so that all array indices are
 // compile-time constants and the working sets live in VGPRs.
@@ -38,58 +38,12 @@ __host__ __device__ constexpr int cart_ly(int l, int i) {
 }
 __host__ __device__ constexpr int cart_lz(int l, int i) { return l - cart_lx(l, i) - cart_ly(l, i); }
 
-// F_n(T), n = 0..L, for T >= kBoysSwitch: F_0 = sqrt(pi/T)/2 (erf(sqrt T) = 1
-// to 2e-17 there) and the exact upward recursion
-// F_{n+1} = ((2n+1) F_n - e^{-T}) / (2T), stable for T > L.
-template <int L>
-__device__ __forceinline__ void boys_large(double T, double (&F)[L + 1]) {
-  const double iT = 1.0 / T;
-  F[0] = 0.886226925452758013649083741671 * sqrt(iT); /* sqrt(pi)/2 */
-  if (L > 0) {
-    const double e = (T < 50.0) ? exp(-T) : 0.0;
-#pragma unroll
-    for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * (0.5 * iT);
-  }
-}
-
 // Hermite Coulomb integrals R_tuv (t+u+v <= L) at X = P - C from
 // g[n] = (-2 rho)^n G_n: R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X R^(n+1)_{t,u,v}
-// (and likewise in y, z), evaluated in place from n = L down to 0.
-template <int L>
-__device__ __forceinline__ void hermite_R(double X, double Y, double Z, const double (&g)[L + 1],
-                                          double (&R)[nherm(L)]) {
-  R[0] = g[L];
-#pragma unroll
-  for (int n = L - 1; n >= 0; --n) {
-#pragma unroll
-    for (int s = L - n; s >= 1; --s) {
-#pragma unroll
-      for (int t = s; t >= 0; --t) {
-#pragma unroll
-        for (int u = s - t; u >= 0; --u) {
-          const int v = s - t - u;
-          double val;
-          if (t > 0) {
-            val = X * R[hidx(t - 1, u, v)];
-            if (t > 1) val += (t - 1) * R[hidx(t - 2, u, v)];
-          } else if (u > 0) {
-            val = Y * R[hidx(t, u - 1, v)];
-            if (u > 1) val += (u - 1) * R[hidx(t, u - 2, v)];
-          } else {
-            val = Z * R[hidx(t, u, v - 1)];
-            if (v > 1) val += (v - 1) * R[hidx(t, u, v - 2)];
-          }
-          R[hidx(t, u, v)] = val;
-        }
-      }
-    }
-    R[0] = g[n];
-  }
-}
-
-// As hermite_R<L> but adds R^(0)_tuv into Racc: levels n >= 1 are built in a
-// scratch array of nherm(L-1) entries; level 0 is formed and accumulated
-// directly, shell by shell from the top (it only reads level-1 values).
+// (and likewise in y, z), evaluated in place from n = L down to 0, with
+// R^(0)_tuv added into Racc: levels n >= 1 are built in a scratch array of
+// nherm(L-1) entries; level 0 is formed and accumulated directly, shell by
+// shell from the top (it only reads level-1 values).
 template <int L>
 __device__ __forceinline__ void hermite_R_acc(double X, double Y, double Z, const double (&g)[L + 1],
                                               double (&Racc)[nherm(L)]) {
@@ -151,7 +105,7 @@ __device__ __forceinline__ void hermite_R_acc(double X, double Y, double Z, cons
   }
 }
 
-// Static FP64 operation count of hermite_R<L> (one multiply or add = 1).
+// Static FP64 operation count of the recursion of hermite_R_acc<L> (one multiply or add = 1).
 __host__ __device__ constexpr int hermite_R_flops(int L) {
   int f = 0;
   for (int n = L - 1; n >= 0; --n)

@@ -165,9 +165,12 @@ __device__ __forceinline__ void boys_large_e(double T, double e, double (&F)[L +
   for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
 }
 
-// G_n = F_n(T) - theta^{2n+1} F_n(theta^2 T) (erfc operator, see device_math.h);
-// zero once theta^2 T >= kBoysSwitch (both terms share their asymptote to
-// within e^{-theta^2 T}).
+// Boys values of the attenuated operator erfc(w r)/r = 1/r - erf(w r)/r: the
+// erf part of a primitive triple with reduced exponent rho is the Coulomb
+// part at exponent rho w^2/(rho + w^2), that is at T theta^2 with
+// theta^2 = w^2/(w^2 + rho), scaled by theta^{2n+1} for order n; so
+// G_n = F_n(T) - theta^{2n+1} F_n(theta^2 T), set to zero once
+// theta^2 T >= kBoysSwitch (both terms share their asymptote to within e^{-theta^2 T}).
 template <int L>
 __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const double *__restrict__ tab,
                                          const double *__restrict__ etab, double (&G)[L + 1]) {
