@@ -86,3 +86,26 @@ def test_c2_diagonal_kpairs_hermitian():
     _say("  max Hermitian defect", err, "max |Im V(Gamma, Gamma)|", im0, "max |V|", float(out.abs().max()))
     assert err <= TOL
     assert im0 <= TOL
+
+
+def test_large_mesh_sampled_kpairs():
+    """A 4x3x3 mesh (36 k-points, 666 k-pairs): more cells than one LDS stage of
+    the fold's transforms holds, several k2 tiles, and k2 values with more than
+    16 k-pairs; the oracle checks a spread of k-pairs.  This triclinic cell with
+    d shells carries the short-range screening error of about 1e-8 at
+    thresh = 1e-10 (the bounds are estimates, not rigorous upper bounds), so the
+    bar is checked at thresh = 1e-11, and the error must fall with thresh (a
+    fault in the fold would not)."""
+    p = synth.tiny_problem(kmesh=(4, 3, 3), omega=0.8, diffuse=False)
+    nkp = oracle.nkpairs(p.kmesh)
+    sel = sorted({0, 1, 17, 35, 36, 200, 401, nkp - 2, nkp - 1})
+    _say("case tiny cell 4x3x3 mesh, k-pairs", sel)
+    ref = oracle.j3c(p, kpairs=sel)
+    errs = {}
+    for thresh in (1e-10, 1e-11):
+        got, st = run_gpu(p, thresh=thresh)
+        assert got.shape[0] == nkp == 666
+        errs[thresh] = max_err(got[sel], ref[sel])
+        _say("  thresh", thresh, "max err", errs[thresh], "max |ref|", np.abs(ref[sel]).max())
+    assert errs[1e-11] <= TOL
+    assert errs[1e-11] < errs[1e-10] / 3
