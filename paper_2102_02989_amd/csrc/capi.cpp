@@ -196,9 +196,16 @@ double f_sr(double R, double eta1, double eta2) {  // Eq. S7
   return (std::erf(eta1 * R) - std::erf(eta2 * R)) / R;
 }
 
-// largest R > 0 with K exp(-eta^2 R^2)/R >= eps (Eq. S14); the left side is decreasing
-double solve_rc(double K, double eta, double eps) {
-  auto g = [&](double R) { return std::log(K) - eta * eta * R * R - std::log(R) - std::log(eps); };
+// largest R > 0 with K (1 + 2 eta R)^L exp(-eta^2 R^2)/R >= eps: the bound of Eq. S14
+// with the growth of an angular momentum L = l_P + l_a + l_b term, whose
+// Gaussian tail carries a degree-L polynomial (the L-th Hermite derivative of
+// exp(-eta^2 R^2) is (2 eta^2 R)^L exp(-eta^2 R^2) times 1 + O(1/R^2)), which the
+// s-type model of Eq. S14 leaves out.  The left side rises at most once and
+// then decreases, so bisection from a point where it holds finds the cut.
+double solve_rc(double K, double eta, double eps, int L) {
+  auto g = [&](double R) {
+    return std::log(K) + L * std::log1p(2.0 * eta * R) - eta * eta * R * R - std::log(R) - std::log(eps);
+  };
   double lo = 1e-8, hi = 1.0;
   if (g(lo) < 0) return lo;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
@@ -451,7 +458,7 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
       const double eta1 = std::sqrt(sP.a_d * pd / (sP.a_d + pd));
       const double eta2 = 1.0 / std::sqrt(1.0 / (eta1 * eta1) + 1.0 / (omega * omega));
       const double K = Aamp * Sh[ip] * 4.0 * kPi / L.vol / (std::sqrt(kPi) * 2.0 * eta2 * eta2 * eta2);
-      const double rc = solve_rc(K, eta2, thresh);
+      const double rc = solve_rc(K, eta2, thresh, sP.l + sA.l + sB.l);
       hp.rc_t[t] = rc;
       const int W = std::max(1, (int)std::ceil(rc / S.dR));
       double nfmax = 0.0;
