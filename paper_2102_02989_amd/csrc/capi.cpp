@@ -630,6 +630,9 @@ struct Job {
   std::vector<float> split;  // per-class work-split factors (24), empty = 1
   // ---- plan
   HostPlan hp;
+  bool planned = false;      // hp already built (batches plan their cells on worker threads)
+  int plan_rc = 0;
+  std::string plan_err;
   int nk = 0, nkp = 0, npair = 0, nxs = 0, nb = 0;
   int64_t nao = 0, naux = 0, nao2 = 0, need = 0;
   double t_plan = 0.0;
@@ -641,6 +644,8 @@ struct Job {
   DBuf d_kph, d_kdiag, d_SP, d_O, d_Smn, d_kp1, d_tk2, d_tkp, d_Y;
   int ftiles = 0;         // k-pair tiles of the fold's second transform
   int64_t fchunk = 1;     // output elements per fold pass
+  double *ybuf = nullptr; // the fold's intermediate: d_Y, or a batch's shared buffer
+  bool own_y = true;      // false: the batch allocates one Y for all its cells (their folds run in turn)
   // SR
   std::vector<int> batch_start;
   int nbatch = 0;
@@ -668,6 +673,14 @@ struct Job {
   std::vector<long long> counts;  // per work item [4], filled by finish()
 
   int prepare(hipStream_t st, double mem_frac);
+  // elements per fold pass for a Y buffer of ybytes (at least one tile, at most
+  // the largest aux batch); the bytes that takes: fchunk * nk^2 * 16
+  void set_fold_chunk(double ybytes) {
+    const int64_t per = (int64_t)nk * nk * 16;
+    fchunk = std::max<int64_t>(64, (int64_t)(ybytes / (double)per) / 64 * 64);
+    fchunk = std::min<int64_t>(fchunk, std::max<int64_t>(max_bf_el, 1));
+  }
+  int64_t max_bf_el = 0;  // output elements of the largest aux batch
   SRParams batch_params(int b) const;
   int enqueue_pre(hipStream_t st);
   int enqueue_zero(int b, hipStream_t st);
@@ -710,7 +723,8 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       if (!(f > 0.f) || !std::isfinite(f)) return fail(RSGDF_EINVAL, "sr_split factors must be > 0");
   }
 
-  int rc = build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
+  if (planned && plan_rc) return fail(plan_rc, plan_err);
+  int rc = planned ? RSGDF_OK : build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
   if (rc) return rc;
   // host sources of asynchronous uploads stay alive until the final synchronise
   std::vector<SRParams> prms;
@@ -859,14 +873,13 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   if (do_sr && (double)max_bf * nb * nao2 * 8.0 > 0.9 * (double)free_b)
     return fail(RSGDF_ENOMEM, "one aux shell's short-range scratch does not fit in device memory");
   if (do_sr) HIPCHK(d_X.alloc((size_t)max_bf * nb * nao2 * sizeof(double)));
-  if (do_sr) {  // the fold's intermediate Y: nk^2 complex values per element of a pass
+  max_bf_el = max_bf * nao2;
+  if (do_sr && own_y) {  // the fold's intermediate Y: nk^2 complex values per element of a pass
     size_t fr = 0, tt = 0;
     HIPCHK(hipMemGetInfo(&fr, &tt));
-    const double ybudget = std::min(0.25 * mem_frac * (double)fr, 8e9);
-    const int64_t per = (int64_t)nk * nk * 16;
-    fchunk = std::max<int64_t>(64, (int64_t)(ybudget / (double)per) / 64 * 64);
-    fchunk = std::min<int64_t>(fchunk, std::max<int64_t>(max_bf * nao2, 1));
-    HIPCHK(d_Y.alloc((size_t)fchunk * per));
+    set_fold_chunk(std::min(0.25 * mem_frac * (double)fr, 8e9));
+    HIPCHK(d_Y.alloc((size_t)fchunk * nk * nk * 16));
+    ybuf = d_Y.as<double>();
   }
 
   // triplets for all batches, grouped by (batch, lP, pair class)
@@ -1236,7 +1249,7 @@ int Job::enqueue_fold(int b, hipStream_t st) {
   FoldParams fp{};
   fp.kph = d_kph.as<double>();
   fp.X = do_sr ? d_X.as<double>() : nullptr;
-  fp.Y = do_sr ? d_Y.as<double>() : nullptr;
+  fp.Y = do_sr ? ybuf : nullptr;
   fp.out = d_out;
   fp.kdiag = d_kdiag.as<int32_t>();
   fp.kp1 = d_kp1.as<int32_t>();
@@ -1566,7 +1579,7 @@ int tune_trial(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_bas
 // The whole device sequence is captured once into a graph and replayed.
 struct rsgdf_batch {
   std::vector<std::unique_ptr<Job>> jobs;
-  DBuf d_prm, d_work, d_cnt;
+  DBuf d_prm, d_work, d_cnt, d_Y;  // d_Y: the fold intermediate shared by the cells
   std::vector<int> cls_off;                   // [25] merged work offsets per class
   std::vector<double> cls_cost;               // [24]
   std::vector<std::pair<int, int64_t>> from;  // merged item -> (job, local item)
@@ -1660,13 +1673,61 @@ int rsgdf_batch_create(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis
     j->o.g_thresh = -1.0;
     j->o.parts = RSGDF_PART_ALL;
     if (opt) j->o = *opt;
+    B->jobs.push_back(std::move(j));
+  }
+  // inputs are validated here, before any planning thread reads them
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
+  if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
+  for (int i = 0; i < ncell; ++i) {
+    const int64_t nb = rsgdf_j3c_nbytes(&cells[i], &bases[i], &auxes[i], kmeshes[i]);
+    if (nb < 0) return fail((int)nb, "cell " + std::to_string(i) + ": " + g_err);
+    for (int q = 0; q < 3 * cells[i].natm; ++q)
+      if (!std::isfinite(cells[i].coords[q])) return fail(RSGDF_EINVAL, "cell " + std::to_string(i) + ": non-finite coordinates");
+  }
+  // host planning of the cells is independent: up to 8 worker threads (each
+  // plan may itself fan out); device allocations and uploads stay in order
+  {
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    const int nt = std::min<int>(ncell, 8);
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&]() {
+        for (int i; (i = next.fetch_add(1)) < ncell;) {
+          Job &j = *B->jobs[i];
+          j.plan_rc = build_plan(j.cell, j.basis, j.auxbasis, j.kmesh, j.omega, j.thresh, j.hp);
+          if (j.plan_rc) j.plan_err = g_err;  // this worker's message
+          j.planned = true;
+        }
+      });
+    for (auto &t : th) t.join();
+  }
+  for (int i = 0; i < ncell; ++i) {
+    Job &j = *B->jobs[i];
     // all cells' short-range scratch is resident at once (one merged launch),
     // so a cell may take what is left; one needing more is built alone
-    int rc = j->prepare(B->st, 0.9);
+    j.own_y = false;
+    int rc = j.prepare(B->st, 0.9);
     if (rc) return fail(rc, "cell " + std::to_string(i) + ": " + g_err);
-    if (j->do_sr && j->nbatch != 1)
+    if (j.do_sr && j.nbatch != 1)
       return fail(RSGDF_EUNSUPPORTED, "cell " + std::to_string(i) + " needs aux batching; build it alone");
-    B->jobs.push_back(std::move(j));
+  }
+  {  // one fold intermediate for all cells: the folds run one after another on one stream
+    double ymax = 0.0;
+    for (auto &j : B->jobs)
+      if (j->do_sr) ymax = std::max(ymax, (double)j->max_bf_el * j->nk * j->nk * 16.0);
+    if (ymax > 0.0) {
+      size_t fr = 0, tt = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tt));
+      const double ybytes = std::min({ymax, 0.25 * 0.9 * (double)fr, 8e9});
+      size_t need_b = 0;
+      for (auto &j : B->jobs)
+        if (j->do_sr) {
+          j->set_fold_chunk(ybytes);
+          need_b = std::max(need_b, (size_t)j->fchunk * j->nk * j->nk * 16);
+        }
+      HIPCHK(B->d_Y.alloc(need_b));
+      for (auto &j : B->jobs) j->ybuf = B->d_Y.as<double>();
+    }
   }
   // merged SR queue: per class, all cells' items, heaviest first
   std::vector<SRParams> prms;
