@@ -590,12 +590,11 @@ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// four side streams per device for concurrent class launches (default priority)
 // n non-blocking side streams of the current device (created once per thread
 // and device, default priority).  The single-cell build forks its short-range
 // classes onto 3 of them: with the calling stream that is one stream per
-// hardware queue at HIP's default of 4 queues per process (measured on C2:
-// 3.04 s SR with 3, 3.24 s with 4, where two streams share a queue); graph
+// hardware queue at HIP's default of 4 queues per process (measured on the 8-atom
+// 2x2x2 workload: 3.04 s SR with 3, 3.24 s with 4, where two streams share a queue); graph
 // replays schedule their own nodes and use 4.
 int side_streams(std::vector<hipStream_t> &ss, size_t n) {
   static thread_local std::vector<std::pair<int, hipStream_t>> pool;
