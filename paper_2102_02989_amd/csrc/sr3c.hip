@@ -324,10 +324,10 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
 #pragma unroll
   for (int d = 0; d < 3; ++d) bn[d] = sqrt(b[3 * d] * b[3 * d] + b[3 * d + 1] * b[3 * d + 1] + b[3 * d + 2] * b[3 * d + 2]);
 
-  // group layout: ncb groups of gs lanes, group gl owns BvK cell cb0 + gl
+  // group layout: ncb groups of gs = floor(64 / ncb) lanes (any count, so that
+  // 5, 6 or 7 cells per wave keep 60-63 lanes busy), group gl owns BvK cell cb0 + gl
   const int ncbw = wk.ncb;
-  int gs = 1;
-  while (gs * 2 * ncbw <= 64) gs *= 2;
+  const int gs = 64 / ncbw;
   const int lig = lane % gs;
   const int gl = lane / gs;
   const unsigned long long gmask_lo = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
@@ -644,11 +644,10 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
         // magnitude log: the accumulator holds only this pair image's block (it is
         // flushed after every image in logging runs); max |block| per BvK cell c1,
         // each (ii, c1) owned by one wave
-        if (grp_on) {
+        if (grp_on && lig == 0) {
           double mx = 0.0;
-          for (int comp = lig; comp < NBLK; comp += gs) mx = fmax(mx, fabs(s_blk[gl * NBLK + comp]));
-          for (int off = 1; off < gs; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-          if (lig == 0) prm.logmag[(cbase + ii) * nk + c1] = (float)mx;
+          for (int comp = 0; comp < NBLK; ++comp) mx = fmax(mx, fabs(s_blk[gl * NBLK + comp]));
+          prm.logmag[(cbase + ii) * nk + c1] = (float)mx;
         }
         flush(cur_cls);
         __syncthreads();
