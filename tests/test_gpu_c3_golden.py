@@ -50,6 +50,24 @@ def test_c3_forms_vs_oracle_blocks():
         assert err <= tol, (name, err)
 
 
+def _count_q(problem):
+    """Number of q = G + k12 (q != 0, exp(-q^2/4w^2) >= g_thr) summed over the Nk
+    k12 classes of the mesh, by brute force over a box of G."""
+    B = 2 * np.pi * np.linalg.inv(np.asarray(problem.cell.lattice, float)).T
+    n = problem.kmesh
+    q2max = -4.0 * problem.omega ** 2 * np.log(problem.g_thr)
+    span = [int(np.ceil(np.sqrt(q2max) * np.linalg.norm(problem.cell.lattice[i]) / (2 * np.pi))) + 2 for i in range(3)]
+    g = np.stack(np.meshgrid(*[np.arange(-s, s + 1) for s in span], indexing="ij"), -1).reshape(-1, 3) @ B
+    total = 0
+    for j0 in range(n[0]):
+        for j1 in range(n[1]):
+            for j2 in range(n[2]):
+                q = g + (j0 / n[0]) * B[0] + (j1 / n[1]) * B[1] + (j2 / n[2]) * B[2]
+                q2 = (q * q).sum(1)
+                total += int(np.count_nonzero((q2 > 1e-20) & (np.exp(-q2 / (4 * problem.omega ** 2)) >= problem.g_thr)))
+    return total
+
+
 def test_c3_forms_full_tensor():
     import torch
 
@@ -61,12 +79,16 @@ def test_c3_forms_full_tensor():
         out, st = P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, p.omega, p.thresh, g_thresh=p.g_thr,
                               lr_precision=prec, parts=P.PART_LR)
         torch.cuda.synchronize()
-        print(f"  t_lr {st['t_lr_ms']:.0f} ms  gemm {st['t_lr_gemm_ms']:.0f} ms", flush=True)
-        return out
+        print(f"  t_lr {st['t_lr_ms']:.0f} ms  gemm {st['t_lr_gemm_ms']:.0f} ms  q vectors {st['n_g_total']}",
+              flush=True)
+        return out, st
 
-    ref = lr(P.FP64)
+    ref, st = lr(P.FP64)
+    nq = _count_q(p)
+    print(f"  q vectors: library {st['n_g_total']}, brute force {nq} ({nq / 27:.0f} per k12 class)", flush=True)
+    assert st["n_g_total"] == nq
     for prec, tol in ((P.FP32, 1e-6), (P.BF16X3, 4e-6)):
-        o = lr(prec)
+        o, _ = lr(prec)
         err = float((o - ref).abs().max())
         print(f"  form {prec}: max abs deviation from the FP64 form {err:.3e}", flush=True)
         del o
