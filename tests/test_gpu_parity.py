@@ -89,3 +89,27 @@ def test_config2_sampled_blocks():
     err = _block_err(p, got, ref, aux, pairs)
     _say("  max err", err, "max |ref|", np.abs(ref).max())
     assert err <= TOL
+
+
+def test_config5_sampled_blocks():
+    """The 16-atom cubic cell (a = 9) on the 4x4x4 mesh (2080 k-pairs, 54.5 GB
+    output) at full size: sampled (aux shell, AO shell pair) blocks, s/p/d aux
+    and same-atom and cross-atom s/p pairs, on k-pairs that include k1 = k2 ones
+    (the G = 0 term) and the last pair."""
+    p = synth.config5()
+    _say("case C5 sampled blocks")
+    aux = [0, 4, 6, 13, 20, 111]
+    pairs = [(0, 0), (2, 5), (1, 30), (47, 47), (2, 2), (5, 17)]
+    kps = [0, 1, 63, 64, 777, 1500, 2079]
+    import torch
+
+    import paper_2102_02989_amd as P
+    out, st = P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, p.omega, p.thresh, g_thresh=p.g_thr)
+    torch.cuda.synchronize()
+    got = out[torch.as_tensor(kps, device=out.device)].cpu().numpy()  # the sampled k-pairs only
+    del out
+    _say("  gpu", {k: st[k] for k in ("t_total_ms", "t_sr_ms", "t_fold_ms", "t_lr_ms", "n_sr_terms")})
+    ref = oracle.j3c(p, aux_shells=aux, pairs=pairs, kpairs=kps)
+    err = _block_err(p, got, ref[kps], aux, pairs)
+    _say("  max err", err, "max |ref|", np.abs(ref).max())
+    assert err <= TOL
