@@ -85,9 +85,24 @@ def test_batch_c4_cells_sampled():
     for i in picks:
         p = probs[i]
         single, _ = run_gpu(p)
-        d = max_err(b.outs[i].cpu().numpy(), single)
-        _say("  cell", i, "natm", p.cell.natm, "kmesh", p.kmesh, "batch vs single", d)
+        got = b.outs[i].cpu().numpy()
+        d = max_err(got, single)
+        # and against oracle blocks: first and last aux shell, a same-shell and a
+        # cross-cell AO pair, the first, a middle and the last k-pair
+        nkp = got.shape[0]
+        aux = [0, p.aux.nshell - 1]
+        pairs = [(0, 0), (0, p.basis.nshell - 1)]
+        kps = sorted({0, nkp // 2, nkp - 1})
+        ref = oracle.j3c(p, aux_shells=aux, pairs=pairs, kpairs=kps)
+        xo, bo = p.aux.offsets(), p.basis.offsets()
+        e = 0.0
+        for P_ in aux:
+            for mu, nu in pairs:
+                sl = (kps, slice(xo[P_], xo[P_ + 1]), slice(bo[mu], bo[mu + 1]), slice(bo[nu], bo[nu + 1]))
+                e = max(e, float(np.abs(got[sl] - ref[sl]).max()))
+        _say("  cell", i, "natm", p.cell.natm, "kmesh", p.kmesh, "batch vs single", d, "vs oracle", e)
         assert d <= 1e-12
+        assert e <= 1e-8
     b.close()
 
 
