@@ -209,7 +209,7 @@ double solve_rc(double K, double eta, double eps, int L) {
   double lo = 1e-8, hi = 1.0;
   if (g(lo) < 0) return lo;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 80; ++it) {
+  for (int it = 0; it < 52; ++it) {  // the bracket shrinks to 2^-52 of its width
     const double mid = 0.5 * (lo + hi);
     if (g(mid) > 0) lo = mid;
     else hi = mid;
@@ -224,7 +224,7 @@ double solve_r12(double NF, double beta, double eps) {
   auto g = [&](double x) { return std::log(NF) + std::log(x) - beta * x * x - std::log(eps); };
   double lo = xs, hi = 2.0 * xs;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 80; ++it) {
+  for (int it = 0; it < 52; ++it) {  // the bracket shrinks to 2^-52 of its width
     const double mid = 0.5 * (lo + hi);
     if (g(mid) > 0) lo = mid;
     else hi = mid;
@@ -407,14 +407,17 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
     }
     Sh[ip] = sh;
     std::sort(r12s.begin(), r12s.end());
-    // crossing of N_cell(x) x/(2 beta) e^{-beta x^2} and sum_{R12 > x} h
+    // crossing of N_cell(x) x/(2 beta) e^{-beta x^2} and sum_{R12 > x} h, the
+    // tail sums taken from suffix sums over the sorted list
     double r12min = 0.0;
     const double step = 0.05;
     const double xend = r12s.back() + step;
+    std::vector<double> tail(r12s.size() + 1, 0.0);
+    for (size_t i = r12s.size(); i-- > 0;) tail[i] = tail[i + 1] + std::exp(-beta * r12s[i] * r12s[i]);
+    size_t first = 0;  // first index with r12s[first] > x
     for (double x = 0.0; x <= xend; x += step) {
-      double rhs = 0.0;
-      for (double r : r12s)
-        if (r > x) rhs += std::exp(-beta * r * r);
+      while (first < r12s.size() && r12s[first] <= x) ++first;
+      const double rhs = tail[first];
       const double lhs = S.N(x) * x / (2.0 * beta) * std::exp(-beta * x * x);
       if (lhs < rhs) r12min = x + step;
     }
