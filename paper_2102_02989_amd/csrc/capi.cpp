@@ -203,9 +203,8 @@ double f_sr(double R, double eta1, double eta2) {  // Eq. S7
 // s-type model of Eq. S14 leaves out.  The left side rises at most once and
 // then decreases, so bisection from a point where it holds finds the cut.
 double solve_rc(double K, double eta, double eps, int L) {
-  auto g = [&](double R) {
-    return std::log(K) + L * std::log1p(2.0 * eta * R) - eta * eta * R * R - std::log(R) - std::log(eps);
-  };
+  const double c0 = std::log(K) - std::log(eps);
+  auto g = [&](double R) { return c0 + L * std::log1p(2.0 * eta * R) - eta * eta * R * R - std::log(R); };
   double lo = 1e-8, hi = 1.0;
   if (g(lo) < 0) return lo;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
@@ -221,7 +220,8 @@ double solve_rc(double K, double eta, double eps, int L) {
 double solve_r12(double NF, double beta, double eps) {
   const double xs = 1.0 / std::sqrt(2.0 * beta);
   if (!(NF > 0.0) || NF * xs * std::exp(-0.5) < eps) return 0.0;
-  auto g = [&](double x) { return std::log(NF) + std::log(x) - beta * x * x - std::log(eps); };
+  const double c0 = std::log(NF) - std::log(eps);
+  auto g = [&](double x) { return c0 + std::log(x) - beta * x * x; };
   double lo = xs, hi = 2.0 * xs;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
   for (int it = 0; it < 52; ++it) {  // the bracket shrinks to 2^-52 of its width
