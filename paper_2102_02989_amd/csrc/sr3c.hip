@@ -231,9 +231,16 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   constexpr int NK = (KX + 1) * (KX + 1) * (KX + 1);
   constexpr int NW = NCP * NHAB;           // W entries per group
   constexpr int MG = sr_max_cells(NBLK);   // groups per wave
-  __shared__ double s_T[64 * CH];          // reduction scratch: lane x entry
+  // The reduction scratch (lane x entry) and the W table of the contraction
+  // share one buffer: within a primitive triple the reduction ends with a
+  // barrier before W is written, and the comps pass ends with one before the
+  // next triple's reduction writes its scratch.  (The classes with L >= 6
+  // stay under 40 KB of LDS this way: four one-wave workgroups per CU.)
+  constexpr int NTW = (64 * CH > MG * NW) ? 64 * CH : MG * NW;
+  __shared__ double s_TW[NTW];
+  double *const s_T = s_TW;
+  double *const s_W = s_TW;
   __shared__ double s_R[MG * (NH + 1)];    // group sums (tetrahedral order) + a zero slot
-  __shared__ double s_W[MG * NW];
   __shared__ int s_wtab[NW];               // W entry (ic, h): cx | cy << 2 | cz << 4
   __shared__ short s_widx[NW * NK];        // Hermite index of h + (tau nu phi), or NH
   __shared__ int s_ctab[NBLK];             // component: ic | (ax,bx) << 8 | (ay,by) << 16 | (az,bz) << 24
