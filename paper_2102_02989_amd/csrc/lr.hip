@@ -423,16 +423,20 @@ __device__ __forceinline__ unsigned short lr_f2bf(float x) {  // round to neares
 __device__ __forceinline__ float lr_bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---- tiled G-space contraction ----------------------------------------------
-// Workgroup output tile BM (aux rows) x 128 (pair columns): 2 x (BM/32)
-// wavefronts, wave (wm, wn) owning rows 32 wm .. +32 and columns 64 wn .. +64
-// (2 x 4 MFMA blocks).  Per step of 16 q the A and B tiles are read once,
+// Workgroup output tile BM (aux rows) x BN (pair columns): 2 x (BM/32)
+// wavefronts, wave (wm, wn) owning rows 32 wm .. +32 and columns (BN/2) wn ..
+// + BN/2 (2 x BN/32 MFMA blocks).  Per step of 16 q the A and B tiles are read once,
 // converted to the form's operand format and staged in LDS (rows padded
 // against bank conflicts); the next step's tiles are loaded into registers
 // while the matrix cores work on the current one.  Modes 1 and 2 promote the
 // FP32 block sums to FP64 registers after every step, which needs twice the
-// registers: they run 4 waves (BM = 64, up to 512 registers per lane), mode 0
-// runs 8 (BM = 128).  Columns q in [q_lo, nq) of the launch.
-constexpr int TG_BN = 128, TG_BK = 16;
+// registers: they run 4 waves per workgroup (BM = 64, BN = 64), mode 0 runs 8
+// (BM = 128, BN = 128).  Columns q in [q_lo, nq) of the launch.
+constexpr int TG_BK = 16;
+// pair columns per workgroup: 64 in the reduced-precision forms (a wave holds
+// 2 x 2 blocks, so its FP32 and FP64 accumulators leave room for three waves
+// per SIMD; with 2 x 4 blocks it was one), 128 for FP64 operands
+__host__ __device__ constexpr int tg_bn(int mode) { return mode == 0 ? 128 : 64; }
 __host__ __device__ constexpr int tg_bm(int mode) { return mode == 0 ? 128 : 64; }
 __host__ __device__ constexpr int tg_threads(int mode) { return 2 * (tg_bm(mode) / 32) * 64; }
 
@@ -440,21 +444,22 @@ template <int MODE>
 struct TgTile;
 template <>
 struct TgTile<0> {  // FP64 re / im planes
-  double ar[128][TG_BK + 1], ai[128][TG_BK + 1], br[TG_BN][TG_BK + 1], bi[TG_BN][TG_BK + 1];
+  double ar[128][TG_BK + 1], ai[128][TG_BK + 1], br[tg_bn(0)][TG_BK + 1], bi[tg_bn(0)][TG_BK + 1];
 };
 template <>
 struct TgTile<1> {  // FP32 re / im planes
-  float ar[64][TG_BK + 1], ai[64][TG_BK + 1], br[TG_BN][TG_BK + 1], bi[TG_BN][TG_BK + 1];
+  float ar[64][TG_BK + 1], ai[64][TG_BK + 1], br[tg_bn(1)][TG_BK + 1], bi[tg_bn(1)][TG_BK + 1];
 };
 template <>
 struct TgTile<2> {  // BF16 hi / lo of re / im; rows of 16 + 4 halves (8-byte aligned)
-  unsigned short a[4][64][TG_BK + 4], b[4][TG_BN][TG_BK + 4];  // planes: re_hi, re_lo, im_hi, im_lo
+  unsigned short a[4][64][TG_BK + 4], b[4][tg_bn(2)][TG_BK + 4];  // planes: re_hi, re_lo, im_hi, im_lo
 };
 
 template <int MODE>
 __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const LRGemmParams gp, int q_lo) {
-  constexpr int BM = tg_bm(MODE), NT = tg_threads(MODE);
-  constexpr int RA = BM * 4 / NT, RB = TG_BN * 4 / NT;  // staged rows per thread (4 threads x 4 q per row)
+  constexpr int BM = tg_bm(MODE), NT = tg_threads(MODE), BN = tg_bn(MODE);
+  constexpr int NB = BN / 32;   // 16-column blocks per wave (a wave takes half the columns)
+  constexpr int RA = BM * 4 / NT, RB = BN * 4 / NT;  // staged rows per thread (4 threads x 4 q per row)
   __shared__ TgTile<MODE> S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -465,11 +470,11 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   // b + 16, ... are renumbered consecutively, and consecutive tile numbers
   // walk the aux rows first, so the row tiles that share one B tile (and
   // stream the same q columns of A) run together on one XCD.
-  const int mt = (gp.naux + BM - 1) / BM, ntile = mt * ((gp.nmn + TG_BN - 1) / TG_BN);
+  const int mt = (gp.naux + BM - 1) / BM, ntile = mt * ((gp.nmn + BN - 1) / BN);
   const int per = (ntile + 7) / 8;  // the grid holds 8 per workgroups
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (t >= ntile) return;
-  const int M0 = (t % mt) * BM, N0 = (t / mt) * TG_BN;
+  const int M0 = (t % mt) * BM, N0 = (t / mt) * BN;
   const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
   const float *Bk32 = gp.B32 + 2 * (size_t)kpi * gp.nq * gp.nmn;
   const int sr0 = tid >> 2, sq = (tid & 3) * 4;
@@ -560,12 +565,12 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   };
 
   typedef typename std::conditional<MODE == 0, lr_d4, lr_f4>::type acc_t;
-  acc_t cre[2][4], cim[2][4];
-  double hre[2][4][4], him[2][4][4];  // FP64 sums of modes 1 and 2 (f32 fragment order)
+  acc_t cre[2][NB], cim[2][NB];
+  double hre[2][NB][4], him[2][NB][4];  // FP64 sums of modes 1 and 2 (f32 fragment order)
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NB; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         cre[r][c][v] = cim[r][c][v] = 0;
@@ -578,10 +583,10 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   if constexpr (MODE != 0) {
     const int khi = gp.nq_hi < gp.nq ? gp.nq_hi : gp.nq;
     for (int k = q_lo; k < khi; ++k) {
-      double br[4], bi[4];
+      double br[NB], bi[NB];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int n = N0 + wn * 64 + c * 16 + li;
+      for (int c = 0; c < NB; ++c) {
+        const int n = N0 + wn * (BN / 2) + c * 16 + li;
         const size_t o = ((size_t)kpi * gp.nmn + n) * gp.nq_hi + k;
         br[c] = (n < gp.nmn) ? gp.Bhi[2 * o] : 0.0;
         bi[c] = (n < gp.nmn) ? gp.Bhi[2 * o + 1] : 0.0;
@@ -594,7 +599,7 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
           const size_t o = (size_t)m * gp.lda + k;
           const double ar = (m < gp.naux) ? gp.A[2 * o] : 0.0, ai = (m < gp.naux) ? gp.A[2 * o + 1] : 0.0;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
+          for (int c = 0; c < NB; ++c) {
             hre[r][c][v] += ar * br[c] - ai * bi[c];
             him[r][c][v] += ar * bi[c] + ai * br[c];
           }
@@ -613,21 +618,21 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
       for (int ks = 0; ks < TG_BK / 4; ++ks) {
         const int k = ks * 4 + lg;
         typedef typename std::conditional<MODE == 0, double, float>::type op_t;
-        op_t ar[2], ai[2], br[4], bi[4];
+        op_t ar[2], ai[2], br[NB], bi[NB];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
           ar[r] = S.ar[wm * 32 + r * 16 + li][k];
           ai[r] = S.ai[wm * 32 + r * 16 + li][k];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          br[c] = S.br[wn * 64 + c * 16 + li][k];
-          bi[c] = S.bi[wn * 64 + c * 16 + li][k];
+        for (int c = 0; c < NB; ++c) {
+          br[c] = S.br[wn * (BN / 2) + c * 16 + li][k];
+          bi[c] = S.bi[wn * (BN / 2) + c * 16 + li][k];
         }
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
+          for (int c = 0; c < NB; ++c) {
             if constexpr (MODE == 0) {
               cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], br[c], cre[r][c], 0, 0, 0);
               cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[r], bi[c], cre[r][c], 0, 0, 0);
@@ -642,7 +647,7 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
           }
       }
     } else {
-      lr_s4 a[2][4], an[2][2], b[4][4];  // a: re_hi, re_lo, im_hi, im_lo; an: -im_hi, -im_lo
+      lr_s4 a[2][4], an[2][2], b[NB][4];  // a: re_hi, re_lo, im_hi, im_lo; an: -im_hi, -im_lo
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -659,17 +664,17 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
           an[r][1][j] = (short)((unsigned short)a[r][3][j] ^ 0x8000u);
         }
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < NB; ++c)
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) {
-          const unsigned short *src = &S.b[pl][wn * 64 + c * 16 + li][4 * lg];
+          const unsigned short *src = &S.b[pl][wn * (BN / 2) + c * 16 + li][4 * lg];
 #pragma unroll
           for (int j = 0; j < 4; ++j) b[c][pl][j] = (short)src[j];
         }
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NB; ++c) {
           lr_f4 x = cre[r][c], y = cim[r][c];
           x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][0], x, 0, 0, 0);
           x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][1], x, 0, 0, 0);
@@ -691,7 +696,7 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NB; ++c)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             hre[r][c][v] += (double)cre[r][c][v];
@@ -706,11 +711,11 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < NB; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = M0 + wm * 32 + r * 16 + ((MODE == 0) ? (lg + 4 * v) : (4 * lg + v));
-        const int n = N0 + wn * 64 + c * 16 + li;
+        const int n = N0 + wn * (BN / 2) + c * 16 + li;
         if (m < gp.naux && n < gp.nmn) {
           const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
           if constexpr (MODE == 0) {
@@ -727,7 +732,8 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream) {
   if (q_lo >= gp.nq) return hipSuccess;
   const int bm = tg_bm(mode);
-  const int64_t ntile = (int64_t)((gp.nmn + TG_BN - 1) / TG_BN) * ((gp.naux + bm - 1) / bm);
+  const int bn = tg_bn(mode);
+  const int64_t ntile = (int64_t)((gp.nmn + bn - 1) / bn) * ((gp.naux + bm - 1) / bm);
   if (ntile * 8 > 0x7fffffff) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(8 * ((ntile + 7) / 8)), 1, nkpi);
   if (mode == 0) hipLaunchKernelGGL(lr_gemm_tiled_kernel<0>, grid, dim3(tg_threads(0)), 0, stream, gp, q_lo);
