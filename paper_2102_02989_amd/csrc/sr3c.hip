@@ -41,14 +41,14 @@ constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators
 constexpr int kSRWinCap = 256;    // screening windows held in LDS
 constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
 constexpr int kTripCap = 40;         // primitive triples whose constants are held in LDS
-constexpr int kTripC = 10;           // constants per primitive triple
+constexpr int kTripC = 9;            // constants per primitive triple
 
 // Constants of a primitive triple (AO a, AO b, aux c) that do not depend on
 // the pair image: t[0] 1/p, t[1] g_b/p (P = A + t[1] (B - A)), t[2] g_a g_b/p
 // (K_ab = e^{-t[2] R12^2}), t[3] rho, t[4] theta^2, t[5] theta, t[6] the
 // signed contraction prefactor c_c c_a c_b 2 pi^{5/2}/(p g_c sqrt(p + g_c)),
 // t[7] the 1s screening estimate per unit K_ab and lattice vector
-// (Eqs. S4-S9 with the erfc attenuation), t[8] 1/(2 g_c), t[9] unused.
+// (Eqs. S4-S9 with the erfc attenuation), t[8] 1/(2 g_c).
 template <int LP>
 __device__ __forceinline__ void triple_consts(double ga, double gb, double gc, double ca, double cb, double cc,
                                               double ca1, double cb1, double cc1, double omega, double *t) {
@@ -69,7 +69,6 @@ __device__ __forceinline__ void triple_consts(double ga, double gb, double gc, d
   t[7] = kPi * kPi * kPi * cc1 * ca1 * cb1 / (gc * p * sqrt(gc * p)) * 2.0 * (e1 - e2) *
          0.564189583547756286948079451561;
   t[8] = 0.5 / gc;
-  t[9] = 0.0;
 }
 
 // cells per wave for which the Cartesian accumulators of a class fit in LDS
@@ -106,17 +105,18 @@ __device__ __forceinline__ void cart_decode(int l, int i, int &x, int &y, int &z
   x = y = z = 0;
 }
 
-// e^{-T} for T >= 0 without the library's range reduction: T = (i + 1/2) + u
-// with i = floor(T), |u| <= 1/2, e^{-T} = e^{-(i+1/2)} e^{-u}; the first factor
-// comes from a table of kExpTab entries, the second from its Taylor series to
-// degree 14 (truncation below 3e-17 relative), evaluated by Estrin's scheme.
-// Zero beyond the table (e^{-64} < 2e-28).
-constexpr int kExpTab = 64;
-__device__ __forceinline__ double exp_neg_tab(double T, const double *__restrict__ etab) {
-  const int i = min((int)T, kExpTab - 1);
-  const double v = (i + 0.5) - fmin(T, (double)kExpTab);  // -u
+// e^{-T} for T >= 0 by Cody-Waite range reduction: T = k ln 2 + r with
+// k = rint(T / ln 2) and |r| <= ln(2)/2, ln 2 split into a 32-bit head (k ln2_hi
+// is exact for the k that occur) and a tail; e^{-T} = 2^{-k} e^{-r}, with e^{-r}
+// from its Taylor series to degree 13 (truncation below 5e-18 relative) by
+// Estrin's scheme and 2^{-k} applied exactly by ldexp.  No table, so no LDS
+// read in the image loop.  Zero for T >= 64 (e^{-64} < 2e-28).
+__device__ __forceinline__ double exp_neg(double T) {
+  const double Tc = fmin(T, 64.0);
+  const double k = rint(Tc * 1.4426950408889634);  // log2(e)
+  const double v = -fma(-k, 1.9082149292705877e-10, fma(-k, 0.6931471803691238, Tc));  // -r
   const double v2 = v * v, v4 = v2 * v2, v8 = v4 * v4;
-  // 1/k!, k = 0..14
+  // 1/n!, n = 0..13
   const double a0 = fma(v, 1.0, 1.0);
   const double a1 = fma(v, 1.0 / 6.0, 1.0 / 2.0);
   const double a2 = fma(v, 1.0 / 120.0, 1.0 / 24.0);
@@ -124,29 +124,34 @@ __device__ __forceinline__ double exp_neg_tab(double T, const double *__restrict
   const double a4 = fma(v, 1.0 / 362880.0, 1.0 / 40320.0);
   const double a5 = fma(v, 1.0 / 39916800.0, 1.0 / 3628800.0);
   const double a6 = fma(v, 1.0 / 6227020800.0, 1.0 / 479001600.0);
-  const double a7 = 1.0 / 87178291200.0;
-  const double b0 = fma(a1, v2, a0), b1 = fma(a3, v2, a2), b2 = fma(a5, v2, a4), b3 = fma(a7, v2, a6);
-  const double d0 = fma(b1, v4, b0), d1 = fma(b3, v4, b2);
-  const double e = etab[i] * fma(d1, v8, d0);
-  return T < (double)kExpTab ? e : 0.0;
+  const double b0 = fma(a1, v2, a0), b1 = fma(a3, v2, a2), b2 = fma(a5, v2, a4);
+  const double d0 = fma(b1, v4, b0), d1 = fma(a6, v4, b2);
+  const double e = ldexp(fma(d1, v8, d0), -(int)k);
+  return T < 64.0 ? e : 0.0;
 }
 
 // F_L(T) for 0 <= T < kBoysSwitch from the per-L polynomial table (Taylor
 // expansion of degree kBoysPolyDeg about each unit interval's centre), then the
 // downward recursion F_n = (2T F_{n+1} + e^{-T})/(2n+1), e = e^{-T} given.
 // The polynomial is evaluated by Estrin's scheme (pairs, then powers u^2,
-// u^4, u^8): dependency depth 5 instead of 12 for Horner's rule.
+// u^4, u^8): dependency depth 5 instead of 12 for Horner's rule.  The table in
+// LDS holds kBoysPolyDeg + 2 doubles per interval (the last one zero), so an
+// interval starts on a 16-byte boundary and its coefficients arrive in seven
+// 16-byte reads issued back to back, before the first multiply waits on them.
 static_assert(kBoysPolyDeg == 12, "Estrin evaluation below is written for degree 12");
 template <int L>
 __device__ __forceinline__ void boys_poly(double T, double e, const double *__restrict__ tab, double (&F)[L + 1]) {
   const int i = (int)T;
   const double u = T - (i + 0.5);
-  const double *c = tab + i * (kBoysPolyDeg + 1);
+  const double2 *c2 = reinterpret_cast<const double2 *>(tab + i * (kBoysPolyDeg + 2));
+  double2 c[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) c[k] = c2[k];
   const double u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
-  const double a0 = fma(c[1], u, c[0]), a1 = fma(c[3], u, c[2]), a2 = fma(c[5], u, c[4]);
-  const double a3 = fma(c[7], u, c[6]), a4 = fma(c[9], u, c[8]), a5 = fma(c[11], u, c[10]);
+  const double a0 = fma(c[0].y, u, c[0].x), a1 = fma(c[1].y, u, c[1].x), a2 = fma(c[2].y, u, c[2].x);
+  const double a3 = fma(c[3].y, u, c[3].x), a4 = fma(c[4].y, u, c[4].x), a5 = fma(c[5].y, u, c[5].x);
   const double b0 = fma(a1, u2, a0), b1 = fma(a3, u2, a2), b2 = fma(a5, u2, a4);
-  const double d0 = fma(b1, u4, b0), d1 = fma(c[12], u4, b2);
+  const double d0 = fma(b1, u4, b0), d1 = fma(c[6].x, u4, b2);
   F[L] = fma(d1, u8, d0);
   const double t2 = 2.0 * T;
 #pragma unroll
@@ -173,7 +178,7 @@ __device__ __forceinline__ void boys_large_e(double T, double e, double (&F)[L +
 // theta^2 T >= kBoysSwitch (both terms share their asymptote to within e^{-theta^2 T}).
 template <int L>
 __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const double *__restrict__ tab,
-                                         const double *__restrict__ etab, double (&G)[L + 1]) {
+                                         double (&G)[L + 1]) {
   const double x = th2 * T;
   if (x >= kBoysSwitch) {
 #pragma unroll
@@ -181,10 +186,10 @@ __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const 
     return;
   }
   double F1[L + 1], F2[L + 1];
-  const double eT = (L > 0) ? exp_neg_tab(T, etab) : 0.0;
+  const double eT = (L > 0) ? exp_neg(T) : 0.0;
   if (T < kBoysSwitch) boys_poly<L>(T, eT, tab, F1);
   else boys_large_e<L>(T, eT, F1);
-  boys_poly<L>(x, (L > 0) ? exp_neg_tab(x, etab) : 0.0, tab, F2);
+  boys_poly<L>(x, (L > 0) ? exp_neg(x) : 0.0, tab, F2);
   double f = th;
 #pragma unroll
   for (int n = 0; n <= L; ++n) {
@@ -220,14 +225,14 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   constexpr int EA = (LA + 1) * (LB + 1) * (LAB + 1);
   constexpr int BLK = NBLK * sr_max_cells(NBLK);
   __shared__ float s_nf[kSRWinCap];
-  __shared__ double s_boys[kBoysIntervals * (kBoysPolyDeg + 1)];
-  __shared__ double s_etab[kExpTab];  // e^{-(i + 1/2)}
+  __shared__ __attribute__((aligned(16))) double s_boys[kBoysIntervals * (kBoysPolyDeg + 2)];
   __shared__ int s_cand[kCandCap];
   __shared__ double s_blk[BLK];
   // contraction of all lane groups at once: W[g][ic][h] from the group sums
   // R[g][h'] through a table of Hermite indices (NH marks an invalid aux
   // order and reads the zero slot), then the components from W
-  constexpr int CH = 8;                    // Hermite entries per step of the group reduction
+  constexpr int CH = 7;                    // Hermite entries per step of the group reduction (an odd
+                                           // row stride: the 64 lanes' rows start in distinct LDS banks)
   constexpr int KX = LP / 2;               // aux Hermite orders tau = (c & 1) + 2k, k <= KX
   constexpr int NK = (KX + 1) * (KX + 1) * (KX + 1);
   constexpr int NW = NCP * NHAB;           // W entries per group
@@ -266,8 +271,8 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
 
   // ---- per-item tables in LDS: Boys polynomials of order L, screening windows
   for (int i = lane; i < kBoysIntervals * (kBoysPolyDeg + 1); i += 64)
-    s_boys[i] = prm.boys[L * kBoysIntervals * (kBoysPolyDeg + 1) + i];
-  for (int i = lane; i < kExpTab; i += 64) s_etab[i] = exp(-(i + 0.5));
+    s_boys[(i / (kBoysPolyDeg + 1)) * (kBoysPolyDeg + 2) + i % (kBoysPolyDeg + 1)] = prm.boys[L * kBoysIntervals * (kBoysPolyDeg + 1) + i];
+  for (int i = lane; i < kBoysIntervals; i += 64) s_boys[i * (kBoysPolyDeg + 2) + kBoysPolyDeg + 1] = 0.0;
   const int nta = shA.nprim, ntb = shB.nprim, ntcp = shP.nprim;
   const int ntrip_p = nta * ntb * ntcp;
   const bool tc_lds = ntrip_p <= kTripCap;
@@ -513,7 +518,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 const double Z = dPz + M0 * a[2] + M1 * a[5] + M2 * a[8];
                 const double T = rho * (X * X + Y * Y + Z * Z);
                 double g[L + 1];
-                gvals_sr<L>(T, th2, th, s_boys, s_etab, g);
+                gvals_sr<L>(T, th2, th, s_boys, g);
                 double f = 1.0;
 #pragma unroll
                 for (int n = 1; n <= L; ++n) {
