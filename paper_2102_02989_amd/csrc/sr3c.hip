@@ -539,8 +539,18 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 __syncthreads();
                 if (grp_on) {
                   for (int j = lig; j < CH && c0 + j < NH; j += gs) {
+                    // reads issued eight at a time (gs >= 8); the sum keeps lane order
+                    const double *col = s_T + gl * gs * CH + j;
                     double acc = 0.0;
-                    for (int r = 0; r < gs; ++r) acc += s_T[(gl * gs + r) * CH + j];
+                    int r = 0;
+                    for (; r + 8 <= gs; r += 8) {
+                      double v[8];
+#pragma unroll
+                      for (int q = 0; q < 8; ++q) v[q] = col[(r + q) * CH];
+#pragma unroll
+                      for (int q = 0; q < 8; ++q) acc += v[q];
+                    }
+                    for (; r < gs; ++r) acc += col[r * CH];
                     s_R[gl * (NH + 1) + c0 + j] = acc;
                   }
                 }
@@ -586,6 +596,10 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                 }
                 const double *rg = s_R + g * (NH + 1);
                 const short *wi = s_widx + idx * NK;
+                // every group sum this entry needs, read before the first multiply
+                double rv[NK];
+#pragma unroll
+                for (int k = 0; k < NK; ++k) rv[k] = rg[wi[k]];
                 double sw = 0.0;
 #pragma unroll
                 for (int kx = 0; kx <= KX; ++kx)
@@ -593,7 +607,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   for (int ky = 0; ky <= KX; ++ky) {
                     double sz = 0.0;
 #pragma unroll
-                    for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rg[wi[(kx * (KX + 1) + ky) * (KX + 1) + kz]];
+                    for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rv[(kx * (KX + 1) + ky) * (KX + 1) + kz];
                     sw += ex[kx] * ey[ky] * sz;
                   }
                 s_W[g * NW + idx] = sw;
