@@ -137,16 +137,17 @@ __device__ __forceinline__ double exp_neg(double T) {
 // u^4, u^8): dependency depth 5 instead of 12 for Horner's rule.  The table in
 // LDS holds kBoysPolyDeg + 2 doubles per interval (the last one zero), so an
 // interval starts on a 16-byte boundary and its coefficients arrive in seven
-// 16-byte reads issued back to back, before the first multiply waits on them.
+// 16-byte reads issued back to back, before the first multiply waits on them
+// (boys_row; the caller issues the reads of both Boys arguments together).
 static_assert(kBoysPolyDeg == 12, "Estrin evaluation below is written for degree 12");
-template <int L>
-__device__ __forceinline__ void boys_poly(double T, double e, const double *__restrict__ tab, double (&F)[L + 1]) {
-  const int i = (int)T;
-  const double u = T - (i + 0.5);
+__device__ __forceinline__ void boys_row(const double *__restrict__ tab, int i, double2 (&c)[7]) {
   const double2 *c2 = reinterpret_cast<const double2 *>(tab + i * (kBoysPolyDeg + 2));
-  double2 c[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) c[k] = c2[k];
+}
+template <int L>
+__device__ __forceinline__ void boys_poly(double T, int i, double e, const double2 (&c)[7], double (&F)[L + 1]) {
+  const double u = T - (i + 0.5);
   const double u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
   const double a0 = fma(c[0].y, u, c[0].x), a1 = fma(c[1].y, u, c[1].x), a2 = fma(c[2].y, u, c[2].x);
   const double a3 = fma(c[3].y, u, c[3].x), a4 = fma(c[4].y, u, c[4].x), a5 = fma(c[5].y, u, c[5].x);
@@ -186,10 +187,15 @@ __device__ __forceinline__ void gvals_sr(double T, double th2, double th, const 
     return;
   }
   double F1[L + 1], F2[L + 1];
+  const int ix = (int)x;
+  const int iT = T < kBoysSwitch ? (int)T : kBoysIntervals - 1;  // row read but unused for T beyond the table
+  double2 cx[7], cT[7];
+  boys_row(tab, ix, cx);
+  boys_row(tab, iT, cT);
   const double eT = (L > 0) ? exp_neg(T) : 0.0;
-  if (T < kBoysSwitch) boys_poly<L>(T, eT, tab, F1);
+  boys_poly<L>(x, ix, (L > 0) ? exp_neg(x) : 0.0, cx, F2);
+  if (T < kBoysSwitch) boys_poly<L>(T, iT, eT, cT, F1);
   else boys_large_e<L>(T, eT, F1);
-  boys_poly<L>(x, (L > 0) ? exp_neg(x) : 0.0, tab, F2);
   double f = th;
 #pragma unroll
   for (int n = 0; n <= L; ++n) {
