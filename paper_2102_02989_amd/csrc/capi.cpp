@@ -945,7 +945,15 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       for (int c = 0; c < nk; ++c) nimg += hp.nsr[(size_t)tr.pair * nk + c];
       const double nm = 4.18879020478639098 * tr.rc_cut * tr.rc_cut * tr.rc_cut / L.vol + 1.0;
       const int Lt = sP.l + sA.l + sB.l;
-      est[t] = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg * nm * sr_term_flops(Lt);
+      // per (primitive triple, pair image, cell range): the group reduction, the
+      // W table and the Cartesian components of the contraction, in flops; the
+      // weight 13.6 is the least-squares ratio of the two costs over the 24
+      // classes' standalone durations on the 8-atom 2x2x2 workload
+      const int lab = sA.l + sB.l, nkx = (sP.l / 2 + 1) * (sP.l / 2 + 1) * (sP.l / 2 + 1);
+      const int nblk = ncart_h(sP.l) * ncart_h(sA.l) * ncart_h(sB.l);
+      const double ev = 2.0 * nherm(Lt) + 2.0 * ncart_h(sP.l) * nherm(lab) * nkx + 2.0 * nblk * nherm(lab);
+      const double nranges = std::ceil((double)nk / std::min(nk, sr_cells_per_wave(nblk)));
+      est[t] = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg * (nm * sr_term_flops(Lt) + 13.6 * nranges * ev);
       tot += est[t];
     }
     // target cost per wave: 8 waves per SIMD over the build
