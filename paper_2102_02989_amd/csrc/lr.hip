@@ -111,21 +111,41 @@ hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream) {
 // c_q = 1 + |q|/2p + sqrt((la+lb)/2p), is below eps: it can move no output
 // element by more than eps.  Images of a class are sorted by r, so the loop
 // ends at the first skipped image beyond the maximiser r* of the r factor.
+// q values per lane: the image-dependent work of a term (Gaussian factor,
+// bound, pair centre, E coefficients) is the same for every q, so the lanes of
+// the lighter classes take several q each and do it once for all of them (s-s
+// four, up to l_a + l_b = 3 two; the d-d accumulators leave no registers for more)
+__host__ __device__ constexpr int pairft_qpl(int la, int lb) { return la + lb == 0 ? 4 : (la + lb <= 3 ? 2 : 1); }
+
 template <int LA, int LB>
-__device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, int iq) {
+__device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, int iq0) {
   constexpr int NCA = ncart(LA), NCB = ncart(LB);
   constexpr int LT = LA + LB;
+  constexpr int QP = pairft_qpl(LA, LB);
   const Pair pr = pp.pairs[ip];
   const Shell s1 = pp.ao[pr.sa];
   const Shell s2 = pp.ao[pr.sb];
-  const bool live = iq < pp.nq;
-  const int iqc = live ? iq : pp.nq - 1;  // idle lanes of the last block follow a valid q, write nothing
-  const double qx = pp.q[3 * iqc], qy = pp.q[3 * iqc + 1], qz = pp.q[3 * iqc + 2];
+  // lane q values iq0 + 64 s, s < QP; idle slots of the last block follow a
+  // valid q and write nothing
+  bool live[QP];
+  double qx[QP], qy[QP], qz[QP], q2[QP];
   // The skip tests use the wave's extreme values (largest amax and |q|,
-  // smallest q^2), so they bound every lane's terms and every lane takes the
-  // same branch.
-  const double q2 = qx * qx + qy * qy + qz * qz;
-  double am = pp.amax[iqc], q2w = q2, qnw = sqrt(q2);
+  // smallest q^2), so they bound every term of every lane and every lane takes
+  // the same branch.
+  double am = 0.0, q2w = 1e300, qnw = 0.0;
+#pragma unroll
+  for (int s = 0; s < QP; ++s) {
+    const int iq = iq0 + 64 * s;
+    live[s] = iq < pp.nq;
+    const int iqc = live[s] ? iq : pp.nq - 1;
+    qx[s] = pp.q[3 * iqc];
+    qy[s] = pp.q[3 * iqc + 1];
+    qz[s] = pp.q[3 * iqc + 2];
+    q2[s] = qx[s] * qx[s] + qy[s] * qy[s] + qz[s] * qz[s];
+    am = fmax(am, pp.amax[iqc]);
+    q2w = fmin(q2w, q2[s]);
+    qnw = fmax(qnw, sqrt(q2[s]));
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     am = fmax(am, __shfl_xor(am, o, 64));
@@ -133,26 +153,32 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
     qnw = fmax(qnw, __shfl_xor(qnw, o, 64));
   }
   const double cut = am > 0.0 ? pp.eps / am : 1e300;
-  // (-i q_d)^t = qr[d][t] + i qi[d][t]
-  double qr[3][LT + 1], qi[3][LT + 1];
-  {
-    const double qd[3] = {qx, qy, qz};
+  // (-i q_d)^t = qr[s][d][t] + i qi[s][d][t]
+  double qr[QP][3][LT + 1], qi[QP][3][LT + 1];
+#pragma unroll
+  for (int s = 0; s < QP; ++s) {
+    const double qd[3] = {qx[s], qy[s], qz[s]};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       double pw = 1.0;
 #pragma unroll
       for (int t = 0; t <= LT; ++t) {
         const int m = t & 3;  // (-i)^t = 1, -i, -1, i
-        qr[d][t] = (m == 0) ? pw : (m == 2 ? -pw : 0.0);
-        qi[d][t] = (m == 1) ? -pw : (m == 3 ? pw : 0.0);
+        qr[s][d][t] = (m == 0) ? pw : (m == 2 ? -pw : 0.0);
+        qi[s][d][t] = (m == 1) ? -pw : (m == 3 ? pw : 0.0);
         pw *= qd[d];
       }
     }
   }
-  double accr[NCA * NCB], acci[NCA * NCB];
+  double accr[QP][NCA * NCB], acci[QP][NCA * NCB];
 #pragma unroll
-  for (int i = 0; i < NCA * NCB; ++i) accr[i] = acci[i] = 0.0;
+  for (int s = 0; s < QP; ++s)
+#pragma unroll
+    for (int i = 0; i < NCA * NCB; ++i) accr[s][i] = acci[s][i] = 0.0;
   long long cnt = 0;
+  int nlive = 0;
+#pragma unroll
+  for (int s = 0; s < QP; ++s) nlive += live[s];
   const int beg = pp.cls_off[pr.cls_off + c], end = pp.cls_off[pr.cls_off + c + 1];
   for (int ka = 0; ka < s1.nprim; ++ka)
     for (int kb = 0; kb < s2.nprim; ++kb) {
@@ -167,7 +193,9 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
 #pragma unroll
       for (int t = 0; t < LT; ++t) fmax *= (cq + rstar);
       if (fmax < cut) continue;
-      const double camp = cc * pre * exp(-q2 * 0.25 * oop);
+      double camp[QP];
+#pragma unroll
+      for (int s = 0; s < QP; ++s) camp[s] = cc * pre * exp(-q2[s] * 0.25 * oop);
       for (int ii = beg; ii < end; ++ii) {
         const double *nv = pp.img + 3 * (size_t)(pr.img_off + ii);
         const double Bx = s2.x + nv[0], By = s2.y + nv[1], Bz = s2.z + nv[2];
@@ -182,16 +210,12 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
           if (rr > rstar) break;
           continue;
         }
-        cnt += live;
+        cnt += nlive;
         // P - A = (gb/p) R, P - B = -(ga/p) R
         const double wa = gb * oop, wb = -ga * oop;
         const double Px = s1.x + wa * Rx, Py = s1.y + wa * Ry, Pz = s1.z + wa * Rz;
-        double sph, cph;
-        sincos(-(qx * Px + qy * Py + qz * Pz), &sph, &cph);
-        const double amp = camp * er;
-        const double cr = amp * cph, ci = amp * sph;
-        // F_d[i][j] = sum_t E_d[i][j][t] (-i q_d)^t
-        double Fr[3][LA + 1][LB + 1], Fi[3][LA + 1][LB + 1];
+        // F_d[i][j] = sum_t E_d[i][j][t] (-i q_d)^t, per q value of the lane
+        double Fr[QP][3][LA + 1][LB + 1], Fi[QP][3][LA + 1][LB + 1];
         {
           double E[LA + 1][LB + 1][LT + 1];
           const double Rd[3] = {Rx, Ry, Rz};
@@ -199,85 +223,101 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
           for (int d = 0; d < 3; ++d) {
             hermite_E<LA, LB>(wa * Rd[d], wb * Rd[d], 0.5 * oop, E);
 #pragma unroll
-            for (int i = 0; i <= LA; ++i)
+            for (int s = 0; s < QP; ++s)
 #pragma unroll
-              for (int j = 0; j <= LB; ++j) {
-                double re = 0.0, im = 0.0;
+              for (int i = 0; i <= LA; ++i)
 #pragma unroll
-                for (int t = 0; t <= i + j; ++t) {
-                  if ((t & 1) == 0) re += E[i][j][t] * qr[d][t];
-                  else im += E[i][j][t] * qi[d][t];
+                for (int j = 0; j <= LB; ++j) {
+                  double re = 0.0, im = 0.0;
+#pragma unroll
+                  for (int t = 0; t <= i + j; ++t) {
+                    if ((t & 1) == 0) re += E[i][j][t] * qr[s][d][t];
+                    else im += E[i][j][t] * qi[s][d][t];
+                  }
+                  Fr[s][d][i][j] = re;
+                  Fi[s][d][i][j] = im;
                 }
-                Fr[d][i][j] = re;
-                Fi[d][i][j] = im;
-              }
           }
         }
-        // fold the amplitude and phase into the x factor
-        double Gr[LA + 1][LB + 1], Gi[LA + 1][LB + 1];
 #pragma unroll
-        for (int i = 0; i <= LA; ++i)
+        for (int s = 0; s < QP; ++s) {
+          double sph, cph;
+          sincos(-(qx[s] * Px + qy[s] * Py + qz[s] * Pz), &sph, &cph);
+          const double amp = camp[s] * er;
+          const double cr = amp * cph, ci = amp * sph;
+          // fold the amplitude and phase into the x factor
+          double Gr[LA + 1][LB + 1], Gi[LA + 1][LB + 1];
 #pragma unroll
-          for (int j = 0; j <= LB; ++j) {
-            Gr[i][j] = cr * Fr[0][i][j] - ci * Fi[0][i][j];
-            Gi[i][j] = cr * Fi[0][i][j] + ci * Fr[0][i][j];
-          }
+          for (int i = 0; i <= LA; ++i)
 #pragma unroll
-        for (int ia = 0; ia < NCA; ++ia)
+            for (int j = 0; j <= LB; ++j) {
+              Gr[i][j] = cr * Fr[s][0][i][j] - ci * Fi[s][0][i][j];
+              Gi[i][j] = cr * Fi[s][0][i][j] + ci * Fr[s][0][i][j];
+            }
 #pragma unroll
-          for (int ib = 0; ib < NCB; ++ib) {
-            const int ax_ = cart_lx(LA, ia), ay_ = cart_ly(LA, ia), az_ = cart_lz(LA, ia);
-            const int bx_ = cart_lx(LB, ib), by_ = cart_ly(LB, ib), bz_ = cart_lz(LB, ib);
-            const double xr = Gr[ax_][bx_] * Fr[1][ay_][by_] - Gi[ax_][bx_] * Fi[1][ay_][by_];
-            const double xi = Gr[ax_][bx_] * Fi[1][ay_][by_] + Gi[ax_][bx_] * Fr[1][ay_][by_];
-            accr[ia * NCB + ib] += xr * Fr[2][az_][bz_] - xi * Fi[2][az_][bz_];
-            acci[ia * NCB + ib] += xr * Fi[2][az_][bz_] + xi * Fr[2][az_][bz_];
-          }
+          for (int ia = 0; ia < NCA; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < NCB; ++ib) {
+              const int ax_ = cart_lx(LA, ia), ay_ = cart_ly(LA, ia), az_ = cart_lz(LA, ia);
+              const int bx_ = cart_lx(LB, ib), by_ = cart_ly(LB, ib), bz_ = cart_lz(LB, ib);
+              const double xr = Gr[ax_][bx_] * Fr[s][1][ay_][by_] - Gi[ax_][bx_] * Fi[s][1][ay_][by_];
+              const double xi = Gr[ax_][bx_] * Fi[s][1][ay_][by_] + Gi[ax_][bx_] * Fr[s][1][ay_][by_];
+              accr[s][ia * NCB + ib] += xr * Fr[s][2][az_][bz_] - xi * Fi[s][2][az_][bz_];
+              acci[s][ia * NCB + ib] += xr * Fi[s][2][az_][bz_] + xi * Fr[s][2][az_][bz_];
+            }
+        }
       }
     }
-  if (!live) return cnt;
   const int nao = pp.nao;
   const size_t nq = pp.nq;
   double *Ic = pp.B + 2 * ((size_t)c * nao * nao * nq);
-#pragma unroll
-  for (int ia = 0; ia < NCA; ++ia)
-#pragma unroll
-    for (int ib = 0; ib < NCB; ++ib) {
-      const size_t o = ((size_t)(s1.foff + ia) * nao + s2.foff + ib) * nq + iq;
-      Ic[2 * o] = accr[ia * NCB + ib];
-      Ic[2 * o + 1] = acci[ia * NCB + ib];
-    }
+  double sp = 0.0, cp = 1.0;
+  int cneg = 0;
   if (!pr.diag) {
     const int n0 = pp.kn[0], n1 = pp.kn[1], n2 = pp.kn[2];
     const int i0 = c / (n1 * n2), i1 = (c / n2) % n1, i2 = c % n2;
-    const int cneg = (((n0 - i0) % n0) * n1 + (n1 - i1) % n1) * n2 + (n2 - i2) % n2;
+    cneg = (((n0 - i0) % n0) * n1 + (n1 - i1) % n1) * n2 + (n2 - i2) % n2;
     // e^{+i k_cls.L_c} = e^{2 pi i sum_d j_d i_d / n_d}, reduced exactly in integers
     const int nt = n0 * n1 * n2;
     const int num = ((pp.kcls[0] * i0 % n0) * n1 * n2 + (pp.kcls[1] * i1 % n1) * n0 * n2 +
                      (pp.kcls[2] * i2 % n2) * n0 * n1) % nt;
-    double sp, cp;
     sincospi(2.0 * num / nt, &sp, &cp);
-    double *In = pp.B + 2 * ((size_t)cneg * nao * nao * nq);
+  }
+  double *In = pp.B + 2 * ((size_t)cneg * nao * nao * nq);
+#pragma unroll
+  for (int s = 0; s < QP; ++s) {
+    if (!live[s]) continue;
+    const size_t iq = (size_t)iq0 + 64 * s;
 #pragma unroll
     for (int ia = 0; ia < NCA; ++ia)
 #pragma unroll
       for (int ib = 0; ib < NCB; ++ib) {
-        const size_t o = ((size_t)(s2.foff + ib) * nao + s1.foff + ia) * nq + iq;
-        const double re = accr[ia * NCB + ib], im = acci[ia * NCB + ib];
-        In[2 * o] = cp * re - sp * im;
-        In[2 * o + 1] = cp * im + sp * re;
+        const size_t o = ((size_t)(s1.foff + ia) * nao + s2.foff + ib) * nq + iq;
+        Ic[2 * o] = accr[s][ia * NCB + ib];
+        Ic[2 * o + 1] = acci[s][ia * NCB + ib];
       }
+    if (!pr.diag) {
+#pragma unroll
+      for (int ia = 0; ia < NCA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NCB; ++ib) {
+          const size_t o = ((size_t)(s2.foff + ib) * nao + s1.foff + ia) * nq + iq;
+          const double re = accr[s][ia * NCB + ib], im = acci[s][ia * NCB + ib];
+          In[2 * o] = cp * re - sp * im;
+          In[2 * o + 1] = cp * im + sp * re;
+        }
+    }
   }
   return cnt;
 }
 
-// grid: x = (pair of one angular group, class), y = 64-wide blocks of q;
+// grid: x = (pair of one angular group, class), y = blocks of 64 * pairft_qpl q;
 // one kernel per (l(sa), l(sb)) so that each runs at its own register count
 template <int LA, int LB>
 __global__ __launch_bounds__(64) void pairft_binned_kernel(const PairFTParams pp, int pbeg) {
   const int ip = pp.plist[pbeg + (int)(blockIdx.x / pp.nk)], c = (int)(blockIdx.x % pp.nk);
-  const int iq = blockIdx.y * 64 + threadIdx.x;
-  long long cnt = pairft_binned_one<LA, LB>(pp, ip, c, iq);
+  const int iq0 = blockIdx.y * (64 * pairft_qpl(LA, LB)) + threadIdx.x;
+  long long cnt = pairft_binned_one<LA, LB>(pp, ip, c, iq0);
   // wave sum of the evaluation counts, one integer atomic per wave
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
@@ -286,15 +326,17 @@ __global__ __launch_bounds__(64) void pairft_binned_kernel(const PairFTParams pp
 
 hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream) {
   if (pp.nq == 0 || pp.npair == 0) return hipSuccess;
-  const int64_t ny = (pp.nq + 63) / 64;
-  if (ny > 65535) return hipErrorInvalidConfiguration;
   typedef void (*K)(const PairFTParams, int);
   const K ks[6] = {pairft_binned_kernel<2, 2>, pairft_binned_kernel<2, 1>, pairft_binned_kernel<2, 0>,
                    pairft_binned_kernel<1, 1>, pairft_binned_kernel<1, 0>, pairft_binned_kernel<0, 0>};
+  static const int la_of[6] = {2, 2, 2, 1, 1, 0}, lb_of[6] = {2, 1, 0, 1, 0, 0};
   for (int g = 0; g < 6; ++g) {
     const int64_t nx = (int64_t)(pp.pgrp[g + 1] - pp.pgrp[g]) * pp.nk;
     if (nx == 0) continue;
     if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const int64_t qb = 64 * pairft_qpl(la_of[g], lb_of[g]);
+    const int64_t ny = (pp.nq + qb - 1) / qb;
+    if (ny > 65535) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(ks[g], dim3((unsigned)nx, (unsigned)ny), dim3(64), 0, stream, pp, pp.pgrp[g]);
   }
   return hipGetLastError();
