@@ -587,9 +587,11 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
               const double coef = tcl[6] * Kab;
               __syncthreads();  // E coefficients and group sums visible to every lane
               // W[g][ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R[g][h + (tau nu phi)]
-              for (int e = lane; e < ngrp * NW; e += 64) {
-                const int g = e / NW, idx = e - g * NW;
-                if (!((gnz >> (g * gs)) & 1ull)) continue;
+              // a lane holds one entry's aux factors and Hermite indices and runs
+              // over the groups of its lane set (64 / NW sets when NW < 64)
+              constexpr int RW = NW >= 64 ? 1 : 64 / NW;
+              for (int cb = lane; cb < NW * RW; cb += 64) {
+                const int idx = cb % NW, gset = cb / NW;
                 const int w = s_wtab[idx];
                 const int cx = w & 3, cy = (w >> 2) & 3, cz = (w >> 4) & 3;
                 double ex[KX + 1], ey[KX + 1], ez[KX + 1];
@@ -600,34 +602,49 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   ey[k] = (ty <= cy) ? s_EP[cy * (LP + 1) + min(ty, LP)] : 0.0;
                   ez[k] = (tz <= cz) ? s_EP[cz * (LP + 1) + min(tz, LP)] : 0.0;
                 }
-                const double *rg = s_R + g * (NH + 1);
-                const short *wi = s_widx + idx * NK;
-                // every group sum this entry needs, read before the first multiply
-                double rv[NK];
+                const short *wip = s_widx + idx * NK;
+                int wi[NK];
 #pragma unroll
-                for (int k = 0; k < NK; ++k) rv[k] = rg[wi[k]];
-                double sw = 0.0;
+                for (int k = 0; k < NK; ++k) wi[k] = wip[k];
+                for (int g = gset; g < ngrp; g += RW) {
+                  if (!((gnz >> (g * gs)) & 1ull)) continue;
+                  const double *rg = s_R + g * (NH + 1);
+                  // every group sum this entry needs, read before the first multiply
+                  double rv[NK];
 #pragma unroll
-                for (int kx = 0; kx <= KX; ++kx)
+                  for (int k = 0; k < NK; ++k) rv[k] = rg[wi[k]];
+                  double sw = 0.0;
 #pragma unroll
-                  for (int ky = 0; ky <= KX; ++ky) {
-                    double sz = 0.0;
+                  for (int kx = 0; kx <= KX; ++kx)
 #pragma unroll
-                    for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rv[(kx * (KX + 1) + ky) * (KX + 1) + kz];
-                    sw += ex[kx] * ey[ky] * sz;
-                  }
-                s_W[g * NW + idx] = sw;
+                    for (int ky = 0; ky <= KX; ++ky) {
+                      double sz = 0.0;
+#pragma unroll
+                      for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rv[(kx * (KX + 1) + ky) * (KX + 1) + kz];
+                      sw += ex[kx] * ey[ky] * sz;
+                    }
+                  s_W[g * NW + idx] = sw;
+                }
               }
               __syncthreads();
               // component (ic, ia, ib) of group g = sum_{tuv} E^x_t E^y_u E^z_v W[g][ic][tuv]
-              for (int e = lane; e < ngrp * NBLK; e += 64) {
-                const int g = e / NBLK, comp = e - g * NBLK;
-                if (!((gnz >> (g * gs)) & 1ull)) continue;
+              // a lane holds one component's E rows in registers and runs over
+              // the groups of its lane set (64 / NBLK sets share the groups when
+              // NBLK < 64), so the rows are read once per component, not per group
+              constexpr int RS = NBLK >= 64 ? 1 : 64 / NBLK;
+              for (int cb = lane; cb < NBLK * RS; cb += 64) {
+                const int comp = cb % NBLK, gset = cb / NBLK;
                 const int c = s_ctab[comp];
                 const int ic = c & 0xff;
-                const double *ex = s_E + 0 * EA + ((c >> 8) & 0xff) * (LAB + 1);
-                const double *ey = s_E + 1 * EA + ((c >> 16) & 0xff) * (LAB + 1);
-                const double *ez = s_E + 2 * EA + ((c >> 24) & 0xff) * (LAB + 1);
+                double ex[LAB + 1], ey[LAB + 1], ez[LAB + 1];
+#pragma unroll
+                for (int t = 0; t <= LAB; ++t) {
+                  ex[t] = s_E[0 * EA + ((c >> 8) & 0xff) * (LAB + 1) + t];
+                  ey[t] = s_E[1 * EA + ((c >> 16) & 0xff) * (LAB + 1) + t];
+                  ez[t] = s_E[2 * EA + ((c >> 24) & 0xff) * (LAB + 1) + t];
+                }
+                for (int g = gset; g < ngrp; g += RS) {
+                if (!((gnz >> (g * gs)) & 1ull)) continue;
                 const double *wr = s_W + g * NW + ic * NHAB;
                 double so = 0.0;
 #pragma unroll
@@ -660,6 +677,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                     if (!pr.diag)
                       prm.X[(size_t)(c2 * nk + cg) * xplane + (rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
                   }
+                }
                 }
               }
               __syncthreads();
