@@ -587,8 +587,12 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
               const double coef = tcl[6] * Kab;
               __syncthreads();  // E coefficients and group sums visible to every lane
               // W[g][ic][h] = sum_{tau nu phi} E^c_{cx,tau} E^c_{cy,nu} E^c_{cz,phi} R[g][h + (tau nu phi)]
-              // a lane holds one entry's aux factors and Hermite indices and runs
-              // over the groups of its lane set (64 / NW sets when NW < 64)
+              if constexpr (L >= 5) {
+              // L >= 5 (one wave per SIMD, registers to spare in the AGPRs): a lane
+              // holds one entry's aux factors and Hermite indices and runs over the
+              // groups of its lane set (64 / NW sets when NW < 64); the lighter
+              // classes spill if they hold them, so their lanes take (group, entry)
+              // pairs in turn
               constexpr int RW = NW >= 64 ? 1 : 64 / NW;
               for (int cb = lane; cb < NW * RW; cb += 64) {
                 const int idx = cb % NW, gset = cb / NW;
@@ -626,10 +630,44 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   s_W[g * NW + idx] = sw;
                 }
               }
+              } else {
+              for (int e = lane; e < ngrp * NW; e += 64) {
+                const int g = e / NW, idx = e - g * NW;
+                if (!((gnz >> (g * gs)) & 1ull)) continue;
+                const int w = s_wtab[idx];
+                const int cx = w & 3, cy = (w >> 2) & 3, cz = (w >> 4) & 3;
+                double ex[KX + 1], ey[KX + 1], ez[KX + 1];
+#pragma unroll
+                for (int k = 0; k <= KX; ++k) {
+                  const int tx = (cx & 1) + 2 * k, ty = (cy & 1) + 2 * k, tz = (cz & 1) + 2 * k;
+                  ex[k] = (tx <= cx) ? s_EP[cx * (LP + 1) + min(tx, LP)] : 0.0;
+                  ey[k] = (ty <= cy) ? s_EP[cy * (LP + 1) + min(ty, LP)] : 0.0;
+                  ez[k] = (tz <= cz) ? s_EP[cz * (LP + 1) + min(tz, LP)] : 0.0;
+                }
+                const double *rg = s_R + g * (NH + 1);
+                const short *wi = s_widx + idx * NK;
+                // every group sum this entry needs, read before the first multiply
+                double rv[NK];
+#pragma unroll
+                for (int k = 0; k < NK; ++k) rv[k] = rg[wi[k]];
+                double sw = 0.0;
+#pragma unroll
+                for (int kx = 0; kx <= KX; ++kx)
+#pragma unroll
+                  for (int ky = 0; ky <= KX; ++ky) {
+                    double sz = 0.0;
+#pragma unroll
+                    for (int kz = 0; kz <= KX; ++kz) sz += ez[kz] * rv[(kx * (KX + 1) + ky) * (KX + 1) + kz];
+                    sw += ex[kx] * ey[ky] * sz;
+                  }
+                s_W[g * NW + idx] = sw;
+              }
+              }
               __syncthreads();
               // component (ic, ia, ib) of group g = sum_{tuv} E^x_t E^y_u E^z_v W[g][ic][tuv]
-              // a lane holds one component's E rows in registers and runs over
-              // the groups of its lane set (64 / NBLK sets share the groups when
+              if constexpr (L >= 5) {
+              // L >= 5: a lane holds one component's E rows in registers and runs
+              // over the groups of its lane set (64 / NBLK sets share the groups when
               // NBLK < 64), so the rows are read once per component, not per group
               constexpr int RS = NBLK >= 64 ? 1 : 64 / NBLK;
               for (int cb = lane; cb < NBLK * RS; cb += 64) {
@@ -679,6 +717,50 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
                   }
                 }
                 }
+              }
+              } else {
+              for (int e = lane; e < ngrp * NBLK; e += 64) {
+                const int g = e / NBLK, comp = e - g * NBLK;
+                if (!((gnz >> (g * gs)) & 1ull)) continue;
+                const int c = s_ctab[comp];
+                const int ic = c & 0xff;
+                const double *ex = s_E + 0 * EA + ((c >> 8) & 0xff) * (LAB + 1);
+                const double *ey = s_E + 1 * EA + ((c >> 16) & 0xff) * (LAB + 1);
+                const double *ez = s_E + 2 * EA + ((c >> 24) & 0xff) * (LAB + 1);
+                const double *wr = s_W + g * NW + ic * NHAB;
+                double so = 0.0;
+#pragma unroll
+                for (int t = 0; t <= LAB; ++t) {
+                  double st = 0.0;
+#pragma unroll
+                  for (int u = 0; u <= LAB - t; ++u) {
+                    double su = 0.0;
+#pragma unroll
+                    for (int v = 0; v <= LAB - t - u; ++v) su += ez[v] * wr[hidx(t, u, v)];
+                    st += ey[u] * su;
+                  }
+                  so += ex[t] * st;
+                }
+                const double val = coef * so;
+                if (blk_in_lds) {
+                  s_blk[g * NBLK + comp] += val;
+                } else {
+                  const int cg = wk.cb0 + g;
+                  const int ig0 = cg / (lat.n[1] * lat.n[2]), ig1 = (cg / lat.n[2]) % lat.n[1], ig2 = cg % lat.n[2];
+                  const int dc0 = cls / (lat.n[1] * lat.n[2]), dc1 = (cls / lat.n[2]) % lat.n[1], dc2 = cls % lat.n[2];
+                  const int c2 = (((ig0 + dc0) % lat.n[0]) * lat.n[1] + (ig1 + dc1) % lat.n[1]) * lat.n[2] +
+                                 (ig2 + dc2) % lat.n[2];
+                  if (part) {
+                    part[((size_t)g * nk + c2) * NBLK + comp] += val;
+                  } else {
+                    const int ia = (comp / NCB) % NCA, ib = comp % NCB;
+                    const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
+                    prm.X[(size_t)(cg * nk + c2) * xplane + (rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += val;
+                    if (!pr.diag)
+                      prm.X[(size_t)(c2 * nk + cg) * xplane + (rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += val;
+                  }
+                }
+              }
               }
               __syncthreads();
               ++n_contr;
