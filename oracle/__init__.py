@@ -25,6 +25,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 COUL, ERF, ERFC = 0, 1, 2
 PART_SR, PART_G0, PART_LR = 1, 2, 4
+PART_M15 = 8  # the range-separation-free q sum of Eq. M15 (alone; omega and g_thr set the q sphere)
 PART_ALL = PART_SR | PART_G0 | PART_LR
 
 

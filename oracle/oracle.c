@@ -44,7 +44,7 @@
 #define ORC_PI 3.14159265358979323846264338327950288
 
 enum { ORC_COUL = 0, ORC_ERF = 1, ORC_ERFC = 2 };
-enum { ORC_PART_SR = 1, ORC_PART_G0 = 2, ORC_PART_LR = 4 };
+enum { ORC_PART_SR = 1, ORC_PART_G0 = 2, ORC_PART_LR = 4, ORC_PART_M15 = 8 };
 
 static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
@@ -490,7 +490,8 @@ static void bvk_of(const int *mm, const int *kmesh, int *cidx) {
  *   lattice[9], natm, coords[natm*3], basis/aux (shell arrays), kmesh[3],
  *   omega, cut   : per-term truncation cutoff of the oracle's own rule,
  *   g_thr        : keep q with exp(-q^2/4w^2) >= g_thr,
- *   parts        : bitmask ORC_PART_SR | ORC_PART_G0 | ORC_PART_LR,
+ *   parts        : bitmask ORC_PART_SR | ORC_PART_G0 | ORC_PART_LR, or
+ *                  ORC_PART_M15 alone (the range-separation-free q sum),
  *   all_pairs    : 0 -> k-pairs k1<=k2 (row-major upper triangle),
  *                  1 -> all Nk^2 ordered pairs (k1 major),
  *   naux_sel, aux_sel : aux shells to compute (others left zero),
@@ -748,8 +749,14 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
   }
 
   /* ---------------- LR reciprocal-space sum (Eq. M10, M11), one AO shell
-   * pair per task so each pair transform is evaluated once for all aux shells */
-  if (parts & ORC_PART_LR) {
+   * pair per task so each pair transform is evaluated once for all aux shells.
+   * With ORC_PART_M15 instead, the same q sum without range separation
+   * (Eq. M15): weight 4 pi/(Omega q^2) with no Gaussian damping; omega and
+   * g_thr then only fix the q sphere (exp(-q^2/4w^2) >= g_thr), which the
+   * caller makes large enough for the transforms to have decayed. */
+  const int m15 = (parts & ORC_PART_M15) != 0;
+  if (m15 && (parts & ORC_PART_LR)) err = 1;
+  if ((parts & (ORC_PART_LR | ORC_PART_M15)) && !err) {
     const double q2max = -4.0 * omega * omega * log(g_thr);
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : nlr)
     for (int pr = 0; pr < nbs * nbs; ++pr) {
@@ -809,7 +816,7 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
               if (q2 < 1e-20) continue; /* the q = 0 term is excluded */
               const double damp = exp(-q2 / (4.0 * omega * omega));
               if (damp < g_thr) continue;
-              const double wgt = 4.0 * ORC_PI / L.vol * damp / q2;
+              const double wgt = 4.0 * ORC_PI / L.vol * (m15 ? 1.0 : damp) / q2;
               /* rho^^{k2}_{mu nu}(q) = sum_n e^{+i k2.n} int phi_mu(r) phi_nu(r-n) e^{-iq.r} dr */
               for (int x = 0; x < 2 * nca * ncb; ++x) rho[x] = 0.0;
               for (int ka = 0; ka < npa; ++ka)

@@ -15,5 +15,8 @@ from .configs import (  # noqa: F401
     config4_cells,
     config5,
     tiny_problem,
+    nacl_problem,
+    NACL_CHARGES,
+    supercell,
     cart_count,
 )

@@ -243,3 +243,49 @@ def tiny_problem(kmesh=(1, 1, 1), omega=0.5, seed=7, diffuse=True) -> Problem:
     for atom, l in aux:
         ax.add(atom, l, _log_uniform(rng, 0.3, hi, 1), [1.0])
     return Problem("tiny", Cell(lat, coords), bs.basis(), ax.basis(), tuple(kmesh), omega)
+
+
+def nacl_problem(a: float = 8.0, alpha_aux: float = 6.0, alpha_ao: float = 3.0, omega: float = 0.5) -> Problem:
+    """Rock salt in its 8-ion conventional cubic cell (nearest-neighbour
+    distance a/2).  Every ion carries one aux s primitive normalised to unit
+    charge, (alpha/pi)^{3/2} exp(-alpha r^2), and one AO s primitive whose
+    square has unit charge, (2 alpha/pi)^{3/4} exp(-alpha r^2).  Ions 0-3
+    (face-centred sites) are the cations, 4-7 (shifted by a/2 x) the anions.
+    Gamma only."""
+    fr = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]], float)
+    fr = np.vstack([fr, fr + np.array([0.5, 0.0, 0.0])])
+    cell = Cell(np.eye(3) * a, fr * a)
+    n = cell.natm
+    idx = np.arange(n, dtype=np.int32)
+    ones = np.ones(n, np.int32)
+    zeros = np.zeros(n, np.int32)
+    aux = Basis(idx, zeros, ones, idx.copy(), np.full(n, alpha_aux), np.full(n, (alpha_aux / math.pi) ** 1.5))
+    ao = Basis(idx.copy(), zeros.copy(), ones.copy(), idx.copy(), np.full(n, alpha_ao),
+               np.full(n, (2.0 * alpha_ao / math.pi) ** 0.75))
+    return Problem("NaCl", cell, ao, aux, (1, 1, 1), omega)
+
+
+NACL_CHARGES = np.array([1.0] * 4 + [-1.0] * 4)
+
+
+def supercell(problem: Problem, reps) -> Problem:
+    """The Born-von Karman supercell of ``problem``: lattice rows scaled by
+    reps, atoms and shells repeated per cell c = (c1 r2 + c2) r3 + c3 (cell
+    major, then the original order), Gamma only."""
+    reps = tuple(int(r) for r in reps)
+    lat = np.asarray(problem.cell.lattice, float)
+    cells = [(i, j, k) for i in range(reps[0]) for j in range(reps[1]) for k in range(reps[2])]
+    natm = problem.cell.natm
+    coords = np.vstack([problem.cell.coords + np.array(c, float) @ lat for c in cells])
+
+    def tile(b: Basis) -> Basis:
+        nprim_tot = len(b.exps)
+        return Basis(np.concatenate([b.shell_atom + natm * i for i in range(len(cells))]).astype(np.int32),
+                     np.tile(b.shell_l, len(cells)).astype(np.int32),
+                     np.tile(b.shell_nprim, len(cells)).astype(np.int32),
+                     np.concatenate([b.shell_ptr + nprim_tot * i for i in range(len(cells))]).astype(np.int32),
+                     np.tile(b.exps, len(cells)), np.tile(b.coefs, len(cells)))
+
+    sup = Cell(lat * np.array(reps, float)[:, None], coords)
+    return Problem(problem.name + f"[{reps[0]}x{reps[1]}x{reps[2]} supercell]", sup, tile(problem.basis),
+                   tile(problem.aux), (1, 1, 1), problem.omega, problem.thresh, problem.g_thr)

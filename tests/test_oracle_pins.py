@@ -321,3 +321,90 @@ def test_selection_restricts_work_only():
             mask[kps, xo[P]:xo[P + 1], bo[mu]:bo[mu + 1], bo[nu]:bo[nu + 1]] = True
     assert np.array_equal(got[mask], full[mask])
     assert not np.any(got[~mask])
+
+
+# ------------------------------------------------- the regime of the workloads
+def test_truncation_convergence_omega01():
+    """At omega = 0.1, the range separation of every benchmark workload, the
+    erfc tail reaches R_c ~ 50 bohr; the oracle's own per-term cutoff (1e-15
+    by default) must still be converged there (SI: the screening error is
+    controlled by epsilon).  C1, an s and a d aux shell."""
+    p = synth.config1()
+    sel = [0, 6]
+    V15 = oracle.j3c(p, aux_shells=sel, cut=1e-15)
+    V18 = oracle.j3c(p, aux_shells=sel, cut=1e-18)
+    assert np.abs(V15 - V18).max() <= 1e-11, np.abs(V15 - V18).max()
+    assert np.abs(V18).max() > 0.1
+
+
+def test_omega_independence_omega01_vs_03():
+    """j3c at omega = 0.1 (a few q vectors, a long real-space tail) equals
+    j3c at omega = 0.3 (Eq. M9 splits 1/r exactly)."""
+    p = synth.config1()
+    sel = [0, 6]
+    V1 = oracle.j3c(p, omega=0.1, aux_shells=sel)
+    V3 = oracle.j3c(p, omega=0.3, aux_shells=sel)
+    assert np.abs(V1 - V3).max() <= 1e-10, np.abs(V1 - V3).max()
+
+
+# ------------------------------------------------------ special cases
+MADELUNG_NACL = 1.747564594633182  # rock-salt Madelung constant (nearest-neighbour distance units)
+
+
+def test_nacl_madelung():
+    """Rock salt with every ion a unit Gaussian charge (one aux function and
+    one AO function whose square is that charge, both tight).  The
+    G=0-removed j3c at Gamma gives the electrostatic energy per cell of the
+    neutral periodic charge array, 1/2 sum_ij q_i q_j V[P_i; mu_j mu_j]; minus
+    each ion's self-interaction (2/sqrt(pi)) eta_1 (the R -> 0 limit of Eq.
+    S7's erf form) it is the point-charge Madelung energy, -alpha_M per ion
+    pair over the nearest-neighbour distance.  Pins the absolute
+    normalisation 4 pi/Omega of Eq. M10, the G=0 term of Eq. M12 and the
+    lattice sums of Eq. M13a together."""
+    p = synth.nacl_problem(a=8.0, alpha_aux=6.0, alpha_ao=3.0, omega=0.5)
+    V = oracle.j3c(p, pairs=[(j, j) for j in range(8)], cut=1e-17)
+    assert np.abs(V.imag).max() <= 1e-14
+    V = V.real[0]
+    q = synth.NACL_CHARGES
+    Vd = np.array([[V[i, j, j] for j in range(8)] for i in range(8)])
+    E = 0.5 * q @ Vd @ q
+    eta1 = math.sqrt(6.0 * 6.0 / (6.0 + 6.0))  # aux exponent 6, AO square exponent 2 x 3
+    self_energy = 0.5 * float(np.sum(q ** 2)) * 2.0 / math.sqrt(math.pi) * eta1
+    r0 = 8.0 / 2
+    assert abs((E - self_energy) - (-4 * MADELUNG_NACL / r0)) <= 1e-9, E - self_energy
+
+
+def test_bvk_supercell_gamma_equals_kmesh():
+    """The Gamma-point j3c of the 2x1x1 Born-von Karman supercell, Fourier
+    transformed over the cell indices of mu and nu, equals the 2x1x1 k-mesh
+    result:  V^{k1k2}_{P mu nu} = sum_{c1,c2} e^{-ik1.L_c1} e^{+ik2.L_c2}
+    V^S[(0,P)][(c1,mu)][(c2,nu)]  (Eq. M14; the supercell's q = 0 maps to
+    k12 = 0, Eq. M10)."""
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.8, diffuse=False)
+    Vk = oracle.j3c(p, all_pairs=True, cut=1e-17)
+    S = synth.supercell(p, (2, 1, 1))
+    VS = oracle.j3c(S, cut=1e-17)[0]
+    nx, nf = p.aux.nfunc, p.basis.nfunc
+    ks = oracle.kpoints(p)
+    Lc = [np.zeros(3), np.asarray(p.cell.lattice[0], float)]
+    for t, (k1, k2) in enumerate(oracle.kpair_list(p.kmesh, all_pairs=True)):
+        ref = np.zeros((nx, nf, nf), complex)
+        for c1 in range(2):
+            for c2 in range(2):
+                ref += (np.exp(-1j * ks[k1] @ Lc[c1]) * np.exp(1j * ks[k2] @ Lc[c2]) *
+                        VS[:nx, c1 * nf:(c1 + 1) * nf, c2 * nf:(c2 + 1) * nf])
+        assert np.abs(ref - Vk[t]).max() <= 1e-12, (t, np.abs(ref - Vk[t]).max())
+
+
+def test_range_separation_free_sum_on_diffuse_basis():
+    """Eq. M15: for diffuse functions the j3c is the plain reciprocal-space
+    sum (4 pi/Omega) sum_{q != 0} chi~_P(-q) rho^(q)/q^2 with no range
+    separation.  With a q sphere large enough for the transforms to decay
+    it equals the range-separated result (SR - G0 + LR), at Gamma and with
+    k1 != k2."""
+    for kmesh in [(1, 1, 1), (2, 1, 1)]:
+        p = synth.tiny_problem(kmesh=kmesh, omega=0.7, diffuse=True)
+        Vrs = oracle.j3c(p, cut=1e-17, all_pairs=True)
+        Vft = oracle.j3c(p, omega=1.2, g_thr=1e-12, parts=oracle.PART_M15, all_pairs=True)
+        assert np.abs(Vft - Vrs).max() <= 1e-10, (kmesh, np.abs(Vft - Vrs).max())
+        assert np.abs(Vrs).max() > 0.1
