@@ -61,6 +61,8 @@ def lib():
         L.orc_j3c.restype = i
         L.orc_j3c.argtypes = [P, i, P, i, P, P, P, P, P, P, i, P, P, P, P, P, P, P, d, d, d, i, i, i, P, i, P,
                               i, P, P, P]
+        L.orc_j2c.restype = i
+        L.orc_j2c.argtypes = [P, i, P, i, P, P, P, P, P, P, P, d, d, d, i, P, P]
         L.orc_num_threads.restype = i
         _lib = L
     return _lib
@@ -152,6 +154,53 @@ def j3c(problem, omega=None, cut=1e-15, g_thr=None, parts=PART_ALL, all_pairs=Fa
     if return_counts:
         return out, counts
     return out
+
+
+def j2c(problem, omega=None, cut=1e-15, g_thr=None, parts=PART_ALL, return_counts=False):
+    """Oracle two-center metric J^k_PQ (Eq. M5, q = 0 removed) of the aux basis
+    for every k of the mesh: complex128 [nk][naux][naux], k in mesh order
+    (j = (j1 n2 + j2) n3 + j3).  ``parts`` as for j3c (PART_M15 alone: the plain
+    reciprocal-space sum)."""
+    omega = problem.omega if omega is None else omega
+    g_thr = problem.g_thr if g_thr is None else g_thr
+    cell, ax = problem.cell, problem.aux
+    lat = np.ascontiguousarray(cell.lattice, np.float64).reshape(9)
+    crd = np.ascontiguousarray(cell.coords, np.float64)
+    km = np.asarray(problem.kmesh, np.int32)
+    nk = int(np.prod(problem.kmesh))
+    out = np.zeros((nk, ax.nfunc, ax.nfunc), np.complex128)
+    counts = np.zeros(2, np.int64)
+    arrs = [np.ascontiguousarray(a) for a in (ax.shell_atom, ax.shell_l, ax.shell_nprim, ax.shell_ptr, ax.exps,
+                                                ax.coefs)]
+    rc = lib().orc_j2c(_ptr(lat), cell.natm, _ptr(crd), ax.nshell, *[_ptr(a) for a in arrs], _ptr(km), float(omega),
+                       float(cut), float(g_thr), int(parts), _ptr(out), _ptr(counts))
+    if rc:
+        raise RuntimeError(f"orc_j2c failed ({rc})")
+    if return_counts:
+        return out, counts
+    return out
+
+
+def df_coefficients(J, V, kmesh, all_pairs=False):
+    """The density-fitting coefficients of Eq. M4: solve J^{k12} d^{k1k2} = V^{k1k2}
+    for every k-pair (k12 = k2 - k1 folded onto the mesh), by a Cholesky
+    factorisation of each Hermitian positive-definite J^k and two triangular
+    solves (numpy/scipy library routines).  J: [nk][naux][naux]; V:
+    [nkpair][naux][nao][nao]; returns d with V's shape."""
+    import scipy.linalg as sla
+    n = tuple(int(x) for x in kmesh)
+    pairs = kpair_list(n, all_pairs)
+    d = np.empty_like(V)
+    naux = V.shape[1]
+    chol = {}
+    for t, (k1, k2) in enumerate(pairs):
+        j1 = np.unravel_index(k1, n)
+        j2 = np.unravel_index(k2, n)
+        c = int(np.ravel_multi_index(tuple((b - a) % m for a, b, m in zip(j1, j2, n)), n))
+        if c not in chol:
+            chol[c] = sla.cho_factor(J[c], lower=True)
+        d[t] = sla.cho_solve(chol[c], V[t].reshape(naux, -1)).reshape(V.shape[1:])
+    return d
 
 
 def num_threads() -> int:

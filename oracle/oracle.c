@@ -879,6 +879,216 @@ int orc_j3c(const double *lattice, int natm, const double *coords, int nbs, cons
   return err ? -2 : 0;
 }
 
+/*
+ * orc_j2c: the two-center metric of the density fit, Eq. M5,
+ *   J^k_PQ = (chi_P^{k*} | 1/r | chi_Q^k) = sum_m e^{+ik.m} (P^0 | 1/r | Q^m)
+ * with the q = 0 (G = 0 at k = 0) component removed, evaluated with the
+ * range separation of Eq. M9 exactly as the three-center integrals:
+ *   SR = sum_m e^{+ik.m} (P^0 | erfc(w r)/r | Q^m)
+ *   G0 = delta_{k0} pi/(Omega w^2) S_P S_Q
+ *   LR = (4 pi/Omega) sum_{q=G+k, q!=0, exp(-q^2/4w^2)>=gthr}
+ *          exp(-q^2/4w^2)/q^2 chi~_P(-q) chi~_Q(q)
+ *   J = SR - G0 + LR   (ORC_PART_M15 alone: the plain q sum with 4 pi/(Omega q^2)).
+ * The two-center primitive integral is the three-center one of orc_prim3c
+ * with the second orbital factor set to the constant 1 (exponent 0, l = 0),
+ * which its recurrences admit exactly.
+ * Truncation (oracle's own rule): a term (P prim, Q prim, m) is kept while
+ * |c_P c_Q| pi^3/(a_P a_Q)^{3/2} f(R; eta1, eta2) (1+R)^{l_P+l_Q} >= cut,
+ * eta1 = sqrt(a_P a_Q/(a_P+a_Q)).
+ *   out: complex128 [nk][naux][naux] (k in mesh order), zero-filled by the caller.
+ */
+int orc_j2c(const double *lattice, int natm, const double *coords, int nax, const int32_t *ax_atom,
+            const int32_t *ax_l, const int32_t *ax_nprim, const int32_t *ax_ptr, const double *ax_exps,
+            const double *ax_coefs, const int32_t *kmesh, double omega, double cut, double g_thr, int parts,
+            double *out, int64_t *counts) {
+  orc_lat L;
+  if (make_lattice(lattice, &L)) return -1;
+  if (!(omega > 0.0) || !(cut > 0.0) || !(g_thr > 0.0)) return -1;
+  for (int d = 0; d < 3; ++d)
+    if (kmesh[d] < 1) return -1;
+  const int m15 = (parts & ORC_PART_M15) != 0;
+  if (m15 && (parts & (ORC_PART_LR | ORC_PART_SR | ORC_PART_G0))) return -1;
+  (void)natm;
+  orc_basis ax = {nax, ax_atom, ax_l, ax_nprim, ax_ptr, ax_exps, ax_coefs};
+  int *xoff = (int *)malloc(sizeof(int) * (nax + 1));
+  const int naux = basis_offsets(&ax, xoff);
+  const int nk = kmesh[0] * kmesh[1] * kmesh[2];
+  double *kv = (double *)malloc(sizeof(double) * 3 * nk);
+  int *kj = (int *)malloc(sizeof(int) * 3 * nk);
+  for (int j0 = 0; j0 < kmesh[0]; ++j0)
+    for (int j1 = 0; j1 < kmesh[1]; ++j1)
+      for (int j2 = 0; j2 < kmesh[2]; ++j2) {
+        int k = (j0 * kmesh[1] + j1) * kmesh[2] + j2;
+        kj[3 * k] = j0; kj[3 * k + 1] = j1; kj[3 * k + 2] = j2;
+        for (int d = 0; d < 3; ++d)
+          kv[3 * k + d] = (double)j0 / kmesh[0] * L.b[0][d] + (double)j1 / kmesh[1] * L.b[1][d] +
+                          (double)j2 / kmesh[2] * L.b[2][d];
+      }
+  const size_t plane = (size_t)naux * naux;
+  int64_t nsr = 0, nlr = 0;
+  int err = 0;
+
+  /* ---- SR lattice sum: X[c(m)] then the DFT over the BvK cells */
+  if (parts & ORC_PART_SR) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nsr) reduction(| : err)
+    for (int pq = 0; pq < nax * nax; ++pq) {
+      const int P = pq / nax, Q = pq % nax;
+      const int lP = ax.l[P], lQ = ax.l[Q], ncP = ncart(lP), ncQ = ncart(lQ), blk = ncP * ncQ;
+      const double *C = coords + 3 * ax.atom[P], *B0 = coords + 3 * ax.atom[Q];
+      double *X = (double *)calloc((size_t)nk * blk, sizeof(double));
+      double tmp[100];
+      for (int iP = 0; iP < ax.nprim[P]; ++iP)
+        for (int iQ = 0; iQ < ax.nprim[Q]; ++iQ) {
+          const double gP = ax.exps[ax.ptr[P] + iP], cP = ax.coefs[ax.ptr[P] + iP];
+          const double gQ = ax.exps[ax.ptr[Q] + iQ], cQ = ax.coefs[ax.ptr[Q] + iQ];
+          const double Aest = fabs(cP * cQ) * pow(ORC_PI, 3) / pow(gP * gQ, 1.5);
+          const double eta1 = sqrt(gP * gQ / (gP + gQ));
+          const double eta2 = 1.0 / sqrt(1.0 / (eta1 * eta1) + 1.0 / (omega * omega));
+          double Fstar = 0.0, Rmax = 0.0;
+          for (double R = 0.0; R < 1000.0; R += 0.25) {
+            double v = f_sr(R, eta1, eta2) * pow(1.0 + R, lP + lQ);
+            if (v > Fstar) Fstar = v;
+            if (Aest * v >= cut) Rmax = R + 0.25;
+            if (R > 1.0 && Aest * v < 1e-3 * cut && v < Fstar) break;
+          }
+          /* lattice vectors m with |B0 + m - C| <= Rmax */
+          double dfrac[3];
+          for (int i = 0; i < 3; ++i) {
+            double t = 0.0;
+            for (int d = 0; d < 3; ++d) t += (C[d] - B0[d]) * L.b[i][d];
+            dfrac[i] = t / (2.0 * ORC_PI);
+          }
+          const int c0 = (int)lround(dfrac[0]), c1 = (int)lround(dfrac[1]), c2 = (int)lround(dfrac[2]);
+          const int v0 = box_halfwidth(&L, 0, Rmax), v1 = box_halfwidth(&L, 1, Rmax), v2 = box_halfwidth(&L, 2, Rmax);
+          for (int m0 = c0 - v0; m0 <= c0 + v0; ++m0)
+            for (int m1 = c1 - v1; m1 <= c1 + v1; ++m1)
+              for (int m2 = c2 - v2; m2 <= c2 + v2; ++m2) {
+                double mv[3], Bm[3], r = 0.0;
+                lat_vec(&L, m0, m1, m2, mv);
+                for (int d = 0; d < 3; ++d) {
+                  Bm[d] = B0[d] + mv[d];
+                  r += (Bm[d] - C[d]) * (Bm[d] - C[d]);
+                }
+                r = sqrt(r);
+                if (r > Rmax) continue;
+                if (Aest * f_sr(r, eta1, eta2) * pow(1.0 + r, lP + lQ) < cut) continue;
+                /* (P^0 | erfc | Q^m): aux P as the "c" centre, Q^m as orbital a, b = 1 */
+                if (orc_prim3c(ORC_ERFC, omega, lP, gP, C, lQ, gQ, Bm, 0, 0.0, Bm, tmp)) {
+                  err = 1;
+                  continue;
+                }
+                ++nsr;
+                int mm[3] = {m0, m1, m2}, cm;
+                bvk_of(mm, kmesh, &cm);
+                for (int t = 0; t < blk; ++t) X[(size_t)cm * blk + t] += cP * cQ * tmp[t];
+              }
+        }
+      /* J^k += sum_c e^{+ik.L_c} X[c] */
+      for (int k = 0; k < nk; ++k)
+        for (int c = 0; c < nk; ++c) {
+          int i0 = c / (kmesh[1] * kmesh[2]), i1 = (c / kmesh[2]) % kmesh[1], i2 = c % kmesh[2];
+          double ph = 2.0 * ORC_PI * ((double)kj[3 * k] * i0 / kmesh[0] + (double)kj[3 * k + 1] * i1 / kmesh[1] +
+                                      (double)kj[3 * k + 2] * i2 / kmesh[2]);
+          const double cr = cos(ph), ci = sin(ph);
+          for (int iP = 0; iP < ncP; ++iP)
+            for (int iQ = 0; iQ < ncQ; ++iQ) {
+              double v = X[(size_t)c * blk + iP * ncQ + iQ];
+              size_t o = (size_t)k * plane + (size_t)(xoff[P] + iP) * naux + xoff[Q] + iQ;
+              out[2 * o] += cr * v;
+              out[2 * o + 1] += ci * v;
+            }
+        }
+      free(X);
+    }
+  }
+
+  /* ---- G = 0 term at k = 0 (k index 0 is Gamma) */
+  if (parts & ORC_PART_G0) {
+    for (int P = 0; P < nax; ++P)
+      for (int Q = 0; Q < nax; ++Q) {
+        int pwP[64][3], pwQ[64][3];
+        cart_powers(ax.l[P], pwP);
+        cart_powers(ax.l[Q], pwQ);
+        for (int iP = 0; iP < ncart(ax.l[P]); ++iP)
+          for (int iQ = 0; iQ < ncart(ax.l[Q]); ++iQ) {
+            double SP = 0.0, SQ = 0.0;
+            for (int i = 0; i < ax.nprim[P]; ++i) {
+              double t = ax.coefs[ax.ptr[P] + i];
+              for (int d = 0; d < 3; ++d) t *= gauss_moment(pwP[iP][d], ax.exps[ax.ptr[P] + i]);
+              SP += t;
+            }
+            for (int i = 0; i < ax.nprim[Q]; ++i) {
+              double t = ax.coefs[ax.ptr[Q] + i];
+              for (int d = 0; d < 3; ++d) t *= gauss_moment(pwQ[iQ][d], ax.exps[ax.ptr[Q] + i]);
+              SQ += t;
+            }
+            size_t o = (size_t)(xoff[P] + iP) * naux + xoff[Q] + iQ;
+            out[2 * o] -= ORC_PI / (L.vol * omega * omega) * SP * SQ;
+          }
+      }
+  }
+
+  /* ---- LR (or the range-separation-free sum): q = G + k */
+  if (parts & (ORC_PART_LR | ORC_PART_M15)) {
+    const double q2max = -4.0 * omega * omega * log(g_thr);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nlr)
+    for (int k = 0; k < nk; ++k) {
+      const double *kk = kv + 3 * k;
+      const double qm = sqrt(q2max) + sqrt(kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2]);
+      int gw[3];
+      for (int i = 0; i < 3; ++i) {
+        double an = sqrt(L.a[i][0] * L.a[i][0] + L.a[i][1] * L.a[i][1] + L.a[i][2] * L.a[i][2]);
+        gw[i] = (int)ceil(qm * an / (2.0 * ORC_PI)) + 1;
+      }
+      double *ft = (double *)malloc(sizeof(double) * 4 * naux); /* chi~(-q), chi~(+q) */
+      for (int g0i = -gw[0]; g0i <= gw[0]; ++g0i)
+        for (int g1i = -gw[1]; g1i <= gw[1]; ++g1i)
+          for (int g2i = -gw[2]; g2i <= gw[2]; ++g2i) {
+            double q[3], mq[3], q2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+              q[d] = g0i * L.b[0][d] + g1i * L.b[1][d] + g2i * L.b[2][d] + kk[d];
+              mq[d] = -q[d];
+              q2 += q[d] * q[d];
+            }
+            if (q2 < 1e-20) continue;
+            const double damp = exp(-q2 / (4.0 * omega * omega));
+            if (damp < g_thr) continue;
+            const double wgt = 4.0 * ORC_PI / L.vol * (m15 ? 1.0 : damp) / q2;
+            ++nlr;
+            for (int P = 0; P < nax; ++P)
+              for (int iP = 0; iP < ncart(ax.l[P]); ++iP) {
+                double am[2] = {0.0, 0.0}, ap[2] = {0.0, 0.0};
+                for (int i = 0; i < ax.nprim[P]; ++i) {
+                  double r1[2], r2[2];
+                  orc_prim_ft(ax.l[P], iP, ax.exps[ax.ptr[P] + i], coords + 3 * ax.atom[P], mq, r1);
+                  orc_prim_ft(ax.l[P], iP, ax.exps[ax.ptr[P] + i], coords + 3 * ax.atom[P], q, r2);
+                  am[0] += ax.coefs[ax.ptr[P] + i] * r1[0];
+                  am[1] += ax.coefs[ax.ptr[P] + i] * r1[1];
+                  ap[0] += ax.coefs[ax.ptr[P] + i] * r2[0];
+                  ap[1] += ax.coefs[ax.ptr[P] + i] * r2[1];
+                }
+                const int f = xoff[P] + iP;
+                ft[4 * f] = am[0]; ft[4 * f + 1] = am[1]; ft[4 * f + 2] = ap[0]; ft[4 * f + 3] = ap[1];
+              }
+            for (int a = 0; a < naux; ++a)
+              for (int b = 0; b < naux; ++b) {
+                const double xr = ft[4 * a], xi = ft[4 * a + 1], yr = ft[4 * b + 2], yi = ft[4 * b + 3];
+                size_t o = (size_t)k * plane + (size_t)a * naux + b;
+                out[2 * o] += wgt * (xr * yr - xi * yi);
+                out[2 * o + 1] += wgt * (xr * yi + xi * yr);
+              }
+          }
+      free(ft);
+    }
+  }
+  if (counts) {
+    counts[0] = nsr;
+    counts[1] = nlr;
+  }
+  free(xoff); free(kv); free(kj);
+  return err ? -2 : 0;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

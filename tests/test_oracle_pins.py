@@ -408,3 +408,130 @@ def test_range_separation_free_sum_on_diffuse_basis():
         Vft = oracle.j3c(p, omega=1.2, g_thr=1e-12, parts=oracle.PART_M15, all_pairs=True)
         assert np.abs(Vft - Vrs).max() <= 1e-10, (kmesh, np.abs(Vft - Vrs).max())
         assert np.abs(Vrs).max() > 0.1
+
+
+# ------------------------------------------------ two-center metric (Eq. M5)
+def _two_center_closed(kind, omega, gc, C, ga, A):
+    """(c | w | a) for unnormalised 1s primitives: pi^3/(a_c a_a)^{3/2} times
+    erf(eta R)/R at eta1 = sqrt(a_c a_a/(a_c + a_a)) (Coulomb), at
+    eta2 = (eta1^-2 + w^-2)^{-1/2} (erf), or their difference (erfc)."""
+    A, C = (mpmath.matrix([mpmath.mpf(x) for x in v]) for v in (A, C))
+    ga, gc, omega = (mpmath.mpf(x) for x in (ga, gc, omega))
+    R = mpmath.sqrt(sum((A[i] - C[i]) ** 2 for i in range(3)))
+    eta1 = mpmath.sqrt(gc * ga / (gc + ga))
+    eta2 = 1 / mpmath.sqrt(1 / eta1 ** 2 + 1 / omega ** 2)
+
+    def g(eta):
+        return 2 * eta / mpmath.sqrt(mpmath.pi) if R < mpmath.mpf("1e-30") else mpmath.erf(eta * R) / R
+
+    val = {oracle.COUL: g(eta1), oracle.ERF: g(eta2), oracle.ERFC: g(eta1) - g(eta2)}[kind]
+    return mpmath.pi ** 3 / (gc * ga) ** mpmath.mpf(1.5) * val
+
+
+@pytest.mark.parametrize("kind", [oracle.COUL, oracle.ERF, oracle.ERFC])
+def test_two_center_primitive_closed_form(kind):
+    """The oracle's two-center primitive integral (its three-center routine
+    with the second orbital factor the constant 1) against the s-type closed
+    form, and a (d|f) block against centre derivatives of it."""
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(21)
+    for _ in range(15):
+        gc, ga = np.exp(rng.uniform(np.log(0.05), np.log(30.0), 2))
+        omega = float(np.exp(rng.uniform(np.log(0.05), np.log(3.0))))
+        A, C = rng.normal(size=(2, 3)) * rng.uniform(0.0, 4.0)
+        got = oracle.prim3c(kind, omega, 0, gc, C, 0, ga, A, 0, 0.0, A)[0, 0, 0]
+        ref = float(_two_center_closed(kind, omega, gc, C, ga, A))
+        scale = max(1.0, abs(float(_two_center_closed(oracle.COUL, omega, gc, C, ga, A))))
+        assert abs(got - ref) <= 2e-14 * scale, (got, ref)
+    if kind != oracle.ERFC:
+        return
+    la, lc, ga, gc, omega = 2, 3, 0.8, 1.1, 0.5
+    A = np.array([0.3, -0.2, 0.5])
+    C = np.array([1.2, 0.4, -0.7])
+    blk = oracle.prim3c(oracle.ERFC, omega, lc, gc, C, la, ga, A, 0, 0.0, A)
+    x0 = [mpmath.mpf(v) for v in list(A) + list(C)]
+    for ic, ia in [(0, 0), (3, 1), (9, 5), (5, 2), (7, 4)]:
+        pa, pc = _cart(la)[ia], _cart(lc)[ic]
+        coef = [_deriv_coefs(pa[d], mpmath.mpf(ga)) for d in range(3)] + \
+               [_deriv_coefs(pc[d], mpmath.mpf(gc)) for d in range(3)]
+        total = mpmath.mpf(0)
+        f = lambda *x: _two_center_closed(oracle.ERFC, omega, gc, x[3:6], ga, x[0:3])  # noqa: E731
+
+        def rec(i, orders, c):
+            nonlocal total
+            if i == 6:
+                total += c * mpmath.diff(f, x0, tuple(orders))
+                return
+            for j, cj in coef[i].items():
+                rec(i + 1, orders + [j], c * cj)
+
+        rec(0, [], mpmath.mpf(1))
+        assert abs(blk[ic, ia, 0] - float(total)) <= 1e-12 * max(np.abs(blk).max(), 1e-3), (ic, ia)
+
+
+def test_j2c_invariants():
+    """J^k (Eq. M5 with the range separation of Eq. M9): omega-independent,
+    Hermitian per k, positive definite (a Coulomb metric with q = 0 removed)."""
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.8, diffuse=False)
+    J1 = oracle.j2c(p)
+    J2 = oracle.j2c(p, omega=1.3)
+    assert np.abs(J1 - J2).max() <= 1e-10, np.abs(J1 - J2).max()
+    for k in range(J1.shape[0]):
+        assert np.abs(J1[k] - J1[k].conj().T).max() <= 1e-13
+        assert np.linalg.eigvalsh(J1[k]).min() > 0.0
+    assert np.abs(J1[0].imag).max() <= 1e-13  # Gamma: real symmetric
+
+
+def test_j2c_range_separation_free_and_supercell():
+    """Diffuse aux basis: J = the plain q sum of Eq. M15 with 4 pi/(Omega q^2);
+    and the 2x1x1 supercell's Gamma metric, Fourier transformed over the cell
+    index of Q, is J^k (Eq. M14 for two centres)."""
+    pd = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.7, diffuse=True)
+    Jrs = oracle.j2c(pd, cut=1e-17)
+    Jft = oracle.j2c(pd, omega=1.4, g_thr=1e-12, parts=oracle.PART_M15)
+    assert np.abs(Jrs - Jft).max() <= 1e-10, np.abs(Jrs - Jft).max()
+    p = synth.tiny_problem(kmesh=(2, 1, 1), omega=0.8, diffuse=False)
+    J = oracle.j2c(p, cut=1e-17)
+    JS = oracle.j2c(synth.supercell(p, (2, 1, 1)), cut=1e-17)[0]
+    nx = p.aux.nfunc
+    ks = oracle.kpoints(p)
+    Lc = [np.zeros(3), np.asarray(p.cell.lattice[0], float)]
+    for k in range(2):
+        ref = sum(np.exp(1j * ks[k] @ Lc[c]) * JS[:nx, c * nx:(c + 1) * nx] for c in range(2))
+        assert np.abs(ref - J[k]).max() <= 1e-12
+
+
+def test_j2c_nacl_madelung():
+    """Rock salt of unit Gaussian charges: 1/2 q^T J^Gamma q minus the ions'
+    self-interactions (2/sqrt(pi)) sqrt(a a/(a + a)) is the Madelung energy."""
+    p = synth.nacl_problem(a=8.0, alpha_aux=6.0, alpha_ao=3.0, omega=0.5)
+    J = oracle.j2c(p, cut=1e-17)[0]
+    assert np.abs(J.imag).max() <= 1e-14
+    q = synth.NACL_CHARGES
+    E = 0.5 * q @ J.real @ q
+    self_energy = 0.5 * float(np.sum(q ** 2)) * 2.0 / math.sqrt(math.pi) * math.sqrt(6.0 * 6.0 / 12.0)
+    assert abs((E - self_energy) - (-4 * MADELUNG_NACL / 4.0)) <= 1e-9, E - self_energy
+
+
+def test_df_exact_fit():
+    """Eq. M4 with a pair density the aux basis holds exactly: in the rock-salt
+    cell every AO s function squared is its ion's aux function (cross-image
+    products vanish below 1e-40 at these exponents), so
+    V^{k1k2}[:, j, j] = J^{k12}[:, j] for every k-pair (the three-center and
+    two-center oracles agree), and the fit returns the unit vector e_j."""
+    p = synth.nacl_problem(a=8.0, alpha_aux=6.0, alpha_ao=3.0, omega=0.5)
+    p.kmesh = (2, 1, 1)
+    pairs = [(j, j) for j in range(8)]
+    V = oracle.j3c(p, pairs=pairs, cut=1e-17)
+    J = oracle.j2c(p, cut=1e-17)
+    ks = oracle.kpair_list(p.kmesh)
+    for t, (k1, k2) in enumerate(ks):
+        c = (k2 - k1) % 2  # k12 on the 2x1x1 mesh
+        for j in range(8):
+            assert np.abs(V[t, :, j, j] - J[c][:, j]).max() <= 1e-12
+    d = oracle.df_coefficients(J, V, p.kmesh)
+    for t in range(len(ks)):
+        for j in range(8):
+            e = np.zeros(8)
+            e[j] = 1.0
+            assert np.abs(d[t, :, j, j] - e).max() <= 1e-10
