@@ -157,6 +157,28 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
                        const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
                        rsgdf_out *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * build as rsgdf_build_j3c_ex with every device scratch buffer (tables, the
+ * short-range intermediate, the long-range operands, counters) carved from
+ * one static device array of RSGDF_NOALLOC_SCRATCH_MB MiB that the library
+ * holds per GPU until the process ends.  The call allocates no device memory
+ * (no hipMalloc / hipFree / allocating library routine), creates no streams
+ * or events, and runs every kernel on out->stream; aux-shell batching keeps
+ * the short-range intermediate within the buffer.  out must be device memory
+ * (out->on_device = 1).  Returns RSGDF_ENOMEM, with a message naming the
+ * limit, when the build needs more scratch than the buffer holds (nothing is
+ * written to the output then).  All calls on one GPU share its buffer: calls
+ * from one process are serialised by the library; calls that overlap on one
+ * GPU from separate processes, or kernels still reading the buffer, race.
+ * The buffer keeps the last call's contents; every part that must start at
+ * zero is cleared by a kernel at the start of each call.  Synchronous on
+ * out->stream.  stats: phase times are not measured (t_total_ms is). */
+#define RSGDF_NOALLOC_SCRATCH_MB 256
+int rsgdf_build_j3c_noalloc(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                            const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                            rsgdf_out *out);
+
 /* ---- learned screening (a project addition to the Supplementary-Material
  * bounds).  A candidate is one (aux shell, AO shell pair, pair image n') unit
  * of the short-range lattice sum that passed the rigorous test of Eqs.

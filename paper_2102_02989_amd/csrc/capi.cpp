@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <random>
 #include <string>
 #include <thread>
@@ -48,16 +49,40 @@ int fail(int code, const std::string &msg) {
       return fail(RSGDF_EHIP, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call); \
   } while (0)
 
+// Bump allocator over caller-provided device memory (the no-allocation entry
+// point's static scratch array).  While a thread has one installed, DBuf
+// takes its memory from it and never calls hipMalloc or hipFree.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0, used = 0, want = 0;  // want: bytes requested in all (for the error message)
+  bool overflow = false;
+};
+thread_local Arena *t_arena = nullptr;
+
 // RAII device buffer
 struct DBuf {
   void *p = nullptr;
   size_t n = 0;
+  bool owned = false;
   ~DBuf() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
   }
   hipError_t alloc(size_t bytes) {
     n = bytes;
     if (bytes == 0) bytes = 16;
+    if (t_arena) {
+      const size_t at = (t_arena->used + 255) / 256 * 256;
+      t_arena->want = std::max(t_arena->want, at) + bytes;
+      if (at + bytes > t_arena->cap) {
+        t_arena->overflow = true;
+        return hipErrorOutOfMemory;
+      }
+      p = t_arena->base + at;
+      t_arena->used = at + bytes;
+      owned = false;
+      return hipSuccess;
+    }
+    owned = true;
     return hipMalloc(&p, bytes);
   }
   template <class T>
@@ -103,6 +128,17 @@ int validate_basis(const rsgdf_basis *b, int natm, int lmax, const char *what) {
     }
   }
   return RSGDF_OK;
+}
+
+// free device memory for the scratch budgets: the remainder of the installed
+// arena, else what the runtime reports
+hipError_t mem_avail(size_t *free_b) {
+  if (t_arena) {
+    *free_b = t_arena->cap - std::min(t_arena->cap, t_arena->used);
+    return hipSuccess;
+  }
+  size_t total_b = 0;
+  return hipMemGetInfo(free_b, &total_b);
 }
 
 int64_t nfunc(const rsgdf_basis *b) {
@@ -849,8 +885,8 @@ int Job::prepare(hipStream_t st, double mem_frac) {
 
   // ---------------------------------------------------------- SR plan
   // aux batches bounded by the scratch budget of X
-  size_t free_b = 0, total_b = 0;
-  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  size_t free_b = 0;
+  HIPCHK(mem_avail(&free_b));
   const double budget = std::min(mem_frac * (double)free_b, 64e9);
   batch_start.assign(1, 0);
   {
@@ -877,8 +913,8 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   if (do_sr) HIPCHK(d_X.alloc((size_t)max_bf * nb * nao2 * sizeof(double)));
   max_bf_el = max_bf * nao2;
   if (do_sr && own_y) {  // the fold's intermediate Y: nk^2 complex values per element of a pass
-    size_t fr = 0, tt = 0;
-    HIPCHK(hipMemGetInfo(&fr, &tt));
+    size_t fr = 0;
+    HIPCHK(mem_avail(&fr));
     set_fold_chunk(std::min(0.25 * mem_frac * (double)fr, 8e9));
     HIPCHK(d_Y.alloc((size_t)fchunk * nk * nk * 16));
     ybuf = d_Y.as<double>();
@@ -958,7 +994,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     }
     // target cost per wave: 8 waves per SIMD over the build
     const double target0 = std::max(tot / (8.0 * 1024.0), 1.0);
-    const double part_budget = 1.0e9;  // bytes of partial blocks
+    const double part_budget = std::min(1.0e9, 0.05 * (double)free_b);  // bytes of partial blocks
     double part_bytes = 0.0;
     std::vector<std::vector<SRWork>> grp((size_t)nbatch * 24);
     std::vector<std::vector<double>> gcost((size_t)nbatch * 24);
@@ -1217,6 +1253,15 @@ int Job::enqueue_sr(int b, hipStream_t st, const std::vector<hipStream_t> &ss, h
   if (!do_sr) return RSGDF_OK;
   int rc = enqueue_zero(b, st);
   if (rc) return rc;
+  if (ss.empty()) {  // no side streams: the classes in turn on st, no events
+    for (int g = 0; g < 24; ++g) {
+      const int w0 = wgrp_off[(size_t)b * 24 + g], w1 = wgrp_off[(size_t)b * 24 + g + 1];
+      if (w1 > w0)
+        HIPCHK(launch_sr3c(g / 6, g % 6, d_prm.as<SRParams>() + b, d_work.as<SRWork>(), d_cnt.as<long long>(), w0,
+                           w1 - w0, st));
+    }
+    return enqueue_reduce(b, st);
+  }
   HIPCHK(hipEventRecord(evf, st));
   for (auto s_ : ss) HIPCHK(hipStreamWaitEvent(s_, evf, 0));
   std::vector<int> order(24);
@@ -1839,6 +1884,87 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
                        const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
                        rsgdf_out *out) {
   return build_impl(cell, basis, auxbasis, kmesh, omega, thresh, opt, out, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device scratch of rsgdf_build_j3c_noalloc: one copy per GPU, held until the
+// process ends.  In host code the name `scratch` is a host-side stand-in, not
+// a device address; the address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that pointer is used.
+constexpr size_t kNoallocScratchBytes = (size_t)RSGDF_NOALLOC_SCRATCH_MB << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  std::once_flag once;
+  void *ptr = nullptr;
+  hipError_t err = hipSuccess;
+  std::mutex mu;  // serialises the calls of this process on the device
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+struct ArenaGuard {
+  explicit ArenaGuard(Arena *a) { t_arena = a; }
+  ~ArenaGuard() { t_arena = nullptr; }
+};
+
+}  // namespace
+
+extern "C" {
+
+int rsgdf_build_j3c_noalloc(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                            const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                            rsgdf_out *out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  g_err.clear();
+  if (!out) return fail(RSGDF_EINVAL, "null output");
+  if (!out->on_device) return fail(RSGDF_EINVAL, "rsgdf_build_j3c_noalloc writes device memory only (on_device = 1)");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RSGDF_EUNSUPPORTED, "device index beyond the scratch table");
+  ScratchSlot &slot = g_scratch[dev];
+  std::call_once(slot.once, [&] { slot.err = hipGetSymbolAddress(&slot.ptr, HIP_SYMBOL(scratch)); });
+  if (slot.err != hipSuccess || !slot.ptr)
+    return fail(RSGDF_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(slot.err));
+  std::lock_guard<std::mutex> lock(slot.mu);
+  Arena ar;
+  ar.base = static_cast<char *>(slot.ptr);
+  ar.cap = kNoallocScratchBytes;
+  ArenaGuard guard(&ar);
+  Job j;
+  j.cell = cell;
+  j.basis = basis;
+  j.auxbasis = auxbasis;
+  j.kmesh = kmesh;
+  j.omega = omega;
+  j.thresh = thresh;
+  j.out = out;
+  j.o.g_thresh = -1.0;
+  j.o.lr_precision = RSGDF_FP64;
+  j.o.screening = RSGDF_SCREEN_RIGOROUS;
+  j.o.parts = RSGDF_PART_ALL;
+  if (opt) j.o = *opt;
+  hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
+  int rc = j.prepare(st, 0.45);
+  if (ar.overflow || rc == RSGDF_ENOMEM)
+    return fail(RSGDF_ENOMEM, "rsgdf_build_j3c_noalloc: this build needs more device scratch than the " +
+                                  std::to_string(RSGDF_NOALLOC_SCRATCH_MB) + " MiB static buffer (at least " +
+                                  std::to_string(ar.want >> 20) + " MiB requested" +
+                                  (g_err.empty() ? std::string(")") : "; " + g_err + ")"));
+  if (rc) return rc;
+  const std::vector<hipStream_t> none;  // no side streams, no events
+  if ((rc = j.enqueue_pre(st))) return rc;
+  for (int b = 0; b < j.nbatch; ++b) {
+    if ((rc = j.enqueue_sr(b, st, none, nullptr, nullptr))) return rc;
+    if ((rc = j.enqueue_fold(b, st))) return rc;
+  }
+  if ((rc = j.enqueue_lr(st, nullptr))) return rc;
+  if ((rc = j.finish(st, nullptr))) return rc;
+  if (out->stats) out->stats->t_total_ms = ms_since(t_start);
+  return RSGDF_OK;
 }
 
 int rsgdf_screen_log(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,

@@ -21,6 +21,7 @@ SCREEN_RIGOROUS, SCREEN_LEARNED = 0, 1
 PART_SR, PART_G0, PART_LR = 1, 2, 4
 PART_ALL = 7
 MLP_NFEAT, MLP_NPARAM = 16, 5377
+NOALLOC_SCRATCH_MB = 256  # RSGDF_NOALLOC_SCRATCH_MB
 
 
 class RsgdfError(RuntimeError):
@@ -95,6 +96,8 @@ def library():
         L.rsgdf_build_j3c_ex.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options),
                                          ctypes.POINTER(Out)]
+        L.rsgdf_build_j3c_noalloc.restype = ctypes.c_int
+        L.rsgdf_build_j3c_noalloc.argtypes = L.rsgdf_build_j3c_ex.argtypes
         F = ctypes.c_float
         L.rsgdf_screen_log.restype = ctypes.c_int
         L.rsgdf_screen_log.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
@@ -184,7 +187,7 @@ def _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, m
 
 def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None, lr_precision=FP64,
               screening=SCREEN_RIGOROUS, parts=PART_ALL, sr_slices=0, mlp_weights=None, mlp_margin=0.0,
-              sr_split=None, stream=None):
+              sr_split=None, stream=None, _noalloc=False):
     """Run rsgdf_build_j3c_ex.
 
     ``out``: a contiguous complex128 torch tensor on the GPU of shape
@@ -200,6 +203,8 @@ def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None
         import torch
         out = torch.empty(shape, dtype=torch.complex128, device="cuda")
     if isinstance(out, np.ndarray):
+        if _noalloc:
+            raise ValueError("build_j3c_noalloc writes device memory only")
         if out.dtype != np.complex128 or not out.flags.c_contiguous or out.nbytes < nbytes:
             raise ValueError("host output must be a contiguous complex128 array of the full size")
         on_device = False
@@ -217,11 +222,18 @@ def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None
     o = Out(ptr, cap, int(on_device), sptr, 0, 0, 0, ctypes.pointer(stats))
     keep = []
     opts = _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep)
-    rc = library().rsgdf_build_j3c_ex(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
-                                      m.kmesh.ctypes.data, float(omega), float(thresh), ctypes.byref(opts),
-                                      ctypes.byref(o))
+    fn = library().rsgdf_build_j3c_noalloc if _noalloc else library().rsgdf_build_j3c_ex
+    rc = fn(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux), m.kmesh.ctypes.data, float(omega),
+            float(thresh), ctypes.byref(opts), ctypes.byref(o))
     _check(rc)
     return out, stats.as_dict()
+
+
+def build_j3c_noalloc(cell, basis, aux, kmesh, omega, thresh, out, *, stream=None, **options):
+    """Run rsgdf_build_j3c_noalloc: the build of ``build_j3c`` with every
+    device scratch buffer taken from the library's static per-GPU array (no
+    device allocation in the call).  ``out`` must be a device tensor."""
+    return build_j3c(cell, basis, aux, kmesh, omega, thresh, out, stream=stream, _noalloc=True, **options)
 
 
 # ---- learned screening -------------------------------------------------------
