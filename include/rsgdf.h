@@ -157,6 +157,42 @@ int rsgdf_build_j3c_ex(const rsgdf_cell *cell, const rsgdf_basis *basis, const r
                        const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
                        rsgdf_out *out);
 
+/* ---- density fitting: the two-center metric and the fitting solve.
+ *
+ * J^k_PQ = (chi_P^{k*} | 1/r | chi_Q^k) = sum_m e^{+i k.m} (P^0 | 1/r | Q^m)
+ * (Eq. M5) with the q = 0 (G = 0 at k = 0) component removed, for every k of
+ * the Gamma-centred mesh (index j = (j1 n2 + j2) n3 + j3), evaluated with the
+ * range separation of Eq. M9 as the three-center integrals are: an erfc
+ * lattice sum (screened at 1e-2 thresh, Eq. S14's bound with one AO factor
+ * replaced by the aux function), minus pi/(Omega w^2) S_P S_Q at k = 0, plus
+ * (4 pi/Omega) sum_{q=G+k, q!=0, exp(-q^2/4w^2) >= g_thresh} exp(-q^2/4w^2)/q^2
+ * chi~_P(-q) chi~_Q(q) (Eq. M10) on the FP64 matrix cores.  J^{k12} is the
+ * metric that Eq. M4 pairs with V^{k1k2} (k12 = k2 - k1 folded onto the mesh).
+ * Output: complex128 [nk][naux][naux] (out->on_device as for the three-center
+ * build; out->nkpair = nk and out->naux = out->nao = naux on return).  opt
+ * (may be NULL): g_thresh and parts are used.  stats: t_sr_ms (short range and
+ * fold), t_lr_ms, n_sr_terms (evaluated (P prim, Q prim, m) terms),
+ * n_g_total, lr_gemm_flops. */
+int64_t rsgdf_j2c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const int32_t kmesh[3]);
+int rsgdf_build_j2c(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const int32_t kmesh[3], double omega,
+                    double thresh, const rsgdf_options *opt, rsgdf_out *out);
+
+/* The fitting coefficients of Eq. M4: for every k-pair (k1 <= k2, row-major)
+ *     sum_Q J^{k12}_PQ d^{k1k2}_{Q,c} = V^{k1k2}_{P,c},   c = 0..ncol-1,
+ * by a Cholesky factorisation J = L L^H per k, W = L^{-1} and J^{-1} = W^H W
+ * (FP64 vector ALUs), then d = J^{-1} V on the FP64 matrix cores.
+ *   j2c: device complex128 [nk][naux][naux] (rsgdf_build_j2c; the lower
+ *        triangle of each J^k is read);
+ *   j3c: device complex128 [nkpair][naux][ncol] (rsgdf_build_j3c output:
+ *        ncol = nao * nao);
+ *   d:   device complex128, same shape as j3c; may be j3c itself (then the
+ *        result goes through a bounded device temporary).
+ * Returns RSGDF_EINVAL if a J^k is not numerically positive definite (its
+ * k index is named in the message; d is then untouched).  Synchronous on
+ * stream (hipStream_t or NULL). */
+int rsgdf_df_solve(const int32_t kmesh[3], int64_t naux, int64_t ncol, const void *j2c, const void *j3c, void *d,
+                   void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * build as rsgdf_build_j3c_ex with every device scratch buffer (tables, the

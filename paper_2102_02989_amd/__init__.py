@@ -20,6 +20,9 @@ from .rsgdf import (  # noqa: F401
     SCREEN_RIGOROUS,
     RsgdfError,
     build_j3c,
+    build_j2c,
+    j2c_nbytes,
+    df_solve,
     build_j3c_noalloc,
     NOALLOC_SCRATCH_MB,
     j3c_nbytes,

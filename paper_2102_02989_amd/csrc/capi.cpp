@@ -268,6 +268,35 @@ double solve_r12(double NF, double beta, double eps) {
   return hi;
 }
 
+// largest x with NF x exp(-beta x^2) (1 + c x)^L >= eps, or 0 (Eq. S23 with the
+// angular growth of an l_a + l_b = L pair factor); the left side has one
+// maximum on x > 0, found by bisection on its logarithmic derivative
+double solve_r12_grow(double NF, double beta, double eps, int L, double c) {
+  if (L == 0) return solve_r12(NF, beta, eps);
+  if (!(NF > 0.0)) return 0.0;
+  auto dlog = [&](double x) { return 1.0 / x - 2.0 * beta * x + L * c / (1.0 + c * x); };
+  double lo = 1e-12, hi = 1.0;
+  while (dlog(hi) > 0 && hi < 1e6) hi *= 2.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (dlog(mid) > 0) lo = mid;
+    else hi = mid;
+  }
+  const double xm = hi;
+  const double c0 = std::log(NF) - std::log(eps);
+  auto g = [&](double x) { return c0 + std::log(x) - beta * x * x + L * std::log1p(c * x); };
+  if (g(xm) < 0) return 0.0;
+  lo = xm;
+  hi = 2.0 * xm;
+  while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
+  for (int it = 0; it < 52; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (g(mid) > 0) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
 template <class F>
 void parallel_for(int64_t n, F f) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -304,6 +333,110 @@ struct HostPlan {
   std::vector<int32_t> kp1, kp2;
 };
 
+// Packed shells of a basis: centre, l, primitive range, function offset and
+// the most diffuse primitive with its 1s-equivalent amplitude (the screening
+// bounds treat every function as 1s, Eq. S26).  Returns the function count.
+int64_t pack_shells(const rsgdf_basis *b, const double *coords, std::vector<Shell> &sh, std::vector<double> &ex,
+                    std::vector<double> &cf, std::vector<double> &c1s) {
+  int64_t foff = 0;
+  for (int s = 0; s < b->nshell; ++s) {
+    Shell x{};
+    const double *C = coords + 3 * b->shell_atom[s];
+    x.x = C[0];
+    x.y = C[1];
+    x.z = C[2];
+    x.l = b->shell_l[s];
+    x.nprim = b->shell_nprim[s];
+    x.pptr = (int32_t)ex.size();
+    x.foff = (int32_t)foff;
+    foff += ncart_h(x.l);
+    double amin = 1e300, cmin = 0.0;
+    for (int k = 0; k < x.nprim; ++k) {
+      const double a = b->exps[b->shell_ptr[s] + k], c = b->coefs[b->shell_ptr[s] + k];
+      ex.push_back(a);
+      cf.push_back(c);
+      // 1s function with the L2 norm of the x^l component of this primitive
+      const double c1 = std::fabs(c) * std::sqrt(dfact_odd(x.l) / std::pow(4.0 * a, x.l));
+      c1s.push_back(c1);
+      if (a < amin) {
+        amin = a;
+        cmin = c1;
+      }
+    }
+    x.a_d = amin;
+    x.c_d = cmin;
+    sh.push_back(x);
+  }
+  return foff;
+}
+
+// k-points of the Gamma-centred mesh, k_j = sum_i (j_i / n_i) b_i
+std::vector<double> mesh_kvec(const Lattice &L) {
+  std::vector<double> kv(3 * L.nk);
+  for (int j0 = 0; j0 < L.n[0]; ++j0)
+    for (int j1 = 0; j1 < L.n[1]; ++j1)
+      for (int j2 = 0; j2 < L.n[2]; ++j2) {
+        const int k = (j0 * L.n[1] + j1) * L.n[2] + j2;
+        for (int d = 0; d < 3; ++d)
+          kv[3 * k + d] = (double)j0 / L.n[0] * L.b[d] + (double)j1 / L.n[1] * L.b[3 + d] +
+                          (double)j2 / L.n[2] * L.b[6 + d];
+      }
+  return kv;
+}
+
+// G sets per folded k12 class c (Eq. M10): q = G + k_c, q != 0,
+// exp(-q^2/4w^2) >= g_thr, each sorted by |q|; qv [nq_tot][3], qoff [nk + 1]
+void make_qsets(const Lat &lt, const std::vector<double> &kvec, double omega, double g_thr, std::vector<double> &qv,
+                std::vector<int64_t> &qoff) {
+  const Lattice &L = lt.L;
+  const double q2max = -4.0 * omega * omega * std::log(g_thr);
+  qv.clear();
+  qoff.assign(1, 0);
+  for (int c = 0; c < L.nk; ++c) {
+    const double *kc = &kvec[3 * c];
+    const double qm = std::sqrt(std::max(q2max, 0.0)) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
+    int w[3];
+    for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(qm * lt.an[d] / (2.0 * kPi)) + 1;
+    std::vector<std::array<double, 4>> qc;  // (|q|^2, q)
+    for (int i = -w[0]; i <= w[0]; ++i)
+      for (int j = -w[1]; j <= w[1]; ++j)
+        for (int k = -w[2]; k <= w[2]; ++k) {
+          double q[3], q2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            q[d] = i * L.b[d] + j * L.b[3 + d] + k * L.b[6 + d] + kc[d];
+            q2 += q[d] * q[d];
+          }
+          if (q2 < 1e-20) continue;
+          if (std::exp(-q2 / (4.0 * omega * omega)) < g_thr) continue;
+          qc.push_back({q2, q[0], q[1], q[2]});
+        }
+    // by |q|, so that neighbouring lanes of the pair-transform kernel
+    // drop the same primitive pairs (the e^{-q^2/4p} factor)
+    std::stable_sort(qc.begin(), qc.end(), [](const std::array<double, 4> &x, const std::array<double, 4> &y) {
+      return x[0] < y[0];
+    });
+    for (const auto &e : qc) qv.insert(qv.end(), e.begin() + 1, e.end());
+    qoff.push_back((int64_t)qv.size() / 3);
+  }
+}
+
+// phase table kph[k][c] = e^{+i k.L_c} (complex, [nk][nk])
+std::vector<double> mesh_phases(const Lattice &L) {
+  const int nk = L.nk;
+  std::vector<double> kph((size_t)2 * nk * nk);
+  for (int k = 0; k < nk; ++k)
+    for (int c = 0; c < nk; ++c) {
+      const int j[3] = {k / (L.n[1] * L.n[2]), (k / L.n[2]) % L.n[1], k % L.n[2]};
+      const int i[3] = {c / (L.n[1] * L.n[2]), (c / L.n[2]) % L.n[1], c % L.n[2]};
+      long double t = 0.0L;  // 2 pi sum_d j_d i_d / n_d
+      for (int d = 0; d < 3; ++d) t += (long double)(j[d] * i[d] % L.n[d]) / L.n[d];
+      const double ph = (double)(2.0L * 3.14159265358979323846264338327950288L * t);
+      kph[2 * ((size_t)k * nk + c)] = std::cos(ph);
+      kph[2 * ((size_t)k * nk + c) + 1] = std::sin(ph);
+    }
+  return kph;
+}
+
 int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis *ax, const int32_t *kmesh,
                double omega, double thresh, HostPlan &hp) {
   int rc = make_lattice(cell, kmesh, hp.lt);
@@ -311,52 +444,11 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
   const Lattice &L = hp.lt.L;
   const int nk = L.nk;
   // shells
-  auto pack = [](const rsgdf_basis *b, const double *coords, std::vector<Shell> &sh, std::vector<double> &ex,
-                 std::vector<double> &cf, std::vector<double> &c1s) {
-    int64_t foff = 0;
-    for (int s = 0; s < b->nshell; ++s) {
-      Shell x{};
-      const double *C = coords + 3 * b->shell_atom[s];
-      x.x = C[0];
-      x.y = C[1];
-      x.z = C[2];
-      x.l = b->shell_l[s];
-      x.nprim = b->shell_nprim[s];
-      x.pptr = (int32_t)ex.size();
-      x.foff = (int32_t)foff;
-      foff += ncart_h(x.l);
-      double amin = 1e300, cmin = 0.0;
-      for (int k = 0; k < x.nprim; ++k) {
-        const double a = b->exps[b->shell_ptr[s] + k], c = b->coefs[b->shell_ptr[s] + k];
-        ex.push_back(a);
-        cf.push_back(c);
-        // 1s function with the L2 norm of the x^l component of this primitive
-        const double c1 = std::fabs(c) * std::sqrt(dfact_odd(x.l) / std::pow(4.0 * a, x.l));
-        c1s.push_back(c1);
-        if (a < amin) {
-          amin = a;
-          cmin = c1;
-        }
-      }
-      x.a_d = amin;
-      x.c_d = cmin;
-      sh.push_back(x);
-    }
-    return foff;
-  };
-  hp.nao = pack(bs, cell->coords, hp.ao, hp.ao_exp, hp.ao_coef, hp.ao_c1s);
-  hp.naux = pack(ax, cell->coords, hp.ax, hp.ax_exp, hp.ax_coef, hp.ax_c1s);
+  hp.nao = pack_shells(bs, cell->coords, hp.ao, hp.ao_exp, hp.ao_coef, hp.ao_c1s);
+  hp.naux = pack_shells(ax, cell->coords, hp.ax, hp.ax_exp, hp.ax_coef, hp.ax_c1s);
 
   // k-points and pairs
-  hp.kvec.resize(3 * nk);
-  for (int j0 = 0; j0 < L.n[0]; ++j0)
-    for (int j1 = 0; j1 < L.n[1]; ++j1)
-      for (int j2 = 0; j2 < L.n[2]; ++j2) {
-        const int k = (j0 * L.n[1] + j1) * L.n[2] + j2;
-        for (int d = 0; d < 3; ++d)
-          hp.kvec[3 * k + d] = (double)j0 / L.n[0] * L.b[d] + (double)j1 / L.n[1] * L.b[3 + d] +
-                               (double)j2 / L.n[2] * L.b[6 + d];
-      }
+  hp.kvec = mesh_kvec(L);
   for (int k1 = 0; k1 < nk; ++k1)
     for (int k2 = k1; k2 < nk; ++k2) {
       hp.kp1.push_back(k1);
@@ -503,7 +595,7 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
       double nfmax = 0.0;
       for (int w = 0; w < W; ++w) nfmax = std::max(nfmax, S.N(w * S.dR) * f_sr(w * S.dR, eta1, eta2));
       nfmax *= Aamp * 4.0 * kPi / L.vol / (2.0 * p.beta_d);
-      r12t[t] = solve_r12(nfmax, p.beta_d, thresh);
+      r12t[t] = solve_r12_grow(nfmax, p.beta_d, thresh, sA.l + sB.l, pair_growth_c(p.beta_d));
     });
     for (int P = 0; P < nxs; ++P)
       for (int ip = 0; ip < npair; ++ip) r12pair[ip] = std::max(r12pair[ip], r12t[(size_t)P * npair + ip]);
@@ -821,19 +913,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
 
   // phase table kphase[k][c] = e^{+i k.L_c}; the fold's k-pair tiles: up to 16
   // k-pairs (k1, k2) of one k2 each
-  auto cell_ph = [&](int k, int c) {  // 2 pi sum_d j_d i_d / n_d
-    const int j[3] = {k / (L.n[1] * L.n[2]), (k / L.n[2]) % L.n[1], k % L.n[2]};
-    const int i[3] = {c / (L.n[1] * L.n[2]), (c / L.n[2]) % L.n[1], c % L.n[2]};
-    long double s = 0.0L;
-    for (int d = 0; d < 3; ++d) s += (long double)(j[d] * i[d] % L.n[d]) / L.n[d];
-    return (double)(2.0L * 3.14159265358979323846264338327950288L * s);
-  };
-  kph.assign((size_t)2 * nk * nk, 0.0);
-  for (int k = 0; k < nk; ++k)
-    for (int c = 0; c < nk; ++c) {
-      kph[2 * (k * nk + c)] = std::cos(cell_ph(k, c));
-      kph[2 * (k * nk + c) + 1] = std::sin(cell_ph(k, c));
-    }
+  kph = mesh_phases(L);
   {
     std::vector<std::vector<int32_t>> by_k2(nk);
     for (int t = 0; t < nkp; ++t) by_k2[hp.kp2[t]].push_back(t);
@@ -1125,34 +1205,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
 
   // ---------------------------------------------------------- LR plan
   if (do_lr) {
-    // G sets per folded k12 class: q = G + k_c, q != 0, exp(-q^2/4w^2) >= g_thr
-    const double q2max = -4.0 * omega * omega * std::log(g_thr);
-    for (int c = 0; c < nk; ++c) {
-      const double *kc = &hp.kvec[3 * c];
-      const double qm = std::sqrt(std::max(q2max, 0.0)) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
-      int w[3];
-      for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(qm * hp.lt.an[d] / (2.0 * kPi)) + 1;
-      std::vector<std::array<double, 4>> qc;  // (|q|^2, q)
-      for (int i = -w[0]; i <= w[0]; ++i)
-        for (int j = -w[1]; j <= w[1]; ++j)
-          for (int k = -w[2]; k <= w[2]; ++k) {
-            double q[3], q2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-              q[d] = i * L.b[d] + j * L.b[3 + d] + k * L.b[6 + d] + kc[d];
-              q2 += q[d] * q[d];
-            }
-            if (q2 < 1e-20) continue;
-            if (std::exp(-q2 / (4.0 * omega * omega)) < g_thr) continue;
-            qc.push_back({q2, q[0], q[1], q[2]});
-          }
-      // by |q|, so that neighbouring lanes of the pair-transform kernel
-      // drop the same primitive pairs (the e^{-q^2/4p} factor)
-      std::stable_sort(qc.begin(), qc.end(), [](const std::array<double, 4> &x, const std::array<double, 4> &y) {
-        return x[0] < y[0];
-      });
-      for (const auto &e : qc) qv.insert(qv.end(), e.begin() + 1, e.end());
-      qoff.push_back((int64_t)qv.size() / 3);
-    }
+    make_qsets(hp.lt, hp.kvec, omega, g_thr, qv, qoff);
     nq_tot = qoff.back();
     // k-pairs per class
     cls_kp.assign(nk, {});
@@ -2141,6 +2194,281 @@ int rsgdf_mlp_margin(const float *params, const float *X, const float *y, int64_
   std::sort(r.begin(), r.end());
   const int64_t k = std::min<int64_t>(n - 1, (int64_t)std::ceil(quantile * n) - 1);
   *margin = std::max(0.0, r[std::max<int64_t>(k, 0)]);
+  return RSGDF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Two-center metric J^k (Eq. M5) and the density-fitting solve (Eq. M4)
+// ---------------------------------------------------------------------------
+namespace {
+
+int64_t j2c_nbytes_impl(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const int32_t kmesh[3]) {
+  if (!cell || !kmesh) return fail(RSGDF_EINVAL, "null argument");
+  if (cell->natm < 1 || !cell->coords) return fail(RSGDF_EINVAL, "cell needs at least one atom");
+  int rc = validate_basis(auxbasis, cell->natm, RSGDF_MAX_L_AUX, "auxbasis");
+  if (rc) return rc;
+  for (int d = 0; d < 3; ++d)
+    if (kmesh[d] < 1 || kmesh[d] > 64) return fail(RSGDF_EINVAL, "kmesh entries must be in 1..64");
+  const int64_t nk = (int64_t)kmesh[0] * kmesh[1] * kmesh[2];
+  const int64_t n = nfunc(auxbasis);
+  return nk * n * n * 16;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t rsgdf_j2c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const int32_t kmesh[3]) {
+  g_err.clear();
+  return j2c_nbytes_impl(cell, auxbasis, kmesh);
+}
+
+int rsgdf_build_j2c(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const int32_t kmesh[3], double omega,
+                    double thresh, const rsgdf_options *opt, rsgdf_out *out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  g_err.clear();
+  if (!out) return fail(RSGDF_EINVAL, "null output");
+  const int64_t need = j2c_nbytes_impl(cell, auxbasis, kmesh);
+  if (need < 0) return (int)need;
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
+  if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
+  for (int i = 0; i < 3 * cell->natm; ++i)
+    if (!std::isfinite(cell->coords[i])) return fail(RSGDF_EINVAL, "non-finite coordinates");
+  if (!out->data) return fail(RSGDF_EINVAL, "null output buffer");
+  if (out->capacity_bytes < need) return fail(RSGDF_ESIZE, "output capacity too small");
+  int parts = (opt && opt->parts) ? opt->parts : RSGDF_PART_ALL;
+  const double g_thr = (opt && opt->g_thresh > 0.0) ? opt->g_thresh : 1e-2 * thresh;
+  Lat lt;
+  int rc = make_lattice(cell, kmesh, lt);
+  if (rc) return rc;
+  const Lattice &L = lt.L;
+  const int nk = L.nk;
+  std::vector<Shell> ax;
+  std::vector<double> ax_exp, ax_coef, ax_c1s;
+  const int64_t naux = pack_shells(auxbasis, cell->coords, ax, ax_exp, ax_coef, ax_c1s);
+  const int nxs = (int)ax.size();
+  // (P, Q) shell pairs grouped by (l_P, l_Q), each with the radius beyond which
+  // every term (P^0 | erfc | Q^m) of the 1s model (Eqs. S4-S9 with one AO
+  // factor replaced by the aux function), with its angular growth, stays
+  // below 1e-2 thresh (solve_rc, Eq. S14)
+  std::vector<J2Pair> pairs;
+  int cls_off[17] = {0};
+  for (int lp = 0; lp <= 3; ++lp)
+    for (int lq = 0; lq <= 3; ++lq) {
+      for (int P = 0; P < nxs; ++P) {
+        if (ax[P].l != lp) continue;
+        for (int Q = 0; Q < nxs; ++Q) {
+          if (ax[Q].l != lq) continue;
+          double K = 0.0;
+          for (int i = 0; i < ax[P].nprim; ++i)
+            for (int j = 0; j < ax[Q].nprim; ++j) {
+              const double a = ax_exp[ax[P].pptr + i], b = ax_exp[ax[Q].pptr + j];
+              K += kPi * kPi * kPi * ax_c1s[ax[P].pptr + i] * ax_c1s[ax[Q].pptr + j] / std::pow(a * b, 1.5);
+            }
+          const double a = ax[P].a_d, b = ax[Q].a_d;
+          const double e1 = std::sqrt(a * b / (a + b));
+          const double e2 = 1.0 / std::sqrt(1.0 / (e1 * e1) + 1.0 / (omega * omega));
+          J2Pair jp{};
+          jp.P = P;
+          jp.Q = Q;
+          jp.rmax = solve_rc(K, e2, 1e-2 * thresh, lp + lq) + 1e-9;
+          pairs.push_back(jp);
+        }
+      }
+      cls_off[4 * lp + lq + 1] = (int)pairs.size();
+    }
+  // S_P = int chi_P (all space) for the G = 0 term
+  std::vector<double> SP(naux, 0.0);
+  for (int s_ = 0; s_ < nxs; ++s_) {
+    const Shell &x = ax[s_];
+    int ic = 0;
+    for (int lx = x.l; lx >= 0; --lx)
+      for (int ly = x.l - lx; ly >= 0; --ly, ++ic) {
+        const int lz = x.l - lx - ly;
+        if ((lx | ly | lz) & 1) continue;
+        double v = 0.0;
+        for (int k = 0; k < x.nprim; ++k) {
+          const double g = ax_exp[x.pptr + k];
+          double m = ax_coef[x.pptr + k] * std::pow(kPi / g, 1.5);
+          const int pw[3] = {lx, ly, lz};
+          for (int d = 0; d < 3; ++d) {
+            double df = 1.0;
+            for (int q = pw[d] - 1; q > 1; q -= 2) df *= q;
+            m *= df / std::pow(2.0 * g, pw[d] / 2);
+          }
+          v += m;
+        }
+        SP[x.foff + ic] = v;
+      }
+  }
+  const std::vector<double> kvec = mesh_kvec(L);
+  const std::vector<double> kph = mesh_phases(L);
+  std::vector<double> qv;
+  std::vector<int64_t> qoff;
+  if (parts & RSGDF_PART_LR) make_qsets(lt, kvec, omega, g_thr, qv, qoff);
+  const int64_t nq_tot = qoff.empty() ? 0 : qoff.back();
+  const double t_plan = ms_since(t_start);
+
+  hipStream_t st = reinterpret_cast<hipStream_t>(out->stream);
+  DBuf d_ax, d_axe, d_axc, d_pairs, d_boys, d_kph, d_SP, d_X2, d_nterm, d_q, d_A, d_B, d_kidx, d_J;
+  HIPCHK(upload(d_ax, ax, st));
+  HIPCHK(upload(d_axe, ax_exp, st));
+  HIPCHK(upload(d_axc, ax_coef, st));
+  HIPCHK(upload(d_pairs, pairs, st));
+  const std::vector<double> boys = boys_poly_table();
+  HIPCHK(upload(d_boys, boys, st));
+  HIPCHK(upload(d_kph, kph, st));
+  HIPCHK(upload(d_SP, SP, st));
+  std::vector<int32_t> kidx(nk);
+  for (int k = 0; k < nk; ++k) kidx[k] = k;
+  HIPCHK(upload(d_kidx, kidx, st));
+  HIPCHK(d_X2.alloc((size_t)nk * naux * naux * sizeof(double)));
+  HIPCHK(d_nterm.alloc(sizeof(long long)));
+  double *J = nullptr;
+  if (out->on_device) {
+    J = static_cast<double *>(out->data);
+  } else {
+    HIPCHK(d_J.alloc((size_t)need));
+    J = d_J.as<double>();
+  }
+  EventSet ev;
+  if ((rc = ev.make(4, 0))) return rc;
+  HIPCHK(hipEventRecord(ev.e[0], st));
+  HIPCHK(launch_zero(d_nterm.p, sizeof(long long), st));
+  J2Params jp{};
+  jp.ax = d_ax.as<Shell>();
+  jp.ax_exp = d_axe.as<double>();
+  jp.ax_coef = d_axc.as<double>();
+  jp.pairs = d_pairs.as<J2Pair>();
+  jp.lat = L;
+  jp.omega = omega;
+  jp.boys = d_boys.as<double>();
+  jp.X2 = d_X2.as<double>();
+  jp.nterm = d_nterm.as<long long>();
+  jp.naux = (int32_t)naux;
+  if (parts & RSGDF_PART_SR) {
+    for (int g = 0; g < 16; ++g)
+      HIPCHK(launch_j2c_sr(g / 4, g % 4, jp, cls_off[g], cls_off[g + 1] - cls_off[g], st));
+  } else {
+    HIPCHK(launch_zero(d_X2.p, (size_t)nk * naux * naux * sizeof(double), st));
+  }
+  const double g0fac = (parts & RSGDF_PART_G0) ? kPi / (L.vol * omega * omega) : 0.0;
+  HIPCHK(launch_j2c_fold(d_X2.as<double>(), d_kph.as<double>(), d_SP.as<double>(), g0fac, nk, (int)naux, J, st));
+  HIPCHK(hipEventRecord(ev.e[1], st));
+  double lr_flops = 0.0;
+  if ((parts & RSGDF_PART_LR) && nq_tot > 0) {
+    HIPCHK(upload(d_q, qv, st));
+    HIPCHK(d_A.alloc((size_t)naux * nq_tot * 2 * sizeof(double)));
+    int64_t max_nq = 0;
+    for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, qoff[c + 1] - qoff[c]);
+    HIPCHK(d_B.alloc((size_t)naux * std::max<int64_t>(max_nq, 1) * 2 * sizeof(double)));
+    AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
+                   (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
+    HIPCHK(launch_auxft(ap, st));
+    for (int c = 0; c < nk; ++c) {
+      const int64_t nqc = qoff[c + 1] - qoff[c];
+      if (nqc == 0) continue;
+      HIPCHK(launch_j2c_lr_operand(d_A.as<double>() + 2 * qoff[c], nq_tot, d_q.as<double>() + 3 * qoff[c], (int)nqc,
+                                   (int)naux, 4.0 * kPi / L.vol, omega, d_B.as<double>(), st));
+      LRGemmParams gp{};
+      gp.A = d_A.as<double>() + 2 * qoff[c];
+      gp.lda = nq_tot;
+      gp.B = d_B.as<double>();
+      gp.out = J;
+      gp.kp_of = d_kidx.as<int32_t>() + c;
+      gp.plane = naux * naux;
+      gp.naux = (int32_t)naux;
+      gp.nq = (int32_t)nqc;
+      gp.nmn = (int32_t)naux;
+      gp.nq_hi = 0;
+      HIPCHK(launch_lr_gemm_tiled(RSGDF_FP64, gp, 0, 1, st));
+      lr_flops += 8.0 * (double)naux * naux * nqc;
+    }
+  }
+  HIPCHK(hipEventRecord(ev.e[2], st));
+  long long nterm = 0;
+  HIPCHK(hipMemcpyAsync(&nterm, d_nterm.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+  if (!out->on_device) HIPCHK(hipMemcpyAsync(out->data, J, (size_t)need, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out->nkpair = nk;
+  out->naux = naux;
+  out->nao = naux;
+  if (out->stats) {
+    rsgdf_stats &s_ = *out->stats;
+    std::memset(&s_, 0, sizeof(s_));
+    float ms = 0.f;
+    s_.t_plan_ms = t_plan;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    s_.t_sr_ms = ms;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[1], ev.e[2]));
+    s_.t_lr_ms = ms;
+    s_.n_sr_terms = nterm;
+    s_.n_g_total = nq_tot;
+    s_.n_triplets = (int64_t)pairs.size();
+    s_.bytes_out = need;
+    s_.lr_gemm_flops = lr_flops;
+    s_.t_total_ms = ms_since(t_start);
+  }
+  return RSGDF_OK;
+}
+
+int rsgdf_df_solve(const int32_t kmesh[3], int64_t naux, int64_t ncol, const void *j2c, const void *j3c, void *d,
+                   void *stream) {
+  g_err.clear();
+  if (!kmesh || !j2c || !j3c || !d) return fail(RSGDF_EINVAL, "null argument");
+  for (int k = 0; k < 3; ++k)
+    if (kmesh[k] < 1 || kmesh[k] > 64) return fail(RSGDF_EINVAL, "kmesh entries must be in 1..64");
+  if (naux < 1 || naux > 65535 || ncol < 1) return fail(RSGDF_EINVAL, "naux must be in 1..65535 and ncol >= 1");
+  const int n[3] = {kmesh[0], kmesh[1], kmesh[2]};
+  const int nk = n[0] * n[1] * n[2];
+  const int nkp = nk * (nk + 1) / 2;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // class of each k-pair: the mesh index of k2 - k1
+  std::vector<int32_t> cls;
+  for (int k1 = 0; k1 < nk; ++k1)
+    for (int k2 = k1; k2 < nk; ++k2) {
+      const int j1[3] = {k1 / (n[1] * n[2]), (k1 / n[2]) % n[1], k1 % n[2]};
+      const int j2[3] = {k2 / (n[1] * n[2]), (k2 / n[2]) % n[1], k2 % n[2]};
+      int c = 0;
+      for (int q = 0; q < 3; ++q) c = c * n[q] + ((j2[q] - j1[q]) % n[q] + n[q]) % n[q];
+      cls.push_back(c);
+    }
+  DBuf d_L, d_W, d_bad, d_cls, d_tmp;
+  const size_t mat = (size_t)naux * naux * 16;
+  HIPCHK(d_L.alloc(mat * nk));
+  HIPCHK(d_W.alloc(mat * nk));
+  HIPCHK(d_bad.alloc((size_t)nk * sizeof(int)));
+  HIPCHK(upload(d_cls, cls, st));
+  HIPCHK(launch_df_factor(static_cast<const double *>(j2c), d_L.as<double>(), d_W.as<double>(), d_bad.as<int>(), nk,
+                          (int)naux, st));
+  std::vector<int> bad(nk, 0);
+  HIPCHK(hipMemcpyAsync(bad.data(), d_bad.p, (size_t)nk * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < nk; ++k)
+    if (bad[k])
+      return fail(RSGDF_EINVAL, "J^k is numerically singular at k index " + std::to_string(k) +
+                                    " (a Cholesky pivot below 1e-12 of its diagonal entry: linearly dependent aux functions)");
+  // per chunk of k-pairs: Y = W V into the temporary, then d = W^H Y (in place
+  // allowed: V of the chunk is consumed by the first product before the second
+  // writes it)
+  const size_t per = (size_t)naux * ncol * 16;  // bytes of one k-pair's block
+  size_t free_b = 0;
+  HIPCHK(mem_avail(&free_b));
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nkp, (size_t)(0.25 * free_b) / per));
+  HIPCHK(d_tmp.alloc(per * chunk));
+  const double *V = static_cast<const double *>(j3c);
+  double *D = static_cast<double *>(d);
+  for (int t0 = 0; t0 < nkp; t0 += chunk) {
+    const int nt = std::min(chunk, nkp - t0);
+    const size_t off = 2 * (size_t)t0 * naux * ncol;
+    HIPCHK(launch_df_gemm(false, d_W.as<double>(), d_cls.as<int32_t>() + t0, V + off, d_tmp.as<double>(), (int)naux,
+                          ncol, nt, st));
+    HIPCHK(launch_df_gemm(true, d_W.as<double>(), d_cls.as<int32_t>() + t0, d_tmp.as<double>(), D + off, (int)naux,
+                          ncol, nt, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
   return RSGDF_OK;
 }
 

@@ -92,6 +92,24 @@ struct LRGemmParams {
   int32_t nq_hi;          // leading q columns taken in FP64 by the reduced-precision forms
 };
 
+// two-center metric (j2c.hip): one (P shell, Q shell) pair of an angular class
+struct J2Pair {
+  int32_t P, Q;
+  double rmax;            // short-range screening radius on |C_P - B_Q - m|
+};
+
+struct J2Params {
+  const Shell *ax;
+  const double *ax_exp, *ax_coef;
+  const J2Pair *pairs;
+  Lattice lat;
+  double omega;
+  const double *boys;     // Boys polynomial table [L][interval][degree + 1] (global memory)
+  double *X2;             // real [nk][naux][naux] per BvK cell of m
+  long long *nterm;       // evaluated (P prim, Q prim, m) terms
+  int32_t naux, pad;
+};
+
 int pair_class(int la, int lb);
 int sr_term_flops(int L);
 int sr_cells_per_wave(int nblk);
@@ -109,6 +127,16 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
                          int nkpi, int nq, int64_t nmn, hipStream_t stream);
 hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t stream);
+
+// two-center metric (j2c.hip) and the density-fitting solve (df.hip)
+hipError_t launch_j2c_sr(int lP, int lQ, const J2Params &jp, int p0, int npair, hipStream_t stream);
+hipError_t launch_j2c_fold(const double *X2, const double *kph, const double *SP, double g0fac, int nk, int naux,
+                           double *J, hipStream_t stream);
+hipError_t launch_j2c_lr_operand(const double *A, int64_t lda, const double *q, int nq, int naux, double wfac,
+                                 double omega, double *B, hipStream_t stream);
+hipError_t launch_df_factor(const double *J, double *L, double *W, int *bad, int nk, int n, hipStream_t stream);
+hipError_t launch_df_gemm(bool conjt, const double *W, const int32_t *cls, const double *V, double *D, int naux,
+                          int64_t ncol, int nkp, hipStream_t stream);
 
 // learned screening (learned.hip)
 hipError_t launch_features(const SRParams &prm, int ntrip, const int64_t *idx, int64_t n, float *feat,

@@ -20,6 +20,15 @@ constexpr int kBoysIntervals = 36;             // unit intervals of T in [0, 36)
 constexpr int kBoysPolyDeg = 12;               // Taylor degree about each interval centre
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Angular growth of an AO pair factor in the screening windows (Eqs.
+// S23-S25): the 1s model e^{-beta R12^2} of a pair with l_a + l_b > 0 is
+// multiplied by (1 + c R12)^{l_a + l_b} with c = sqrt(2 beta).  The pair
+// density's polynomial prefactor (x-A)^{i}(x-B)^{j} about the product centre
+// grows like (|PA| / w)^i (|PB| / w)^j in units of the primitive width w
+// that the 1s-equivalent amplitude carries, and for equal exponents
+// |PA| / w = |PB| / w = sqrt(2 beta) R12; the s-type model leaves it out.
+__host__ __device__ inline double pair_growth_c(double beta) { return sqrt(2.0 * beta); }
 __host__ __device__ constexpr int nherm(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
 
 // Packed shell (AO or aux).  a_d, c_d: exponent and 1s-equivalent amplitude

@@ -96,6 +96,13 @@ def library():
         L.rsgdf_build_j3c_ex.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                          ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options),
                                          ctypes.POINTER(Out)]
+        L.rsgdf_j2c_nbytes.restype = ctypes.c_int64
+        L.rsgdf_j2c_nbytes.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), P]
+        L.rsgdf_build_j2c.restype = ctypes.c_int
+        L.rsgdf_build_j2c.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), P, ctypes.c_double,
+                                      ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(Out)]
+        L.rsgdf_df_solve.restype = ctypes.c_int
+        L.rsgdf_df_solve.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
         L.rsgdf_build_j3c_noalloc.restype = ctypes.c_int
         L.rsgdf_build_j3c_noalloc.argtypes = L.rsgdf_build_j3c_ex.argtypes
         F = ctypes.c_float
@@ -234,6 +241,62 @@ def build_j3c_noalloc(cell, basis, aux, kmesh, omega, thresh, out, *, stream=Non
     device scratch buffer taken from the library's static per-GPU array (no
     device allocation in the call).  ``out`` must be a device tensor."""
     return build_j3c(cell, basis, aux, kmesh, omega, thresh, out, stream=stream, _noalloc=True, **options)
+
+
+# ---- density fitting: two-center metric and the fitting solve ---------------
+
+def j2c_nbytes(cell, aux, kmesh) -> int:
+    m = _Marshal(cell, aux, aux, kmesh)
+    n = library().rsgdf_j2c_nbytes(ctypes.byref(m.cell), ctypes.byref(m.aux), m.kmesh.ctypes.data)
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def build_j2c(cell, aux, kmesh, omega, thresh, out=None, *, g_thresh=None, parts=PART_ALL, stream=None):
+    """Run rsgdf_build_j2c: J^k [nk, naux, naux] complex128 (device tensor
+    allocated here if ``out`` is None).  Returns (out, stats dict)."""
+    import torch
+    m = _Marshal(cell, aux, aux, kmesh)
+    nk = int(np.prod(kmesh))
+    if out is None:
+        out = torch.empty((nk, aux.nfunc, aux.nfunc), dtype=torch.complex128, device="cuda")
+    if out.dtype != torch.complex128 or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("output must be a contiguous complex128 CUDA tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    stats = Stats()
+    o = Out(out.data_ptr(), out.numel() * 16, 1, stream.cuda_stream, 0, 0, 0, ctypes.pointer(stats))
+    keep = []
+    opts = _options(g_thresh, FP64, SCREEN_RIGOROUS, parts, 0, None, 0.0, None, keep)
+    _check(library().rsgdf_build_j2c(ctypes.byref(m.cell), ctypes.byref(m.aux), m.kmesh.ctypes.data, float(omega),
+                                     float(thresh), ctypes.byref(opts), ctypes.byref(o)))
+    return out, stats.as_dict()
+
+
+def df_solve(kmesh, j2c, j3c, out=None, *, stream=None):
+    """Run rsgdf_df_solve: d with J^{k12} d = V per k-pair (Eq. M4).  ``j2c``
+    [nk, naux, naux] and ``j3c`` [nkpair, naux, nao, nao] are complex128
+    device tensors; ``out`` (default: a new tensor) may be ``j3c`` itself."""
+    import torch
+    for t in (j2c, j3c):
+        if t.dtype != torch.complex128 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("inputs must be contiguous complex128 CUDA tensors")
+    nk = int(np.prod(kmesh))
+    naux = int(j2c.shape[-1])
+    if j2c.shape != (nk, naux, naux) or j3c.shape[0] != nk * (nk + 1) // 2 or j3c.shape[1] != naux:
+        raise ValueError("shape mismatch between kmesh, j2c and j3c")
+    ncol = int(j3c[0, 0].numel())
+    if out is None:
+        out = torch.empty_like(j3c)
+    if out.shape != j3c.shape or out.dtype != torch.complex128 or not out.is_contiguous():
+        raise ValueError("out must match j3c")
+    if stream is None:
+        stream = torch.cuda.current_stream(j3c.device)
+    km = np.ascontiguousarray(kmesh, np.int32)
+    _check(library().rsgdf_df_solve(km.ctypes.data, naux, ncol, j2c.data_ptr(), j3c.data_ptr(), out.data_ptr(),
+                                    stream.cuda_stream))
+    return out
 
 
 # ---- learned screening -------------------------------------------------------
