@@ -1,8 +1,9 @@
 """The 8-atom cell on the 3x3x3 mesh at omega = 1.5 (about 2e4 q per k12
 class, the workload of the reduced-precision contraction) at full size, in
-every contraction form, against oracle blocks stored by
-tests/golden/make_c3_golden.py (30 of the 378 k-pairs; s, p, d, f aux
-shells; three AO shell pairs).  Bars: 1e-8 au (FP64), 1e-6 au (FP32, BF16x3).
+every contraction form and in the chosen form as benchmarked, against oracle
+blocks stored by tests/golden/make_c3_golden.py (s-s and s-p AO shell pairs on
+30 of the 378 k-pairs; d-d and p-s pairs on 5 k-pairs; s, p, d, f aux shells).
+Bars: 1e-8 au (FP64), 1e-6 au (FP32, BF16x3, chosen).
 The second test compares the whole long-range tensor of the reduced-precision
 forms with the FP64 form: FP32 must stay within 1e-6 au; BF16x3 (hi + lo
 operands keep 16 of FP32's 24 mantissa bits) measures 1.7e-6 au there, above
@@ -17,37 +18,51 @@ import synth
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_blocks.npz")
+GOLDEN_DD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_blocks_dd.npz")
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden blocks not generated")
-def test_c3_forms_vs_oracle_blocks():
+def _golden_err(out, p, path):
+    """Max |GPU - oracle| over the stored blocks of one golden file."""
     import torch
-
-    import paper_2102_02989_amd as P
-    g = np.load(GOLDEN)
-    p = synth.config3()
+    g = np.load(path)
     assert float(g["omega"]) == p.omega and float(g["thresh"]) == p.thresh
     kp = torch.as_tensor(g["kpairs"], device="cuda")
     rows = torch.as_tensor(g["rows"], device="cuda")
     bo = p.basis.offsets()
+    sub = out.index_select(0, kp).index_select(1, rows)
+    err = 0.0
+    for mu, nu in g["pairs"]:
+        blk = sub[:, :, bo[mu]:bo[mu + 1], bo[nu]:bo[nu + 1]].cpu().numpy()
+        err = max(err, float(np.abs(blk - g[f"pair_{mu}_{nu}"]).max()))
+    return err
+
+
+@pytest.mark.skipif(not (os.path.exists(GOLDEN) and os.path.exists(GOLDEN_DD)), reason="golden blocks not generated")
+def test_c3_forms_vs_oracle_blocks():
+    """Every contraction form, and the chosen form exactly as the benchmark
+    times it (FP32 contraction, learned screening with the committed network
+    at its calibrated margin, the single-cell entry point), against both
+    stored oracle sets: s-s/s-p pairs on 30 k-pairs, d-d and p-s pairs against
+    s, p, d, f aux shells on 5 k-pairs."""
+    import torch
+
+    import paper_2102_02989_amd as P
+    from paper_2102_02989_amd.chosen import chosen_options
+    p = synth.config3()
     out = torch.empty((P.nkpairs(p.kmesh), p.aux.nfunc, p.basis.nfunc, p.basis.nfunc), dtype=torch.complex128,
                       device="cuda")
-    errs = {}
-    for name, prec, tol in (("fp64", P.FP64, 1e-8), ("fp32", P.FP32, 1e-6), ("bf16x3", P.BF16X3, 1e-6)):
+    cases = (("fp64", dict(lr_precision=P.FP64), 1e-8), ("fp32", dict(lr_precision=P.FP32), 1e-6),
+             ("bf16x3", dict(lr_precision=P.BF16X3), 1e-6), ("chosen (as benchmarked)", chosen_options(), 1e-6))
+    for name, kw, tol in cases:
         print("case C3 form", name, flush=True)
-        _, st = P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, p.omega, p.thresh, out, g_thresh=p.g_thr,
-                            lr_precision=prec)
+        _, st = P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, p.omega, p.thresh, out, g_thresh=p.g_thr, **kw)
         torch.cuda.synchronize()
-        sub = out.index_select(0, kp).index_select(1, rows)
-        err = 0.0
-        for mu, nu in g["pairs"]:
-            blk = sub[:, :, bo[mu]:bo[mu + 1], bo[nu]:bo[nu + 1]].cpu().numpy()
-            err = max(err, float(np.abs(blk - g[f"pair_{mu}_{nu}"]).max()))
-        errs[name] = err
-        print(f"  max err {err:.3e}  t_total {st['t_total_ms']:.0f} ms  t_lr {st['t_lr_ms']:.0f} ms  "
-              f"gemm {st['t_lr_gemm_ms']:.0f} ms", flush=True)
+        e_sp, e_dd = _golden_err(out, p, GOLDEN), _golden_err(out, p, GOLDEN_DD)
+        print(f"  max err s/p blocks {e_sp:.3e}, d-d/p-s blocks {e_dd:.3e}  t_total {st['t_total_ms']:.0f} ms  "
+              f"t_lr {st['t_lr_ms']:.0f} ms  gemm {st['t_lr_gemm_ms']:.0f} ms  skipped {st['n_screen_skipped']}",
+              flush=True)
         sys.stdout.flush()
-        assert err <= tol, (name, err)
+        assert max(e_sp, e_dd) <= tol, (name, e_sp, e_dd)
 
 
 def _count_q(problem):

@@ -79,6 +79,7 @@ def test_config2_sampled_blocks():
     the benchmark workload at full size in the benchmark's launch
     configuration; the oracle checks sampled (aux shell, AO shell pair) blocks
     for all 36 k-pairs: every aux l, same-atom and cross-atom pairs, s/p/d."""
+    from paper_2102_02989_amd.chosen import chosen_options
     p = synth.config2()
     _say("case C2 sampled blocks")
     got, st = run_gpu(p)
@@ -89,6 +90,37 @@ def test_config2_sampled_blocks():
     err = _block_err(p, got, ref, aux, pairs)
     _say("  max err", err, "max |ref|", np.abs(ref).max())
     assert err <= TOL
+    # the chosen form (reduced-precision contraction, learned screening at the
+    # calibrated margin) on the same blocks, bar 1e-6
+    got_c, st_c = run_gpu(p, **chosen_options())
+    err_c = _block_err(p, got_c, ref, aux, pairs)
+    _say("  chosen form: max err", err_c, "candidates dropped", st_c["n_screen_skipped"])
+    assert err_c <= 1e-6
+
+
+def test_config2_dd_golden_blocks():
+    """C2 at full size, plain and chosen forms, against stored oracle blocks
+    (tests/golden/make_c2_golden.py): d-d AO pairs on one atom and across
+    atoms and a p-s pair against a d and both f aux shells, all 36 k-pairs --
+    the short-range classes up to (f|dd), L = 7, on their full-size work split."""
+    import os
+
+    from paper_2102_02989_amd.chosen import chosen_options
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_blocks_dd.npz")
+    g = np.load(path)
+    p = synth.config2()
+    assert float(g["omega"]) == p.omega and float(g["thresh"]) == p.thresh
+    rows = g["rows"]
+    bo = p.basis.offsets()
+    for name, kw, tol in (("plain", {}, TOL), ("chosen", chosen_options(), 1e-6)):
+        _say("case C2 d-d golden blocks,", name)
+        got, st = run_gpu(p, **kw)
+        err = 0.0
+        for mu, nu in g["pairs"]:
+            blk = got[:, rows][:, :, bo[mu]:bo[mu + 1], bo[nu]:bo[nu + 1]]
+            err = max(err, float(np.abs(blk - g[f"pair_{mu}_{nu}"]).max()))
+        _say(f"  max err {err:.3e}  t_sr {st['t_sr_ms']:.0f} ms")
+        assert err <= tol, (name, err)
 
 
 def test_config5_sampled_blocks():
