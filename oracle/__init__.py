@@ -203,6 +203,28 @@ def df_coefficients(J, V, kmesh, all_pairs=False):
     return d
 
 
+def coulomb_df(problem, dm, cut=1e-15):
+    """Density-fitted Coulomb matrix (Eq. M7 with k1 = k2, k3 = k4, and the
+    fit of Eq. M4 at k12 = 0), written out from its definition:
+        rho_Q = sum_k sum_{l s} V^{kk}_{Q l s} D^k_{s l},   J^0 c = rho,
+        J_{m n}(k) = (1/Nk) sum_Q V^{kk}_{Q m n} c_Q,
+    V from j3c (the k-pairs (k, k)), J^0 from j2c at Gamma, the solve by
+    scipy's Cholesky factorisation.  dm: complex [nk][nao][nao]."""
+    import copy
+
+    import scipy.linalg as sla
+    nk = int(np.prod(problem.kmesh))
+    pairs = kpair_list(problem.kmesh)
+    diag = [t for t, (k1, k2) in enumerate(pairs) if k1 == k2]
+    V = j3c(problem, kpairs=diag, cut=cut)[diag]  # [nk][naux][nao][nao], k order
+    g = copy.copy(problem)
+    g.kmesh = (1, 1, 1)
+    J0 = j2c(g, cut=cut)[0]
+    rho = np.einsum("kqls,ksl->q", V, dm)
+    c = sla.cho_solve(sla.cho_factor(J0, lower=True), rho)
+    return np.einsum("kqmn,q->kmn", V, c) / nk
+
+
 def num_threads() -> int:
     return lib().orc_num_threads()
 

@@ -535,3 +535,21 @@ def test_df_exact_fit():
             e = np.zeros(8)
             e[j] = 1.0
             assert np.abs(d[t, :, j, j] - e).max() <= 1e-10
+
+
+def test_coulomb_df_madelung():
+    """Integral-direct consumer oracle: with D^k = diag(q_j) in the rock-salt
+    cell the electron density is sum_j q_j sum_m phi_j(r - m)^2 exactly (the
+    k sum keeps m = n only), the fit is exact, and the Coulomb energy per
+    cell (1/2Nk) sum_k Tr(D^k J(k)) is the Madelung energy plus the ions'
+    self-interactions, on a 2x1x1 mesh."""
+    p = synth.nacl_problem(a=8.0, alpha_aux=6.0, alpha_ao=3.0, omega=0.5)
+    p.kmesh = (2, 1, 1)
+    q = synth.NACL_CHARGES
+    dm = np.array([np.diag(q).astype(complex)] * 2)
+    J = oracle.coulomb_df(p, dm, cut=1e-17)
+    E = 0.5 * np.einsum("knm,kmn->", dm, J).real / 2
+    self_energy = 0.5 * float(np.sum(q ** 2)) * 2.0 / math.sqrt(math.pi) * math.sqrt(6.0 * 6.0 / 12.0)
+    assert abs((E - self_energy) - (-4 * MADELUNG_NACL / 4.0)) <= 1e-9, E - self_energy
+    for k in range(2):
+        assert np.abs(J[k] - J[k].conj().T).max() <= 1e-12
