@@ -193,6 +193,49 @@ int rsgdf_build_j2c(const rsgdf_cell *cell, const rsgdf_basis *auxbasis, const i
 int rsgdf_df_solve(const int32_t kmesh[3], int64_t naux, int64_t ncol, const void *j2c, const void *j3c, void *d,
                    void *stream);
 
+/* Integral-direct density-fitted Coulomb matrix: a consumer of the
+ * three-center integrals that never stores them (the paper's outlook of
+ * integral-direct algorithms).  For densities D^k (device complex128
+ * [nk][nao][nao], Hermitian per k):
+ *   J_{mu nu}(k) = (1/Nk) sum_{k', lambda sigma} (rho^{kk}_{mu nu} | rho^{k'k'}_{lambda sigma})
+ *                  D^{k'}_{sigma lambda}
+ * with the ERIs of Eq. M7 (d = (J^0)^{-1} V, Eq. M4 at k12 = 0):
+ *   rho_Q = sum_k sum_{lambda sigma} V^{kk}_{Q lambda sigma} D^k_{sigma lambda};  J^0 c = rho;
+ *   J_{mu nu}(k) = (1/Nk) sum_Q V^{kk}_{Q mu nu} c_Q.
+ * The k1 = k2 blocks of V are built per group of aux shells (aux_group
+ * shells per group, 0: groups sized to 10% of free device memory, at most
+ * 8 GB), contracted and dropped; the second pass rebuilds them.  vj: device
+ * complex128 [nk][nao][nao] (overwritten).  opt as for rsgdf_build_j3c_ex
+ * (parts must be all).  RSGDF_EINVAL if J^0 is numerically singular.
+ * stats (optional): phase times and counts summed over both passes,
+ * n_aux_batches = tiles built. */
+int rsgdf_coulomb_direct(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                         const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                         int32_t aux_group, const void *dm, void *vj, void *stream, rsgdf_stats *stats);
+
+/* ---- automatic choice of the range-separation parameter.  The paper picks
+ * omega (and with it the number of plane waves of the long-range part) by
+ * hand; here every omega screened at the same thresh and g_thresh meets the
+ * same precision, so the choice is the fastest one, predicted by a cost model
+ * linear in work features that the host planner computes without device work:
+ *   feat[0] short-range operations (the planner's per-item cost estimate),
+ *   feat[1] pair-transform candidates (q x primitive pairs x images x
+ *           Cartesian components), feat[2] contraction flops, feat[3] k2-phase
+ *           elements, feat[4] output elements, feat[5] short-range
+ *           intermediate elements, feat[6] q vectors, feat[7] short-range
+ *           primitive terms (estimate), feat[8] = 1 (fixed cost per build).
+ * rsgdf_plan_features fills feat for one omega; rsgdf_choose_omega returns
+ * the candidate with the smallest sum_i coef[i] feat[i] (ms), and the
+ * predictions if predicted_ms (nomega doubles) is not NULL.  The coefficients
+ * are fitted to measured MI355X builds (the package's cost-model file). */
+#define RSGDF_NFEATURES 9
+int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                        const int32_t kmesh[3], double omega, double thresh, double g_thresh,
+                        double feat[RSGDF_NFEATURES]);
+int rsgdf_choose_omega(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                       const int32_t kmesh[3], double thresh, double g_thresh, const double *omegas, int32_t nomega,
+                       const double coef[RSGDF_NFEATURES], double *best_omega, double *predicted_ms);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * build as rsgdf_build_j3c_ex with every device scratch buffer (tables, the

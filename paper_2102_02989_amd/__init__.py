@@ -23,6 +23,9 @@ from .rsgdf import (  # noqa: F401
     build_j2c,
     j2c_nbytes,
     df_solve,
+    coulomb_direct,
+    plan_features,
+    choose_omega,
     build_j3c_noalloc,
     NOALLOC_SCRATCH_MB,
     j3c_nbytes,

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsgdf.so")
-SOURCES = ["sr3c.hip", "fold.hip", "lr.hip", "learned.hip", "j2c.hip", "df.hip", "capi.cpp"]
+SOURCES = ["sr3c.hip", "fold.hip", "lr.hip", "learned.hip", "j2c.hip", "df.hip", "coulomb.hip", "capi.cpp"]
 ARCH = os.environ.get("RSGDF_ARCH", "gfx950")
 
 

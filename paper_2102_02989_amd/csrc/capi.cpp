@@ -327,6 +327,7 @@ struct HostPlan {
   std::vector<double> rc_t;  // [naux_shell][npair] Eq. S14 bound
   std::vector<double> amp_t; // [naux_shell][npair] 1s-model amplitude
   int64_t nao = 0, naux = 0;
+  bool diag_only = false;  // k-pairs (k, k) only (the Coulomb consumer needs k12 = 0)
   Screen scr;
   // k-points
   std::vector<double> kvec;     // [nk][3]
@@ -451,6 +452,7 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
   hp.kvec = mesh_kvec(L);
   for (int k1 = 0; k1 < nk; ++k1)
     for (int k2 = k1; k2 < nk; ++k2) {
+      if (hp.diag_only && k2 != k1) continue;
       hp.kp1.push_back(k1);
       hp.kp2.push_back(k2);
     }
@@ -827,6 +829,10 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   if (!out) return fail(RSGDF_EINVAL, "null output");
   need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
   if (need < 0) return (int)need;
+  if (hp.diag_only) {  // Nk k-pairs (k, k) instead of Nk (Nk + 1) / 2
+    const int64_t nk_ = (int64_t)kmesh[0] * kmesh[1] * kmesh[2];
+    need = need / (nk_ * (nk_ + 1) / 2) * nk_;
+  }
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
   if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
   for (int i = 0; i < 3 * cell->natm; ++i)
@@ -1576,10 +1582,11 @@ struct EventSet {
 // one build on one stream, timed per phase with events
 int build_impl(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt, rsgdf_out *out,
-               LearnCtl *ctl) {
+               LearnCtl *ctl, bool diag_only = false) {
   const auto t_start = std::chrono::steady_clock::now();
   g_err.clear();
   Job j;
+  j.hp.diag_only = diag_only;
   j.cell = cell;
   j.basis = basis;
   j.auxbasis = auxbasis;
@@ -2469,6 +2476,249 @@ int rsgdf_df_solve(const int32_t kmesh[3], int64_t naux, int64_t ncol, const voi
                           ncol, nt, st));
   }
   HIPCHK(hipStreamSynchronize(st));
+  return RSGDF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Integral-direct density-fitted Coulomb matrix (a consumer of the
+// three-center integrals that never stores them)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int rsgdf_coulomb_direct(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                         const int32_t kmesh[3], double omega, double thresh, const rsgdf_options *opt,
+                         int32_t aux_group, const void *dm, void *vj, void *stream, rsgdf_stats *stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  g_err.clear();
+  if (!dm || !vj) return fail(RSGDF_EINVAL, "null density or output");
+  if (aux_group < 0) return fail(RSGDF_EINVAL, "aux_group must be >= 0");
+  const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
+  if (need < 0) return (int)need;
+  if (opt && opt->parts && opt->parts != RSGDF_PART_ALL) return fail(RSGDF_EINVAL, "the Coulomb build needs all parts");
+  const int nk = kmesh[0] * kmesh[1] * kmesh[2];
+  const int64_t nao = nfunc(basis), naux = nfunc(auxbasis), ne = nao * nao;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  rsgdf_stats acc{};
+  // J^{k12 = 0} and its factor
+  DBuf d_J0, d_L, d_W, d_bad, d_cls, d_rho, d_y, d_c, d_V;
+  HIPCHK(d_J0.alloc((size_t)naux * naux * 16));
+  {
+    rsgdf_out o{};
+    o.data = d_J0.p;
+    o.capacity_bytes = (int64_t)naux * naux * 16;
+    o.on_device = 1;
+    o.stream = stream;
+    rsgdf_stats s2{};
+    o.stats = &s2;
+    const int32_t gam[3] = {1, 1, 1};
+    int rc = rsgdf_build_j2c(cell, auxbasis, gam, omega, thresh, opt, &o);
+    if (rc) return rc;
+  }
+  HIPCHK(d_L.alloc((size_t)naux * naux * 16));
+  HIPCHK(d_W.alloc((size_t)naux * naux * 16));
+  HIPCHK(d_bad.alloc(sizeof(int)));
+  HIPCHK(launch_df_factor(d_J0.as<double>(), d_L.as<double>(), d_W.as<double>(), d_bad.as<int>(), 1, (int)naux, st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(RSGDF_EINVAL, "J^0 is numerically singular (linearly dependent aux functions)");
+  const std::vector<int32_t> zero1(1, 0);
+  HIPCHK(upload(d_cls, zero1, st));
+  HIPCHK(d_rho.alloc((size_t)naux * 16));
+  HIPCHK(d_y.alloc((size_t)naux * 16));
+  HIPCHK(d_c.alloc((size_t)naux * 16));
+  // aux shell groups: the V tile of a group [nk][naux_g][nao^2] within a budget
+  std::vector<int> gstart(1, 0);
+  {
+    size_t free_b = 0;
+    HIPCHK(mem_avail(&free_b));
+    const double budget = std::min(0.1 * (double)free_b, 8e9);
+    int64_t nf = 0;
+    int ns = 0;
+    for (int s_ = 0; s_ < auxbasis->nshell; ++s_) {
+      const int64_t add = ncart_h(auxbasis->shell_l[s_]);
+      const bool full = aux_group > 0 ? ns >= aux_group : (nf > 0 && (double)(nf + add) * nk * ne * 16 > budget);
+      if (full) {
+        gstart.push_back(s_);
+        nf = 0;
+        ns = 0;
+      }
+      nf += add;
+      ++ns;
+    }
+    gstart.push_back(auxbasis->nshell);
+  }
+  int64_t max_nf = 0;
+  for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+    int64_t nf = 0;
+    for (int s_ = gstart[g]; s_ < gstart[g + 1]; ++s_) nf += ncart_h(auxbasis->shell_l[s_]);
+    max_nf = std::max(max_nf, nf);
+  }
+  HIPCHK(d_V.alloc((size_t)nk * max_nf * ne * 16));
+  HIPCHK(launch_zero(vj, (size_t)nk * ne * 16, st));
+  // one pass: rebuild the diagonal-k-pair tiles of every group; pass 0 forms
+  // rho, pass 1 accumulates J
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t f0 = 0;
+    for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+      const int s0 = gstart[g], s1 = gstart[g + 1];
+      rsgdf_basis sub = *auxbasis;
+      sub.nshell = s1 - s0;
+      sub.shell_atom = auxbasis->shell_atom + s0;
+      sub.shell_l = auxbasis->shell_l + s0;
+      sub.shell_nprim = auxbasis->shell_nprim + s0;
+      sub.shell_ptr = auxbasis->shell_ptr + s0;
+      int64_t nf = 0;
+      for (int s_ = s0; s_ < s1; ++s_) nf += ncart_h(auxbasis->shell_l[s_]);
+      rsgdf_out o{};
+      o.data = d_V.p;
+      o.capacity_bytes = (int64_t)nk * nf * ne * 16;
+      o.on_device = 1;
+      o.stream = stream;
+      rsgdf_stats s2{};
+      o.stats = &s2;
+      int rc = build_impl(cell, basis, &sub, kmesh, omega, thresh, opt, &o, nullptr, true);
+      if (rc) return rc;
+      acc.t_plan_ms += s2.t_plan_ms;
+      acc.t_sr_ms += s2.t_sr_ms;
+      acc.t_fold_ms += s2.t_fold_ms;
+      acc.t_lr_ms += s2.t_lr_ms;
+      acc.t_lr_gemm_ms += s2.t_lr_gemm_ms;
+      acc.n_sr_terms += s2.n_sr_terms;
+      acc.n_lr_terms += s2.n_lr_terms;
+      acc.n_aux_batches += 1;
+      if (pass == 0) {
+        HIPCHK(launch_dm_contract(d_V.as<double>(), static_cast<const double *>(dm), nk, (int)nf, (int)nao,
+                                  d_rho.as<double>() + 2 * f0, st));
+      } else {
+        HIPCHK(launch_vj_accum(d_V.as<double>(), d_c.as<double>() + 2 * f0, nk, (int)nf, ne, 1.0 / nk,
+                               static_cast<double *>(vj), st));
+      }
+      f0 += nf;
+    }
+    if (pass == 0) {  // c = (J^0)^{-1} rho = W^H (W rho)
+      HIPCHK(launch_df_gemm(false, d_W.as<double>(), d_cls.as<int32_t>(), d_rho.as<double>(), d_y.as<double>(),
+                            (int)naux, 1, 1, st));
+      HIPCHK(launch_df_gemm(true, d_W.as<double>(), d_cls.as<int32_t>(), d_y.as<double>(), d_c.as<double>(),
+                            (int)naux, 1, 1, st));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (stats) {
+    *stats = acc;
+    stats->bytes_out = (int64_t)nk * ne * 16;
+    stats->t_total_ms = ms_since(t_start);
+  }
+  return RSGDF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Work features of a build for the cost model of the automatic choice of
+// omega (host planning only, no device work)
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                        const int32_t kmesh[3], double omega, double thresh, double g_thresh,
+                        double feat[RSGDF_NFEATURES]) {
+  g_err.clear();
+  if (!feat) return fail(RSGDF_EINVAL, "null feature array");
+  const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
+  if (need < 0) return (int)need;
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
+  if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
+  const double g_thr = g_thresh > 0.0 ? g_thresh : 1e-2 * thresh;
+  HostPlan hp;
+  int rc = build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
+  if (rc) return rc;
+  const Lattice &L = hp.lt.L;
+  const int nk = L.nk, npair = (int)hp.pairs.size(), nxs = (int)hp.ax.size();
+  // short range: the planner's per-item cost (primitive triples x pair images
+  // x lattice vectors in the R_c ball x per-term operations, plus the
+  // per-(triple, image) contraction), summed over every (aux shell, pair)
+  double sr = 0.0, sr_terms = 0.0;
+  for (int P = 0; P < nxs; ++P)
+    for (int ip = 0; ip < npair; ++ip) {
+      const size_t t = (size_t)P * npair + ip;
+      const Pair &pp = hp.pairs[ip];
+      const Shell &sA = hp.ao[pp.sa], &sB = hp.ao[pp.sb], &sP = hp.ax[P];
+      int64_t nimg = 0;
+      for (int c = 0; c < nk; ++c) nimg += hp.nsr[(size_t)ip * nk + c];
+      const double rc_cut = hp.rc_t[t];
+      const double nm = 4.18879020478639098 * rc_cut * rc_cut * rc_cut / L.vol + 1.0;
+      const int Lt = sP.l + sA.l + sB.l;
+      const int lab = sA.l + sB.l, nkx = (sP.l / 2 + 1) * (sP.l / 2 + 1) * (sP.l / 2 + 1);
+      const int nblk = ncart_h(sP.l) * ncart_h(sA.l) * ncart_h(sB.l);
+      const double ev = 2.0 * nherm(Lt) + 2.0 * ncart_h(sP.l) * nherm(lab) * nkx + 2.0 * nblk * nherm(lab);
+      const double nranges = std::ceil((double)nk / std::min(nk, sr_cells_per_wave(nblk)));
+      const double np3 = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg;
+      sr += np3 * (nm * sr_term_flops(Lt) + 13.6 * nranges * ev);
+      sr_terms += np3 * nm;
+    }
+  // long range: q vectors, pair-transform candidates, contraction flops
+  std::vector<double> qv;
+  std::vector<int64_t> qoff;
+  make_qsets(hp.lt, hp.kvec, omega, g_thr, qv, qoff);
+  std::vector<int> kp_of_cls(nk, 0);
+  for (size_t t = 0; t < hp.kp1.size(); ++t) {
+    const int k1 = hp.kp1[t], k2 = hp.kp2[t];
+    const int j1[3] = {k1 / (L.n[1] * L.n[2]), (k1 / L.n[2]) % L.n[1], k1 % L.n[2]};
+    const int j2[3] = {k2 / (L.n[1] * L.n[2]), (k2 / L.n[2]) % L.n[1], k2 % L.n[2]};
+    int c = 0;
+    for (int d = 0; d < 3; ++d) c = c * L.n[d] + ((j2[d] - j1[d]) % L.n[d] + L.n[d]) % L.n[d];
+    kp_of_cls[c]++;
+  }
+  double img_pp = 0.0;  // (primitive pair, image) units of the pair transforms, per q
+  for (int ip = 0; ip < npair; ++ip) {
+    const Pair &pp = hp.pairs[ip];
+    img_pp += (double)hp.ao[pp.sa].nprim * hp.ao[pp.sb].nprim * hp.cls_off[(size_t)ip * (nk + 1) + nk] *
+              ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+  }
+  double nq = 0.0, gemm = 0.0, kphase = 0.0;
+  for (int c = 0; c < nk; ++c) {
+    const double nqc = (double)(qoff[c + 1] - qoff[c]);
+    if (kp_of_cls[c] == 0) continue;
+    nq += nqc;
+    gemm += 8.0 * (double)hp.naux * nqc * (double)hp.nao * hp.nao * kp_of_cls[c];
+    kphase += nqc * (double)hp.nao * hp.nao * (nk + kp_of_cls[c]);
+  }
+  feat[0] = sr;                                              // SR operations (cost estimate)
+  feat[1] = nq * img_pp;                                     // pair-transform candidate components
+  feat[2] = gemm;                                            // contraction flops
+  feat[3] = kphase;                                          // k2-phase elements read + written
+  feat[4] = (double)hp.kp1.size() * hp.naux * hp.nao * hp.nao;  // output elements (fold, write-out)
+  feat[5] = (double)nk * nk * hp.naux * hp.nao * hp.nao;     // short-range intermediate elements
+  feat[6] = nq;                                              // q vectors summed over the classes
+  feat[7] = sr_terms;                                        // SR primitive terms (estimate)
+  feat[8] = 1.0;                                             // per-build fixed cost
+  return RSGDF_OK;
+}
+
+// argmin over the candidate omegas of the predicted time sum_i coef[i] feat[i]
+int rsgdf_choose_omega(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                       const int32_t kmesh[3], double thresh, double g_thresh, const double *omegas, int32_t nomega,
+                       const double coef[RSGDF_NFEATURES], double *best_omega, double *predicted_ms) {
+  g_err.clear();
+  if (!omegas || nomega < 1 || !coef || !best_omega) return fail(RSGDF_EINVAL, "null argument or no candidates");
+  double best = 1e300;
+  int ib = -1;
+  for (int i = 0; i < nomega; ++i) {
+    double f[RSGDF_NFEATURES];
+    const int rc = rsgdf_plan_features(cell, basis, auxbasis, kmesh, omegas[i], thresh, g_thresh, f);
+    if (rc) return rc;
+    double t = 0.0;
+    for (int j = 0; j < RSGDF_NFEATURES; ++j) t += coef[j] * f[j];
+    if (predicted_ms) predicted_ms[i] = t;
+    if (t < best) {
+      best = t;
+      ib = i;
+    }
+  }
+  *best_omega = omegas[ib];
   return RSGDF_OK;
 }
 

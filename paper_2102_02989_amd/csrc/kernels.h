@@ -138,6 +138,12 @@ hipError_t launch_df_factor(const double *J, double *L, double *W, int *bad, int
 hipError_t launch_df_gemm(bool conjt, const double *W, const int32_t *cls, const double *V, double *D, int naux,
                           int64_t ncol, int nkp, hipStream_t stream);
 
+// integral-direct density-fitted Coulomb build (coulomb.hip)
+hipError_t launch_dm_contract(const double *V, const double *D, int nk, int ng, int nao, double *rho,
+                              hipStream_t stream);
+hipError_t launch_vj_accum(const double *V, const double *c, int nk, int ng, int64_t ne, double scale, double *vj,
+                           hipStream_t stream);
+
 // learned screening (learned.hip)
 hipError_t launch_features(const SRParams &prm, int ntrip, const int64_t *idx, int64_t n, float *feat,
                            hipStream_t stream);

@@ -103,6 +103,17 @@ def library():
                                       ctypes.c_double, ctypes.POINTER(Options), ctypes.POINTER(Out)]
         L.rsgdf_df_solve.restype = ctypes.c_int
         L.rsgdf_df_solve.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P, P, P]
+        L.rsgdf_coulomb_direct.restype = ctypes.c_int
+        L.rsgdf_coulomb_direct.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                           ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options), ctypes.c_int32,
+                                           P, P, P, ctypes.POINTER(Stats)]
+        L.rsgdf_plan_features.restype = ctypes.c_int
+        L.rsgdf_plan_features.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.rsgdf_choose_omega.restype = ctypes.c_int
+        L.rsgdf_choose_omega.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                         ctypes.c_double, ctypes.c_double, P, ctypes.c_int32, P,
+                                         ctypes.POINTER(ctypes.c_double), P]
         L.rsgdf_build_j3c_noalloc.restype = ctypes.c_int
         L.rsgdf_build_j3c_noalloc.argtypes = L.rsgdf_build_j3c_ex.argtypes
         F = ctypes.c_float
@@ -297,6 +308,60 @@ def df_solve(kmesh, j2c, j3c, out=None, *, stream=None):
     _check(library().rsgdf_df_solve(km.ctypes.data, naux, ncol, j2c.data_ptr(), j3c.data_ptr(), out.data_ptr(),
                                     stream.cuda_stream))
     return out
+
+
+def coulomb_direct(cell, basis, aux, kmesh, omega, thresh, dm, vj=None, *, aux_group=0, g_thresh=None,
+                   lr_precision=FP64, stream=None):
+    """Run rsgdf_coulomb_direct: the density-fitted Coulomb matrix J(k)
+    [nk, nao, nao] of the densities ``dm`` (complex128 device tensor, same
+    shape) without storing the three-center integrals.  Returns (vj, stats)."""
+    import torch
+    m = _Marshal(cell, basis, aux, kmesh)
+    if dm.dtype != torch.complex128 or not dm.is_contiguous() or not dm.is_cuda:
+        raise ValueError("dm must be a contiguous complex128 CUDA tensor")
+    if vj is None:
+        vj = torch.empty_like(dm)
+    if stream is None:
+        stream = torch.cuda.current_stream(dm.device)
+    keep = []
+    opts = _options(g_thresh, lr_precision, SCREEN_RIGOROUS, PART_ALL, 0, None, 0.0, None, keep)
+    stats = Stats()
+    _check(library().rsgdf_coulomb_direct(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                          m.kmesh.ctypes.data, float(omega), float(thresh), ctypes.byref(opts),
+                                          int(aux_group), dm.data_ptr(), vj.data_ptr(), stream.cuda_stream,
+                                          ctypes.byref(stats)))
+    return vj, stats.as_dict()
+
+
+# ---- automatic choice of omega -----------------------------------------------
+
+NFEATURES = 9
+
+
+def plan_features(cell, basis, aux, kmesh, omega, thresh, g_thresh=None) -> np.ndarray:
+    """rsgdf_plan_features: the cost-model features of one build (host only)."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    f = np.zeros(NFEATURES, np.float64)
+    _check(library().rsgdf_plan_features(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                         m.kmesh.ctypes.data, float(omega), float(thresh),
+                                         -1.0 if g_thresh is None else float(g_thresh), f.ctypes.data))
+    return f
+
+
+def choose_omega(cell, basis, aux, kmesh, thresh, coef, omegas, g_thresh=None):
+    """rsgdf_choose_omega: (best omega, predicted ms per candidate)."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    om = np.ascontiguousarray(omegas, np.float64)
+    cf = np.ascontiguousarray(coef, np.float64)
+    if cf.size != NFEATURES:
+        raise ValueError(f"expected {NFEATURES} coefficients")
+    pred = np.zeros(len(om), np.float64)
+    best = ctypes.c_double(0.0)
+    _check(library().rsgdf_choose_omega(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                        m.kmesh.ctypes.data, float(thresh),
+                                        -1.0 if g_thresh is None else float(g_thresh), om.ctypes.data, len(om),
+                                        cf.ctypes.data, ctypes.byref(best), pred.ctypes.data))
+    return best.value, pred
 
 
 # ---- learned screening -------------------------------------------------------
