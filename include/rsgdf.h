@@ -106,6 +106,13 @@ typedef struct {
   const float *sr_split; /* host [24] per-class work-split factors (rsgdf_autotune_sr), or NULL;
                             class g = 6 l_P + pair class of (l_a, l_b) in order ss, ps, pp, ds,
                             dp, dd                                                            */
+  double alpha_cut;      /* compact/diffuse split (the paper's Fig. 1), 0 = off.  Primitives with
+                            exponent < alpha_cut are diffuse; a primitive triple with a diffuse aux
+                            primitive or two diffuse AO primitives is evaluated by the
+                            range-separation-free reciprocal sum of Eq. M15 (weight 4 pi/(Omega q^2),
+                            q^2 <= 4 alpha_cut ln(1/g_thresh) for a diffuse aux primitive, twice
+                            that for a compact one with two diffuse AO primitives); the others are
+                            range-separated.                                                      */
 } rsgdf_options;
 
 typedef struct rsgdf_stats {

@@ -328,6 +328,7 @@ struct HostPlan {
   std::vector<double> amp_t; // [naux_shell][npair] 1s-model amplitude
   int64_t nao = 0, naux = 0;
   bool diag_only = false;  // k-pairs (k, k) only (the Coulomb consumer needs k12 = 0)
+  double acut = 0.0;       // > 0: compact/diffuse split; the short-range bounds then cover compact aux primitives
   Screen scr;
   // k-points
   std::vector<double> kvec;     // [nk][3]
@@ -421,6 +422,38 @@ void make_qsets(const Lat &lt, const std::vector<double> &kvec, double omega, do
   }
 }
 
+// q sets per folded k12 class c of a plain sphere: q = G + k_c, q != 0,
+// |q|^2 <= q2max, each sorted by |q| (the Eq. M15 part of the split)
+void make_qsets_sphere(const Lat &lt, const std::vector<double> &kvec, double q2max, std::vector<double> &qv,
+                       std::vector<int64_t> &qoff) {
+  const Lattice &L = lt.L;
+  qv.clear();
+  qoff.assign(1, 0);
+  for (int c = 0; c < L.nk; ++c) {
+    const double *kc = &kvec[3 * c];
+    const double qm = std::sqrt(q2max) + std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
+    int w[3];
+    for (int d = 0; d < 3; ++d) w[d] = (int)std::ceil(qm * lt.an[d] / (2.0 * kPi)) + 1;
+    std::vector<std::array<double, 4>> qc;
+    for (int i = -w[0]; i <= w[0]; ++i)
+      for (int j = -w[1]; j <= w[1]; ++j)
+        for (int k = -w[2]; k <= w[2]; ++k) {
+          double q[3], q2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            q[d] = i * L.b[d] + j * L.b[3 + d] + k * L.b[6 + d] + kc[d];
+            q2 += q[d] * q[d];
+          }
+          if (q2 < 1e-20 || q2 > q2max) continue;
+          qc.push_back({q2, q[0], q[1], q[2]});
+        }
+    std::stable_sort(qc.begin(), qc.end(), [](const std::array<double, 4> &x, const std::array<double, 4> &y) {
+      return x[0] < y[0];
+    });
+    for (const auto &e : qc) qv.insert(qv.end(), e.begin() + 1, e.end());
+    qoff.push_back((int64_t)qv.size() / 3);
+  }
+}
+
 // phase table kph[k][c] = e^{+i k.L_c} (complex, [nk][nk])
 std::vector<double> mesh_phases(const Lattice &L) {
   const int nk = L.nk;
@@ -447,6 +480,23 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
   // shells
   hp.nao = pack_shells(bs, cell->coords, hp.ao, hp.ao_exp, hp.ao_coef, hp.ao_c1s);
   hp.naux = pack_shells(ax, cell->coords, hp.ax, hp.ax_exp, hp.ax_coef, hp.ax_c1s);
+  if (hp.acut > 0.0) {
+    // compact/diffuse split: only the compact primitives of an aux shell enter
+    // the short-range sums, so the bounds take the most diffuse of those
+    // (a_d < 0 marks a shell with none: no short-range work)
+    for (Shell &x : hp.ax) {
+      double amin = -1.0, cmin = 0.0;
+      for (int k = 0; k < x.nprim; ++k) {
+        const double a = hp.ax_exp[x.pptr + k];
+        if (a >= hp.acut && (amin < 0.0 || a < amin)) {
+          amin = a;
+          cmin = hp.ax_c1s[x.pptr + k];
+        }
+      }
+      x.a_d = amin;
+      x.c_d = cmin;
+    }
+  }
 
   // k-points and pairs
   hp.kvec = mesh_kvec(L);
@@ -578,13 +628,23 @@ int build_plan(const rsgdf_cell *cell, const rsgdf_basis *bs, const rsgdf_basis 
     }
     for (int P = 0; P < nxs; ++P) {
       double a = 0.0;
-      for (int k = 0; k < hp.ax[P].nprim; ++k) a += hp.ax_c1s[hp.ax[P].pptr + k] / std::pow(hp.ax_exp[hp.ax[P].pptr + k], 1.5);
+      for (int k = 0; k < hp.ax[P].nprim; ++k) {
+        const double g = hp.ax_exp[hp.ax[P].pptr + k];
+        if (hp.acut > 0.0 && g < hp.acut) continue;  // diffuse: Eq. M15 part
+        a += hp.ax_c1s[hp.ax[P].pptr + k] / std::pow(g, 1.5);
+      }
       aaux[P] = a;
     }
     parallel_for((int64_t)nxs * npair, [&](int64_t t) {
       const int P = (int)(t / npair), ip = (int)(t % npair);
       const Pair &p = hp.pairs[ip];
       const Shell &sP = hp.ax[P], &sA = hp.ao[p.sa], &sB = hp.ao[p.sb];
+      if (sP.a_d <= 0.0) {  // no compact primitive (split): no short-range work
+        hp.amp_t[t] = 0.0;
+        hp.rc_t[t] = 0.0;
+        r12t[t] = 0.0;
+        return;
+      }
       const double pd = sA.a_d + sB.a_d;
       const double Aamp = kPi * kPi * kPi * aaux[P] * apair[ip];
       hp.amp_t[t] = Aamp;
@@ -795,9 +855,22 @@ struct Job {
   // LR
   std::vector<int64_t> qoff{0};
   int64_t nq_tot = 0, qchunk = 1;
+  // long-range parts: without the compact/diffuse split one range-separated
+  // part (Eq. M10); with it, the range-separated part of the compact aux
+  // primitives and non-diffuse-diffuse pairs, plus the Eq. M15 parts of the
+  // diffuse aux primitives (every pair) and of the compact aux primitives with
+  // the diffuse-diffuse pairs, on their own q sphere
+  struct LRPart {
+    std::vector<int64_t> qoff{0};
+    int64_t nq_tot = 0;
+    DBuf d_q, d_A, d_A32;
+    int amode = 0, pmode = 0, undamped = 0;
+  };
+  std::vector<std::unique_ptr<LRPart>> lrp;
+  double acut = 0.0;
   std::vector<std::vector<int>> cls_kp;
   std::vector<int64_t> kpl_off{0};
-  DBuf d_q, d_A, d_I, d_B, d_kp, d_ph, d_nterm, d_amax, d_A32, d_Bhi;
+  DBuf d_I, d_B, d_kp, d_ph, d_nterm, d_amax, d_Bhi;
   // results
   float t_sr = 0.f, t_fold = 0.f, t_lr = 0.f, t_lr_gemm = 0.f;
   long long n_lr = 0, nskip = 0;
@@ -847,6 +920,9 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     return fail(RSGDF_EINVAL, "unknown lr_precision");
   if (o.screening != RSGDF_SCREEN_RIGOROUS && o.screening != RSGDF_SCREEN_LEARNED)
     return fail(RSGDF_EINVAL, "unknown screening mode");
+  if (!(o.alpha_cut >= 0.0) || !std::isfinite(o.alpha_cut)) return fail(RSGDF_EINVAL, "alpha_cut must be >= 0");
+  acut = o.alpha_cut;
+  if (!planned) hp.acut = acut;
   learned = o.screening == RSGDF_SCREEN_LEARNED && !logging;
   if (learned && !o.mlp_weights) return fail(RSGDF_EUNSUPPORTED, "learned screening needs mlp_weights");
   if (logging || tune) o.parts = RSGDF_PART_SR;
@@ -949,6 +1025,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
         double v = 0.0;
         for (int k = 0; k < x.nprim; ++k) {
           const double g = hp.ax_exp[x.pptr + k];
+          if (acut > 0.0 && g < acut) continue;  // the G = 0 term belongs to the range-separated part
           double m = hp.ax_coef[x.pptr + k] * std::pow(kPi / g, 1.5);
           const int pw[3] = {lx, ly, lz};
           for (int d = 0; d < 3; ++d) {
@@ -1014,6 +1091,14 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       Triplet tr{};
       tr.aux = (int32_t)(t / npair);
       tr.pair = (int32_t)(t % npair);
+      if (acut > 0.0) {  // split: aux shells with no compact primitive, pairs of diffuse shells
+        const Pair &pq = hp.pairs[tr.pair];
+        if (hp.ax[tr.aux].a_d <= 0.0) continue;
+        bool anyc = false;
+        for (int k = 0; k < hp.ao[pq.sa].nprim && !anyc; ++k) anyc = hp.ao_exp[hp.ao[pq.sa].pptr + k] >= acut;
+        for (int k = 0; k < hp.ao[pq.sb].nprim && !anyc; ++k) anyc = hp.ao_exp[hp.ao[pq.sb].pptr + k] >= acut;
+        if (!anyc) continue;
+      }
       tr.rc_cut = hp.rc_t[t];
       tr.amp = hp.amp_t[t];
       tr.nwin = std::max(1, (int)std::ceil(tr.rc_cut / S.dR));
@@ -1185,6 +1270,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   base.ncell_nf = hp.scr.ncell_nf;
   base.ncell_r0 = hp.scr.r0;
   base.boys = d_boys.as<double>();
+  base.acut = acut;
   base.X = d_X.as<double>();
   base.nao = (int32_t)nao;
   if (do_sr && (learned || logging)) {
@@ -1211,8 +1297,36 @@ int Job::prepare(hipStream_t st, double mem_frac) {
 
   // ---------------------------------------------------------- LR plan
   if (do_lr) {
+    std::vector<double> qv15d, qv15c;
+    std::vector<int64_t> qoff15d, qoff15c;
     make_qsets(hp.lt, hp.kvec, omega, g_thr, qv, qoff);
-    nq_tot = qoff.back();
+    if (acut > 0.0) {
+      // q spheres of Eq. M15: a diffuse aux function (exponent < acut) has
+      // decayed to g_thr at q^2 = 4 acut ln(1/g_thr); a diffuse-diffuse pair
+      // density (exponent sum < 2 acut) at twice that
+      make_qsets_sphere(hp.lt, hp.kvec, 4.0 * acut * std::log(1.0 / g_thr), qv15d, qoff15d);
+      make_qsets_sphere(hp.lt, hp.kvec, 8.0 * acut * std::log(1.0 / g_thr), qv15c, qoff15c);
+    }
+    {
+      auto add = [&](const std::vector<int64_t> &qo, int amode, int pmode, int undamped) {
+        auto pt = std::make_unique<LRPart>();
+        pt->qoff = qo;
+        pt->nq_tot = qo.back();
+        pt->amode = amode;
+        pt->pmode = pmode;
+        pt->undamped = undamped;
+        lrp.push_back(std::move(pt));
+      };
+      if (acut > 0.0) {
+        add(qoff, 1, 1, 0);     // (C | cc + cd), range-separated long range
+        add(qoff15d, 2, 0, 1);  // (D | all pairs), Eq. M15
+        add(qoff15c, 1, 2, 1);  // (C | dd), Eq. M15
+      } else {
+        add(qoff, 0, 0, 0);
+      }
+    }
+    nq_tot = 0;
+    for (auto &pt : lrp) nq_tot += pt->nq_tot;
     // k-pairs per class
     cls_kp.assign(nk, {});
     for (int t = 0; t < nkp; ++t) {
@@ -1223,8 +1337,13 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       for (int d = 0; d < 3; ++d) c = c * L.n[d] + ((j2[d] - j1[d]) % L.n[d] + L.n[d]) % L.n[d];
       cls_kp[c].push_back(t);
     }
-    HIPCHK(upload(d_q, qv, st));
-    HIPCHK(d_A.alloc((size_t)naux * std::max<int64_t>(nq_tot, 1) * 2 * sizeof(double)));
+    for (size_t ip = 0; ip < lrp.size(); ++ip) {
+      LRPart &pt = *lrp[ip];
+      HIPCHK(upload(pt.d_q, (ip == 0) ? qv : (ip == 1 ? qv15d : qv15c), st));
+      HIPCHK(pt.d_A.alloc((size_t)naux * std::max<int64_t>(pt.nq_tot, 1) * 2 * sizeof(double)));
+      if (o.lr_precision != RSGDF_FP64)  // FP32 operands
+        HIPCHK(pt.d_A32.alloc((size_t)naux * std::max<int64_t>(pt.nq_tot, 1) * 2 * sizeof(float)));
+    }
     // per q chunk: pair transforms binned by BvK class (I), the k2 phases of
     // the class's k-pairs (B), then the G-space contraction
     int max_kpi = 0;
@@ -1233,15 +1352,14 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     qchunk = (int64_t)(bbudget / ((double)(nk + std::max(1, max_kpi)) * nao2 * 16.0));
     qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 8192));
     int64_t max_nq = 0;
-    for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, qoff[c + 1] - qoff[c]);
+    for (auto &pt : lrp)
+      for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, pt->qoff[c + 1] - pt->qoff[c]);
     qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
     HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
     HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
-    if (o.lr_precision != RSGDF_FP64) {  // FP32 operands and the FP64 innermost columns
-      HIPCHK(d_A32.alloc((size_t)naux * std::max<int64_t>(nq_tot, 1) * 2 * sizeof(float)));
+    if (o.lr_precision != RSGDF_FP64)  // the FP64 innermost columns
       HIPCHK(d_Bhi.alloc((size_t)max_kpi * kLrNqHi * nao2 * 2 * sizeof(double)));
-    }
     HIPCHK(d_kp.alloc((size_t)std::max(nkp, 1) * sizeof(int32_t)));
     HIPCHK(d_ph.alloc((size_t)std::max(nkp, 1) * nk * 2 * sizeof(double)));
     HIPCHK(d_nterm.alloc(sizeof(long long)));
@@ -1279,6 +1397,7 @@ int Job::enqueue_pre(hipStream_t st) {
   if (do_g0) {
     OvlParams op{d_ao.as<Shell>(), d_aoe.as<double>(), d_aoc.as<double>(), d_pairs.as<Pair>(),
                  d_coff.as<int32_t>(), d_img.as<double>(), npair, hp.lt.L.nk, d_O.as<double>()};
+    op.acut = acut;
     SmnParams sp{d_ao.as<Shell>(), d_pairs.as<Pair>(), d_O.as<double>(), d_kph.as<double>(), npair, nk,
                  (int32_t)nao, 0, d_Smn.as<double>()};
     HIPCHK(launch_overlaps(op, sp, st));
@@ -1390,70 +1509,80 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
   if (!do_lr) return RSGDF_OK;
   const Lattice &L = hp.lt.L;
   HIPCHK(launch_zero(d_nterm.p, sizeof(long long), st));
-  AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), d_q.as<double>(), (int32_t)nq_tot,
-                 (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, d_A.as<double>()};
-  HIPCHK(launch_auxft(ap, st));
   const bool f32 = o.lr_precision != RSGDF_FP64;
-  if (f32) HIPCHK(launch_to_f32(d_A.as<double>(), d_A32.as<float>(), naux * nq_tot * 2, st));
   const int lr_nq_hi = kLrNqHi;
-  for (int c = 0; c < nk; ++c) {
-    const int nkpi = (int)cls_kp[c].size();
-    const int64_t nqc = qoff[c + 1] - qoff[c];
-    if (nkpi == 0 || nqc == 0) continue;
-    for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
-      const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
-      HIPCHK(launch_amax(d_A.as<double>() + 2 * (qoff[c] + q0), nq_tot, (int)naux, nq, d_amax.as<double>(), st));
-      PairFTParams pp{};
-      pp.ao = d_ao.as<Shell>();
-      pp.ao_exp = d_aoe.as<double>();
-      pp.ao_coef = d_aoc.as<double>();
-      pp.pairs = d_pairs.as<Pair>();
-      pp.plist = d_plist.as<int32_t>();
-      for (int g = 0; g < 7; ++g) pp.pgrp[g] = plist_grp[g];
-      pp.cls_off = d_coff.as<int32_t>();
-      pp.img = d_img.as<double>();
-      pp.q = d_q.as<double>() + 3 * (qoff[c] + q0);
-      pp.amax = d_amax.as<double>();
-      pp.npair = npair;
-      pp.nq = nq;
-      pp.nao = (int32_t)nao;
-      pp.nk = nk;
-      for (int d = 0; d < 3; ++d) pp.kn[d] = L.n[d];
-      pp.kcls[0] = c / (L.n[1] * L.n[2]);
-      pp.kcls[1] = (c / L.n[2]) % L.n[1];
-      pp.kcls[2] = c % L.n[2];
-      pp.eps = 1e-8 * thresh;
-      pp.B = d_I.as<double>();
-      pp.nterm = d_nterm.as<long long>();
-      HIPCHK(launch_pairft_binned(pp, st));
-      const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
-      HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
-                           nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
-      LRGemmParams gp{};
-      gp.A = d_A.as<double>() + 2 * (qoff[c] + q0);
-      gp.lda = nq_tot;
-      gp.B = d_B.as<double>();
-      gp.A32 = f32 ? d_A32.as<float>() + 2 * (qoff[c] + q0) : nullptr;
-      gp.B32 = f32 ? d_B.as<float>() : nullptr;
-      gp.Bhi = nq_hi ? d_Bhi.as<double>() : nullptr;
-      gp.out = d_out;
-      gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
-      gp.plane = naux * nao2;
-      gp.naux = (int32_t)naux;
-      gp.nq = nq;
-      gp.nmn = (int32_t)nao2;
-      gp.nq_hi = nq_hi;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (gev) {
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        gev->push_back(e0);
-        gev->push_back(e1);
-        HIPCHK(hipEventRecord(e0, st));
+  for (auto &ptp : lrp) {
+    LRPart &pt = *ptp;
+    if (pt.nq_tot == 0) continue;
+    AuxFTParams ap{d_ax.as<Shell>(), d_axe.as<double>(), d_axc.as<double>(), pt.d_q.as<double>(), (int32_t)pt.nq_tot,
+                   (int32_t)nxs, (int32_t)naux, 0, 4.0 * kPi / L.vol, omega, pt.d_A.as<double>()};
+    ap.acut = acut;
+    ap.amode = pt.amode;
+    ap.undamped = pt.undamped;
+    HIPCHK(launch_auxft(ap, st));
+    if (f32) HIPCHK(launch_to_f32(pt.d_A.as<double>(), pt.d_A32.as<float>(), naux * pt.nq_tot * 2, st));
+    for (int c = 0; c < nk; ++c) {
+      const int nkpi = (int)cls_kp[c].size();
+      const int64_t nqc = pt.qoff[c + 1] - pt.qoff[c];
+      if (nkpi == 0 || nqc == 0) continue;
+      for (int64_t q0 = 0; q0 < nqc; q0 += qchunk) {
+        const int nq = (int)std::min<int64_t>(qchunk, nqc - q0);
+        HIPCHK(launch_amax(pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0), pt.nq_tot, (int)naux, nq,
+                           d_amax.as<double>(), st));
+        PairFTParams pp{};
+        pp.ao = d_ao.as<Shell>();
+        pp.ao_exp = d_aoe.as<double>();
+        pp.ao_coef = d_aoc.as<double>();
+        pp.pairs = d_pairs.as<Pair>();
+        pp.plist = d_plist.as<int32_t>();
+        for (int g = 0; g < 7; ++g) pp.pgrp[g] = plist_grp[g];
+        pp.cls_off = d_coff.as<int32_t>();
+        pp.img = d_img.as<double>();
+        pp.q = pt.d_q.as<double>() + 3 * (pt.qoff[c] + q0);
+        pp.amax = d_amax.as<double>();
+        pp.npair = npair;
+        pp.nq = nq;
+        pp.nao = (int32_t)nao;
+        pp.nk = nk;
+        for (int d = 0; d < 3; ++d) pp.kn[d] = L.n[d];
+        pp.kcls[0] = c / (L.n[1] * L.n[2]);
+        pp.kcls[1] = (c / L.n[2]) % L.n[1];
+        pp.kcls[2] = c % L.n[2];
+        pp.eps = 1e-8 * thresh;
+        pp.B = d_I.as<double>();
+        pp.nterm = d_nterm.as<long long>();
+        pp.acut = acut;
+        pp.pmode = pt.pmode;
+        HIPCHK(launch_pairft_binned(pp, st));
+        const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+        HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
+                             nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
+        LRGemmParams gp{};
+        gp.A = pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0);
+        gp.lda = pt.nq_tot;
+        gp.B = d_B.as<double>();
+        gp.A32 = f32 ? pt.d_A32.as<float>() + 2 * (pt.qoff[c] + q0) : nullptr;
+        gp.B32 = f32 ? d_B.as<float>() : nullptr;
+        gp.Bhi = nq_hi ? d_Bhi.as<double>() : nullptr;
+        gp.out = d_out;
+        gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];
+        gp.plane = naux * nao2;
+        gp.naux = (int32_t)naux;
+        gp.nq = nq;
+        gp.nmn = (int32_t)nao2;
+        gp.nq_hi = nq_hi;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (gev) {
+          HIPCHK(hipEventCreate(&e0));
+          HIPCHK(hipEventCreate(&e1));
+          gev->push_back(e0);
+          gev->push_back(e1);
+          HIPCHK(hipEventRecord(e0, st));
+        }
+        HIPCHK(launch_lr_gemm_tiled(o.lr_precision, gp, 0, nkpi, st));
+        if (gev) HIPCHK(hipEventRecord(e1, st));
+        lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
       }
-      HIPCHK(launch_lr_gemm_tiled(o.lr_precision, gp, 0, nkpi, st));
-      if (gev) HIPCHK(hipEventRecord(e1, st));
-      lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
     }
   }
   return RSGDF_OK;
@@ -1809,6 +1938,7 @@ int rsgdf_batch_create(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis
       th.emplace_back([&]() {
         for (int i; (i = next.fetch_add(1)) < ncell;) {
           Job &j = *B->jobs[i];
+          j.hp.acut = opt ? opt->alpha_cut : 0.0;
           j.plan_rc = build_plan(j.cell, j.basis, j.auxbasis, j.kmesh, j.omega, j.thresh, j.hp);
           if (j.plan_rc) j.plan_err = g_err;  // this worker's message
           j.planned = true;

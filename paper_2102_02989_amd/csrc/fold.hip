@@ -173,6 +173,7 @@ __device__ void ovl_pair_class(const OvlParams &op, int ip, int c) {
     for (int ka = 0; ka < sA.nprim; ++ka)
       for (int kb = 0; kb < sB.nprim; ++kb) {
         const double ga = op.ao_exp[sA.pptr + ka], gb = op.ao_exp[sB.pptr + kb];
+        if (op.acut > 0.0 && ga < op.acut && gb < op.acut) continue;  // a diffuse-diffuse pair: Eq. M15
         const double p = ga + gb, oop = 1.0 / p;
         const double arg = ga * gb * oop * r2;
         if (arg > 46.0) continue; /* e^{-46} ~ 1e-20 */

@@ -35,6 +35,7 @@ struct OvlParams {
   const double *img;
   int32_t npair, nk;
   double *O;             // [npair][nk][36]
+  double acut;           // > 0: leave out primitive pairs with both exponents below acut
 };
 
 struct SmnParams {
@@ -54,6 +55,9 @@ struct AuxFTParams {
   double wfac;           // 4 pi / Omega
   double omega;
   double *A;             // complex [naux][nq] (row stride nq)
+  double acut;           // primitive selection by exponent (amode)
+  int32_t amode;         // 0 every primitive, 1 exponent >= acut, 2 exponent < acut
+  int32_t undamped;      // 1: weight 4 pi/(Omega q^2) (Eq. M15), 0: times exp(-q^2/4w^2) (Eq. M10)
 };
 
 struct PairFTParams {
@@ -72,6 +76,9 @@ struct PairFTParams {
   double eps;             // skip terms whose weighted bound is below this
   double *B;              // complex I[Nk BvK classes][nao][nao][nq]
   long long *nterm;       // running count of transform evaluations
+  double acut;            // primitive-pair selection (pmode) by exponents
+  int32_t pmode;          // 0 every pair, 1 not both below acut, 2 both below acut
+  int32_t pad2;
 };
 
 // leading q columns of each k12 class (the smallest |q|) that the reduced-precision

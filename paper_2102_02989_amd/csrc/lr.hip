@@ -25,7 +25,7 @@ __device__ void auxft_one(const AuxFTParams &ap, int iq, int s) {
   const Shell sh = ap.ax[s];
   const double qx = ap.q[3 * iq], qy = ap.q[3 * iq + 1], qz = ap.q[3 * iq + 2];
   const double q2 = qx * qx + qy * qy + qz * qz;
-  const double w = ap.wfac * exp(-q2 / (4.0 * ap.omega * ap.omega)) / q2;
+  const double w = ap.undamped ? ap.wfac / q2 : ap.wfac * exp(-q2 / (4.0 * ap.omega * ap.omega)) / q2;
   // e^{+i q.C}
   const double ph = qx * sh.x + qy * sh.y + qz * sh.z;
   const double cph = cos(ph), sph = sin(ph);
@@ -34,6 +34,7 @@ __device__ void auxft_one(const AuxFTParams &ap, int iq, int s) {
   for (int i = 0; i < NC; ++i) accr[i] = acci[i] = 0.0;
   for (int k = 0; k < sh.nprim; ++k) {
     const double g = ap.ax_exp[sh.pptr + k], c = ap.ax_coef[sh.pptr + k];
+    if ((ap.amode == 1 && g < ap.acut) || (ap.amode == 2 && g >= ap.acut)) continue;
     const double amp = c * kPi / g * sqrt(kPi / g) * exp(-q2 / (4.0 * g));
     double E[LP + 1][LP + 1];
     hermite_E1<LP>(0.5 / g, E);
@@ -183,6 +184,10 @@ __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, in
   for (int ka = 0; ka < s1.nprim; ++ka)
     for (int kb = 0; kb < s2.nprim; ++kb) {
       const double ga = pp.ao_exp[s1.pptr + ka], gb = pp.ao_exp[s2.pptr + kb];
+      if (pp.pmode != 0) {
+        const bool dd = ga < pp.acut && gb < pp.acut;
+        if ((pp.pmode == 1) == dd) continue;
+      }
       const double p = ga + gb, oop = 1.0 / p, beta = ga * gb * oop;
       const double cc = pp.ao_coef[s1.pptr + ka] * pp.ao_coef[s2.pptr + kb];
       const double pre = kPi * oop * sqrt(kPi * oop);

@@ -107,6 +107,8 @@ struct SRParams {
   double omega, eps, dR;
   double ncell_nf, ncell_r0;  // N_cell model of Eq. S19
   const double *boys;       // [L = 0..kMaxL][kBoysIntervals][kBoysPolyDeg + 1]
+  double acut;              // > 0: compact/diffuse split (primitive triples with a diffuse aux
+                            // primitive or two diffuse AO primitives are left to Eq. M15)
   double *X;                // [Nk][Nk][naux_b][nao][nao]
   int32_t aux_f0, naux_b, nao, pad;
   // learned screening: candidate (triplet, pair image ii) has index cand_off[trip] + ii

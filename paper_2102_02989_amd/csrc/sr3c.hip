@@ -52,7 +52,8 @@ constexpr int kTripC = 9;            // constants per primitive triple
 // (Eqs. S4-S9 with the erfc attenuation), t[8] 1/(2 g_c).
 template <int LP>
 __device__ __forceinline__ void triple_consts(double ga, double gb, double gc, double ca, double cb, double cc,
-                                              double ca1, double cb1, double cc1, double omega, double *t) {
+                                              double ca1, double cb1, double cc1, double omega, double acut,
+                                              double *t) {
   const double p = ga + gb, oop = 1.0 / p;
   const double rpc = 1.0 / (p + gc);
   const double rho = p * gc * rpc;
@@ -70,6 +71,13 @@ __device__ __forceinline__ void triple_consts(double ga, double gb, double gc, d
   t[7] = kPi * kPi * kPi * cc1 * ca1 * cb1 / (gc * p * sqrt(gc * p)) * 2.0 * (e1 - e2) *
          0.564189583547756286948079451561;
   t[8] = 0.5 / gc;
+  // compact/diffuse split: a diffuse aux primitive or two diffuse AO
+  // primitives put the triple into the Eq. M15 part; a zero screening estimate
+  // makes the image loop's primitive screen skip it
+  if (acut > 0.0 && (gc < acut || (ga < acut && gb < acut))) {
+    t[6] = 0.0;
+    t[7] = 0.0;
+  }
 }
 
 // cells per wave for which the Cartesian accumulators of a class fit in LDS
@@ -189,7 +197,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
       const int kc = t % ntcp, kab = t / ntcp, kb = kab % ntb, ka = kab / ntb;
       triple_consts<LP>(prm.ao_exp[shA.pptr + ka], prm.ao_exp[shB.pptr + kb], prm.ax_exp[shP.pptr + kc],
                         prm.ao_coef[shA.pptr + ka], prm.ao_coef[shB.pptr + kb], prm.ax_coef[shP.pptr + kc],
-                        prm.ao_c1s[shA.pptr + ka], prm.ao_c1s[shB.pptr + kb], prm.ax_c1s[shP.pptr + kc], prm.omega,
+                        prm.ao_c1s[shA.pptr + ka], prm.ao_c1s[shB.pptr + kb], prm.ax_c1s[shP.pptr + kc], prm.omega, prm.acut,
                         s_tc + t * kTripC);
     }
   const double pd = shA.a_d + shB.a_d;
@@ -410,7 +418,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
             triple_consts<LP>(prm.ao_exp[shA.pptr + ka], prm.ao_exp[shB.pptr + kb], prm.ax_exp[shP.pptr + kc],
                               prm.ao_coef[shA.pptr + ka], prm.ao_coef[shB.pptr + kb], prm.ax_coef[shP.pptr + kc],
                               prm.ao_c1s[shA.pptr + ka], prm.ao_c1s[shB.pptr + kb], prm.ax_c1s[shP.pptr + kc],
-                              omega, tcl);
+                              omega, prm.acut, tcl);
           }
           const double oop = tcl[0];
           const double Kab = exp(-tcl[2] * r12sq);

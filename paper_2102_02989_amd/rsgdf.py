@@ -43,7 +43,7 @@ class BasisT(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("g_thresh", ctypes.c_double), ("lr_precision", ctypes.c_int32), ("screening", ctypes.c_int32),
                 ("parts", ctypes.c_int32), ("sr_slices", ctypes.c_int32), ("mlp_weights", ctypes.c_void_p),
-                ("mlp_margin", ctypes.c_double), ("sr_split", ctypes.c_void_p)]
+                ("mlp_margin", ctypes.c_double), ("sr_split", ctypes.c_void_p), ("alpha_cut", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -194,18 +194,19 @@ def nkpairs(kmesh) -> int:
     return nk * (nk + 1) // 2
 
 
-def _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep):
+def _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep,
+             alpha_cut=0.0):
     w = None if mlp_weights is None else _f32(mlp_weights, MLP_NPARAM)
     sp = None if sr_split is None else _f32(sr_split, 24)
     keep += [w, sp]
     return Options(-1.0 if g_thresh is None else float(g_thresh), int(lr_precision), int(screening), int(parts),
                    int(sr_slices), None if w is None else w.ctypes.data, float(mlp_margin),
-                   None if sp is None else sp.ctypes.data)
+                   None if sp is None else sp.ctypes.data, float(alpha_cut))
 
 
 def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None, lr_precision=FP64,
               screening=SCREEN_RIGOROUS, parts=PART_ALL, sr_slices=0, mlp_weights=None, mlp_margin=0.0,
-              sr_split=None, stream=None, _noalloc=False):
+              sr_split=None, alpha_cut=0.0, stream=None, _noalloc=False):
     """Run rsgdf_build_j3c_ex.
 
     ``out``: a contiguous complex128 torch tensor on the GPU of shape
@@ -239,7 +240,8 @@ def build_j3c(cell, basis, aux, kmesh, omega, thresh, out=None, *, g_thresh=None
     stats = Stats()
     o = Out(ptr, cap, int(on_device), sptr, 0, 0, 0, ctypes.pointer(stats))
     keep = []
-    opts = _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep)
+    opts = _options(g_thresh, lr_precision, screening, parts, sr_slices, mlp_weights, mlp_margin, sr_split, keep,
+                    alpha_cut)
     fn = library().rsgdf_build_j3c_noalloc if _noalloc else library().rsgdf_build_j3c_ex
     rc = fn(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux), m.kmesh.ctypes.data, float(omega),
             float(thresh), ctypes.byref(opts), ctypes.byref(o))
