@@ -12,12 +12,13 @@ contraction.
 Two forms are timed on the same input:
   plain  : rsgdf_build_j3c, every stage FP64, rigorous screening;
   chosen : rsgdf_build_j3c_ex with the G-space contraction on reduced-
-           precision matrix cores (operands rounded to FP32, FP32 products
-           accumulated 16 q at a time and promoted to FP64; the 32
-           innermost q of each class in FP64) and learned screening with the
-           committed network at its calibrated margin (the largest
-           under-prediction on held-out samples).  Boys, erfc, every
-           transform and the Bloch sums stay FP64.
+           precision matrix cores (each operand scaled per 32-q block by a
+           power of two and split into two FP16 numbers, three FP16
+           products per real product accumulated in FP32 over the block and
+           promoted to FP64; the 32 innermost q of each class in FP64) and
+           learned screening with the committed network at its calibrated
+           margin (the largest under-prediction on held-out samples).  Boys,
+           erfc, every transform and the Bloch sums stay FP64.
 The chosen form is timed for --steps steps (after --warmup), the plain form
 --plain-steps times; the chosen form's maximum absolute deviation from the
 plain output is taken over the whole tensor.  Sub-records time both forms
@@ -41,9 +42,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR = 78.6e12  # 256 CU x 4 SIMD x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}  # dense matrix-core peaks per operand type
-LR_CHOICES = ("bf16x3", "fp32", "fp64")
-CHOSEN_LR_NAME = "fp32"  # G-space contraction operands of the chosen form (paper_2102_02989_amd.chosen)
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "f16x3": 2.5e15}  # dense matrix-core peaks per operand type
+LR_CHOICES = ("f16x3", "fp32", "fp64")
 TRAFFIC_FILES = {  # committed FETCH_SIZE / WRITE_SIZE summaries, keyed by kernel family
     "sr": os.path.join(ROOT, "profiles", "sr3c_c2_traffic.json"),
     "lr_gemm": os.path.join(ROOT, "profiles", "lr_gemm_c3_traffic.json"),
@@ -201,7 +201,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"],
                     help="c3 (default): the 8-atom cell on the 3x3x3 mesh at omega = 1.5; c2: the same cell on "
                          "the 2x2x2 mesh at omega = 0.1; c5: the 16-atom cell on the 4x4x4 mesh; c1: the 2-atom cell")
-    ap.add_argument("--lr", default=CHOSEN_LR_NAME, choices=LR_CHOICES, help="chosen form's contraction")
+    from paper_2102_02989_amd.chosen import CHOSEN_LR  # numpy and ctypes only: no device touched yet
+    ap.add_argument("--lr", default=CHOSEN_LR, choices=LR_CHOICES, help="chosen form's contraction")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-sub", action="store_true", help="skip the sub-records of the other workloads")
     ap.add_argument("--form", default="both", choices=["both", "plain", "chosen"],

@@ -64,10 +64,11 @@ extern "C" {
  * matrix product per k12 class).  In every form the transforms, the kernel
  * weight, the Bloch phases and the output are FP64; the reduced forms take
  * the 32 smallest-|q| vectors of each class in FP64 and add each 16-q FP32
- * partial into FP64 registers. */
+ * partial (32 q in the F16X3 form) into FP64 registers. */
 #define RSGDF_FP64 0   /* plain: FP64 matrix-core products                          */
 #define RSGDF_FP32 1   /* operands rounded to FP32, FP32 matrix-core products        */
-#define RSGDF_BF16X3 2 /* operands split hi + lo in BF16, three BF16 products        */
+#define RSGDF_F16X3 2  /* operands scaled per row by 2^e, split hi + lo in FP16,
+                          three FP16 products                                     */
 
 /* short-range image screening */
 #define RSGDF_SCREEN_RIGOROUS 0 /* Supplementary-Material bounds (Eqs. S14, S23-S27) */
@@ -97,7 +98,7 @@ typedef struct {
 
 typedef struct {
   double g_thresh;       /* keep q with exp(-|q|^2/4w^2) >= g_thresh; <= 0 -> 1e-2*thresh   */
-  int32_t lr_precision;  /* RSGDF_FP64 | RSGDF_FP32 | RSGDF_BF16X3                          */
+  int32_t lr_precision;  /* RSGDF_FP64 | RSGDF_FP32 | RSGDF_F16X3                           */
   int32_t screening;     /* RSGDF_SCREEN_RIGOROUS | RSGDF_SCREEN_LEARNED                    */
   int32_t parts;         /* RSGDF_PART_* mask; 0 -> RSGDF_PART_ALL                          */
   int32_t sr_slices;     /* lanes cooperating on one (k-cell pair) unit; 0 -> automatic     */

@@ -11,7 +11,7 @@ from .rsgdf import (  # noqa: F401
     PART_SR,
     FP64,
     FP32,
-    BF16X3,
+    F16X3,
     Batch,
     autotune_sr,
     MLP_NFEAT,

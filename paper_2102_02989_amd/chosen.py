@@ -1,9 +1,11 @@
 """The chosen form of the build: the options that the benchmark times and the
 tests check against the oracle (one definition for both).
 
-  * G-space contraction on reduced-precision matrix cores (default: operands
-    rounded to FP32, FP32 products accumulated 16 q at a time and promoted to
-    FP64; the 32 innermost q of each k12 class in FP64);
+  * G-space contraction on reduced-precision matrix cores (default: each
+    operand scaled per 32-q block by a power of two and split into two FP16
+    numbers, three FP16 products per real product accumulated in FP32 over
+    the block and promoted to FP64; the 32 innermost q of each k12 class in
+    FP64);
   * learned screening with the committed network at its calibrated margin:
     the largest under-prediction (log10 units) on the held-out 20% of the
     training samples, so no held-out candidate above thresh would be dropped.
@@ -17,11 +19,11 @@ import os
 
 import numpy as np
 
-from .rsgdf import BF16X3, FP32, FP64, SCREEN_LEARNED
+from .rsgdf import F16X3, FP32, FP64, SCREEN_LEARNED
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "screen_mlp.npz")
-LR_FORMS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
-CHOSEN_LR = "fp32"
+LR_FORMS = {"fp64": FP64, "fp32": FP32, "f16x3": F16X3}
+CHOSEN_LR = "f16x3"
 
 
 def network():

@@ -871,6 +871,7 @@ struct Job {
   std::vector<std::vector<int>> cls_kp;
   std::vector<int64_t> kpl_off{0};
   DBuf d_I, d_B, d_kp, d_ph, d_nterm, d_amax, d_Bhi;
+  DBuf d_Asp;  // split-FP16 aux operand of one chunk (F16X3 form)
   // results
   float t_sr = 0.f, t_fold = 0.f, t_lr = 0.f, t_lr_gemm = 0.f;
   long long n_lr = 0, nskip = 0;
@@ -916,7 +917,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   }
   if (o.parts == 0) o.parts = RSGDF_PART_ALL;
   g_thr = (o.g_thresh > 0.0) ? o.g_thresh : 1e-2 * thresh;
-  if (o.lr_precision != RSGDF_FP64 && o.lr_precision != RSGDF_FP32 && o.lr_precision != RSGDF_BF16X3)
+  if (o.lr_precision != RSGDF_FP64 && o.lr_precision != RSGDF_FP32 && o.lr_precision != RSGDF_F16X3)
     return fail(RSGDF_EINVAL, "unknown lr_precision");
   if (o.screening != RSGDF_SCREEN_RIGOROUS && o.screening != RSGDF_SCREEN_LEARNED)
     return fail(RSGDF_EINVAL, "unknown screening mode");
@@ -1341,7 +1342,7 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       LRPart &pt = *lrp[ip];
       HIPCHK(upload(pt.d_q, (ip == 0) ? qv : (ip == 1 ? qv15d : qv15c), st));
       HIPCHK(pt.d_A.alloc((size_t)naux * std::max<int64_t>(pt.nq_tot, 1) * 2 * sizeof(double)));
-      if (o.lr_precision != RSGDF_FP64)  // FP32 operands
+      if (o.lr_precision == RSGDF_FP32)  // FP32 operands
         HIPCHK(pt.d_A32.alloc((size_t)naux * std::max<int64_t>(pt.nq_tot, 1) * 2 * sizeof(float)));
     }
     // per q chunk: pair transforms binned by BvK class (I), the k2 phases of
@@ -1355,11 +1356,15 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     for (auto &pt : lrp)
       for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, pt->qoff[c + 1] - pt->qoff[c]);
     qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
+    if (o.lr_precision == RSGDF_F16X3)  // whole 32-q blocks per chunk (the split format's unit)
+      qchunk = std::max<int64_t>(kF16Blk, qchunk / kF16Blk * kF16Blk);
     HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
     HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
     if (o.lr_precision != RSGDF_FP64)  // the FP64 innermost columns
       HIPCHK(d_Bhi.alloc((size_t)max_kpi * kLrNqHi * nao2 * 2 * sizeof(double)));
+    if (o.lr_precision == RSGDF_F16X3)  // halves [nb][naux][4][32], then exponents [nb][naux]
+      HIPCHK(d_Asp.alloc(f16_split_bytes(naux, qchunk)));
     HIPCHK(d_kp.alloc((size_t)std::max(nkp, 1) * sizeof(int32_t)));
     HIPCHK(d_ph.alloc((size_t)std::max(nkp, 1) * nk * 2 * sizeof(double)));
     HIPCHK(d_nterm.alloc(sizeof(long long)));
@@ -1520,7 +1525,8 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
     ap.amode = pt.amode;
     ap.undamped = pt.undamped;
     HIPCHK(launch_auxft(ap, st));
-    if (f32) HIPCHK(launch_to_f32(pt.d_A.as<double>(), pt.d_A32.as<float>(), naux * pt.nq_tot * 2, st));
+    if (o.lr_precision == RSGDF_FP32)
+      HIPCHK(launch_to_f32(pt.d_A.as<double>(), pt.d_A32.as<float>(), naux * pt.nq_tot * 2, st));
     for (int c = 0; c < nk; ++c) {
       const int nkpi = (int)cls_kp[c].size();
       const int64_t nqc = pt.qoff[c + 1] - pt.qoff[c];
@@ -1555,14 +1561,33 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
         pp.pmode = pt.pmode;
         HIPCHK(launch_pairft_binned(pp, st));
         const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
-        HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
-                             nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
+        const bool split = o.lr_precision == RSGDF_F16X3;
+        const int nb = (nq + kF16Blk - 1) / kF16Blk;
+        // split format: halves, then the exponents at a 256-byte boundary
+        uint16_t *Xa = d_Asp.as<uint16_t>(), *Xb = d_B.as<uint16_t>();
+        int32_t *Ea = reinterpret_cast<int32_t *>(d_Asp.as<char>() + f16_split_eoff(naux, nb));
+        int32_t *Eb = reinterpret_cast<int32_t *>(d_B.as<char>() + f16_split_eoff((int64_t)nkpi * nao2, nb));
+        if (split) {
+          HIPCHK(launch_asplit(pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0), pt.nq_tot, (int)naux, nq, Xa, Ea, st));
+          HIPCHK(launch_kphase_split(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, Xb, Eb,
+                                     nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
+        } else {
+          HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
+                               nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
+        }
         LRGemmParams gp{};
         gp.A = pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0);
         gp.lda = pt.nq_tot;
         gp.B = d_B.as<double>();
-        gp.A32 = f32 ? pt.d_A32.as<float>() + 2 * (pt.qoff[c] + q0) : nullptr;
-        gp.B32 = f32 ? d_B.as<float>() : nullptr;
+        gp.A32 = o.lr_precision == RSGDF_FP32 ? pt.d_A32.as<float>() + 2 * (pt.qoff[c] + q0) : nullptr;
+        gp.B32 = o.lr_precision == RSGDF_FP32 ? d_B.as<float>() : nullptr;
+        if (split) {
+          gp.Xa = Xa;
+          gp.Ea = Ea;
+          gp.Xb = Xb;
+          gp.Eb = Eb;
+          gp.nb = nb;
+        }
         gp.Bhi = nq_hi ? d_Bhi.as<double>() : nullptr;
         gp.out = d_out;
         gp.kp_of = d_kp.as<int32_t>() + kpl_off[c];

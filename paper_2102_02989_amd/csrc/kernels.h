@@ -97,6 +97,12 @@ struct LRGemmParams {
   int64_t plane;          // naux * nmn
   int32_t naux, nq, nmn;
   int32_t nq_hi;          // leading q columns taken in FP64 by the reduced-precision forms
+  // mode 2: operands split into FP16 planes in blocks of 32 q (see lr.hip)
+  const uint16_t *Xa;     // [nb][naux][4][32]
+  const int32_t *Ea;      // [nb][naux] block exponents of Xa
+  const uint16_t *Xb;     // [nkpi][nb][nmn][4][32]
+  const int32_t *Eb;      // [nkpi][nb][nmn]
+  int32_t nb;             // 32-q blocks of the launch, ceil(nq / 32)
 };
 
 // two-center metric (j2c.hip): one (P shell, Q shell) pair of an angular class
@@ -134,6 +140,20 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
                          int nkpi, int nq, int64_t nmn, hipStream_t stream);
 hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t stream);
+// split FP16 operand formats of the mode-2 contraction (lr.hip)
+constexpr int kF16Blk = 32;  // q per block
+static_assert(kLrNqHi % kF16Blk == 0, "the FP64 columns end on a split block boundary");
+// byte offset of the exponents [nb][rows] behind the halves [nb][rows][4][32]
+inline int64_t f16_split_eoff(int64_t rows, int64_t nb) { return (rows * nb * 4 * kF16Blk * 2 + 255) / 256 * 256; }
+// bytes of the split format of rows x nq (nq a multiple of the block)
+inline int64_t f16_split_bytes(int64_t rows, int64_t nq) {
+  const int64_t nb = (nq + kF16Blk - 1) / kF16Blk;
+  return f16_split_eoff(rows, nb) + rows * nb * 4;
+}
+hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, uint16_t *Xa, int32_t *Ea,
+                         hipStream_t stream);
+hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *Xb, int32_t *Eb, double *Bhi,
+                               int nq_hi, int nk, int nkpi, int nq, int64_t nmn, hipStream_t stream);
 
 // two-center metric (j2c.hip) and the density-fitting solve (df.hip)
 hipError_t launch_j2c_sr(int lP, int lQ, const J2Params &jp, int p0, int npair, hipStream_t stream);

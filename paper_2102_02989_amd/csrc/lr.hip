@@ -366,14 +366,54 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 }
 
 // B[kpi][mn][q] = sum_c phase[kpi][c] I[c][mn][q], phase = e^{+i k2.L_c}; one
-// thread per (mn, q) element.  The k-pairs are taken 16 at a time with their
-// sums in registers, so each I value is read once per 16 k-pairs; the phases
-// are uniform over the wave (scalar loads).  F32: B is written as FP32 pairs
-// (the operand format of the reduced-precision contractions, half the bytes),
-// and the first nq_hi columns also in FP64 into Bhi[kpi][mn][nq_hi] (the
-// columns those forms contract in FP64).
-constexpr int KPH_KB = 16;
-template <bool F32>
+// thread per (mn, q) element.  The k-pairs of the class are taken KB at a time
+// with their sums in registers, KB chosen per launch so that one pass covers
+// up to 28 k-pairs and the passes are even (each pass reads I once); the
+// phases are uniform over the wave (scalar loads), and KPH_CB image classes'
+// loads are in flight before their multiply-adds.  F32: B is written as FP32
+// pairs (the operand format of the FP32 contraction, half the bytes), and the
+// first nq_hi columns also in FP64 into Bhi[kpi][mn][nq_hi] (the columns the
+// reduced-precision forms contract in FP64).
+constexpr int KPH_CB = 3;
+constexpr int KPH_KBMAX = 28;
+// KB of a class with nkpi k-pairs: the pass width rounded up to 4
+inline int kphase_kb(int nkpi) {
+  const int npass = (nkpi + KPH_KBMAX - 1) / KPH_KBMAX;
+  const int per = (nkpi + npass - 1) / npass;
+  return (per + 3) / 4 * 4;
+}
+
+template <int KB>
+__device__ __forceinline__ void kphase_sums(const double *__restrict__ I, int64_t ne, int64_t src, bool ok,
+                                            const double *__restrict__ phase, int nk, int k0, int nkpi,
+                                            double (&sr)[KB], double (&si)[KB]) {
+#pragma unroll
+  for (int kk = 0; kk < KB; ++kk) sr[kk] = si[kk] = 0.0;
+  if (!ok) return;
+  for (int c0 = 0; c0 < nk; c0 += KPH_CB) {
+    double ir[KPH_CB], ii[KPH_CB];
+#pragma unroll
+    for (int j = 0; j < KPH_CB; ++j) {
+      const int c = (c0 + j < nk) ? c0 + j : c0;  // clamped: in-bounds, unused below
+      ir[j] = I[2 * ((int64_t)c * ne + src)];
+      ii[j] = I[2 * ((int64_t)c * ne + src) + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < KPH_CB; ++j) {
+      if (c0 + j >= nk) break;
+      const int c = c0 + j;
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        const int k = (k0 + kk < nkpi) ? k0 + kk : nkpi - 1;  // clamped: in-bounds, result unused
+        const double pr = phase[2 * (k * nk + c)], pi = phase[2 * (k * nk + c) + 1];
+        sr[kk] += pr * ir[j] - pi * ii[j];
+        si[kk] += pr * ii[j] + pi * ir[j];
+      }
+    }
+  }
+}
+
+template <bool F32, int KB>
 __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ I, const double *__restrict__ phase,
                                                      void *__restrict__ Bout, double *__restrict__ Bhi, int nq_hi,
                                                      int nk, int nkpi, int nq, int64_t nmn) {
@@ -382,22 +422,11 @@ __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ 
   if (gid >= ne) return;
   const int q = (int)(gid % nq);
   const int64_t mn = gid / nq;
-  for (int k0 = 0; k0 < nkpi; k0 += KPH_KB) {
-    double sr[KPH_KB], si[KPH_KB];
+  for (int k0 = 0; k0 < nkpi; k0 += KB) {
+    double sr[KB], si[KB];
+    kphase_sums<KB>(I, ne, gid, true, phase, nk, k0, nkpi, sr, si);
 #pragma unroll
-    for (int kk = 0; kk < KPH_KB; ++kk) sr[kk] = si[kk] = 0.0;
-    for (int c = 0; c < nk; ++c) {
-      const double ir = I[2 * ((int64_t)c * ne + gid)], ii = I[2 * ((int64_t)c * ne + gid) + 1];
-#pragma unroll
-      for (int kk = 0; kk < KPH_KB; ++kk) {
-        const int k = (k0 + kk < nkpi) ? k0 + kk : nkpi - 1;  // clamped: in-bounds, result unused
-        const double pr = phase[2 * (k * nk + c)], pi = phase[2 * (k * nk + c) + 1];
-        sr[kk] += pr * ir - pi * ii;
-        si[kk] += pr * ii + pi * ir;
-      }
-    }
-#pragma unroll
-    for (int kk = 0; kk < KPH_KB; ++kk)
+    for (int kk = 0; kk < KB; ++kk)
       if (k0 + kk < nkpi) {
         const int64_t o = (int64_t)(k0 + kk) * ne + gid;
         if constexpr (F32) {
@@ -418,15 +447,31 @@ __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ 
   }
 }
 
+#define KPH_DISPATCH(KERNEL, ...)                                                                   \
+  switch (kphase_kb(nkpi)) {                                                                        \
+    case 4: hipLaunchKernelGGL(KERNEL(4), grid, dim3(256), 0, stream, __VA_ARGS__); break;          \
+    case 8: hipLaunchKernelGGL(KERNEL(8), grid, dim3(256), 0, stream, __VA_ARGS__); break;          \
+    case 12: hipLaunchKernelGGL(KERNEL(12), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
+    case 16: hipLaunchKernelGGL(KERNEL(16), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
+    case 20: hipLaunchKernelGGL(KERNEL(20), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
+    case 24: hipLaunchKernelGGL(KERNEL(24), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL(KERNEL(28), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
+  }
+
 hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
                          int nkpi, int nq, int64_t nmn, hipStream_t stream) {
   const int64_t ne = (int64_t)nq * nmn;
   if (ne == 0 || nkpi == 0) return hipSuccess;
   const dim3 grid((unsigned)((ne + 255) / 256));
-  if (f32)
-    hipLaunchKernelGGL(kphase_kernel<true>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
-  else
-    hipLaunchKernelGGL(kphase_kernel<false>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+#define KPH_F32(kb) kphase_kernel<true, kb>
+#define KPH_F64(kb) kphase_kernel<false, kb>
+  if (f32) {
+    KPH_DISPATCH(KPH_F32, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn)
+  } else {
+    KPH_DISPATCH(KPH_F64, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn)
+  }
+#undef KPH_F32
+#undef KPH_F64
   return hipGetLastError();
 }
 
@@ -448,26 +493,21 @@ hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t strea
 // 16x16 MFMA blocks: C_re += A_re B_re - A_im B_im, C_im += A_re B_im + A_im B_re.
 //   mode 0: FP64 operands, v_mfma_f64_16x16x4 (FP64 accumulation)
 //   mode 1: FP32 operands (rounded from FP64), v_mfma_f32_16x16x4
-//   mode 2: each FP32 operand split x = hi + lo into two BF16 numbers;
-//           a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on v_mfma_f32_16x16x16_bf16
-// In modes 1 and 2 the matrix cores accumulate 16 q at a time in FP32; each
-// 16-q partial is then added to FP64 registers, and the first nq_hi columns
+//   mode 2: split FP16 (lr_gemm_f16x3_kernel below): each FP32 operand of a
+//           32-q step scaled by a power of two per row and split x = hi + lo
+//           into two FP16 numbers; a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//           v_mfma_f32_16x16x32_f16
+// In modes 1 and 2 the matrix cores accumulate one step (16 q, resp. 32 q) in
+// FP32; each step's partial is then added to FP64 registers, and the first nq_hi columns
 // (the smallest |q|, whose kernel weights 1/q^2 dominate) are taken in FP64
 // on the vector ALUs.
 // Operand fragments (li = lane % 16, lg = lane / 16):
 //   16x16x4 (f64, f32): A[li][lg], B[lg][li]
-//   16x16x16 bf16:      A[li][4 lg + j], B[4 lg + j][li], j = 0..3 packed
+//   16x16x32 f16:       A[li][8 lg + j], B[8 lg + j][li], j = 0..7 packed
 // Result fragments, register v of a lane:
 //   f64: D[lg + 4 v][li]       f32: D[4 lg + v][li]
 typedef double lr_d4 __attribute__((ext_vector_type(4)));
 typedef float lr_f4 __attribute__((ext_vector_type(4)));
-typedef short lr_s4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short lr_f2bf(float x) {  // round to nearest even
-  const unsigned u = __float_as_uint(x);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-__device__ __forceinline__ float lr_bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---- tiled G-space contraction ----------------------------------------------
 // Workgroup output tile BM (aux rows) x BN (pair columns): 2 x (BM/32)
@@ -496,10 +536,6 @@ struct TgTile<0> {  // FP64 re / im planes
 template <>
 struct TgTile<1> {  // FP32 re / im planes
   float ar[64][TG_BK + 1], ai[64][TG_BK + 1], br[tg_bn(1)][TG_BK + 1], bi[tg_bn(1)][TG_BK + 1];
-};
-template <>
-struct TgTile<2> {  // BF16 hi / lo of re / im; rows of 16 + 4 halves (8-byte aligned)
-  unsigned short a[4][64][TG_BK + 4], b[4][tg_bn(2)][TG_BK + 4];  // planes: re_hi, re_lo, im_hi, im_lo
 };
 
 template <int MODE>
@@ -573,40 +609,14 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
         const int row = sr0 + r * (NT / 4);
-        if constexpr (MODE == 0) {
-          S.ar[row][sq + j] = ga[r][2 * j];
-          S.ai[row][sq + j] = ga[r][2 * j + 1];
-        } else if constexpr (MODE == 1) {
-          S.ar[row][sq + j] = ga[r][2 * j];
-          S.ai[row][sq + j] = ga[r][2 * j + 1];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const float f = ga[r][2 * j + c];
-            const unsigned short h = lr_f2bf(f);
-            S.a[2 * c][row][sq + j] = h;
-            S.a[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
-          }
-        }
+        S.ar[row][sq + j] = ga[r][2 * j];
+        S.ai[row][sq + j] = ga[r][2 * j + 1];
       }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int row = sr0 + r * (NT / 4);
-        if constexpr (MODE == 0) {
-          S.br[row][sq + j] = gb[r][2 * j];
-          S.bi[row][sq + j] = gb[r][2 * j + 1];
-        } else if constexpr (MODE == 1) {
-          S.br[row][sq + j] = gb[r][2 * j];
-          S.bi[row][sq + j] = gb[r][2 * j + 1];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const float f = gb[r][2 * j + c];
-            const unsigned short h = lr_f2bf(f);
-            S.b[2 * c][row][sq + j] = h;
-            S.b[2 * c + 1][row][sq + j] = lr_f2bf(f - lr_bf2f(h));
-          }
-        }
+        S.br[row][sq + j] = gb[r][2 * j];
+        S.bi[row][sq + j] = gb[r][2 * j + 1];
       }
     }
   };
@@ -660,7 +670,7 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
     sstore();
     __syncthreads();
     if (k0 + TG_BK < gp.nq) gload(k0 + TG_BK);  // in flight during the MFMAs
-    if constexpr (MODE == 0 || MODE == 1) {
+    {
 #pragma unroll
       for (int ks = 0; ks < TG_BK / 4; ++ks) {
         const int k = ks * 4 + lg;
@@ -693,51 +703,6 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
             }
           }
       }
-    } else {
-      lr_s4 a[2][4], an[2][2], b[NB][4];  // a: re_hi, re_lo, im_hi, im_lo; an: -im_hi, -im_lo
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          const unsigned short *src = &S.a[pl][wm * 32 + r * 16 + li][4 * lg];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) a[r][pl][j] = (short)src[j];
-        }
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          an[r][0][j] = (short)((unsigned short)a[r][2][j] ^ 0x8000u);
-          an[r][1][j] = (short)((unsigned short)a[r][3][j] ^ 0x8000u);
-        }
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          const unsigned short *src = &S.b[pl][wn * (BN / 2) + c * 16 + li][4 * lg];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) b[c][pl][j] = (short)src[j];
-        }
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          lr_f4 x = cre[r][c], y = cim[r][c];
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][0], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][1], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][1], b[c][0], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][0], b[c][2], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][0], b[c][3], x, 0, 0, 0);
-          x = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(an[r][1], b[c][2], x, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][2], y, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][0], b[c][3], y, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][1], b[c][2], y, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][2], b[c][0], y, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][2], b[c][1], y, 0, 0, 0);
-          y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r][3], b[c][0], y, 0, 0, 0);
-          cre[r][c] = x;
-          cim[r][c] = y;
-        }
     }
     if constexpr (MODE != 0) {
 #pragma unroll
@@ -776,6 +741,351 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
       }
 }
 
+// ---- split-FP16 contraction (mode 2) ------------------------------------------
+// Operand format.  The q range of a launch is cut into blocks of 32 q.  In a
+// block every operand row (an aux function of A; a pair column of one k-pair's
+// B) is scaled by 2^-e, e chosen so that the row's largest |re|, |im| in the
+// block lies in [2^14, 2^15) (e = 0 for a zero row), and each scaled value x'
+// is split x' = hi + lo with hi = fp16(x'), lo = fp16(x' - hi): 22 significant
+// bits, always inside the FP16 range.  Storage per (block, row): 256 bytes, the
+// planes re_hi, re_lo, im_hi, im_lo of 32 halves, and the exponent e as an int;
+// q past the end of the launch are zero.  The producers write this format
+// from FP64 values (asplit_kernel from the aux transforms, kphase_split_kernel
+// from the Bloch sums), so the contraction only copies 16-byte pieces.
+//
+// Contraction: a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (the dropped lo_a lo_b
+// is 2^-22 of the product) on v_mfma_f32_16x16x32_f16, FP32 accumulation over
+// one block; after each block the FP32 sums are scaled back by 2^(e_m + e_n)
+// (exact) and added to FP64 registers.  The first nq_hi q of the class are
+// taken in FP64 on the vector ALUs as in the FP32 form.  Workgroup tile 64 x
+// 64, 4 waves of 2 x 2 blocks of 16 x 16.  Fragments (li = lane % 16, lg =
+// lane / 16): A[li][8 lg + j], B[8 lg + j][li], j < 8; result D[4 lg + v][li]
+// (the lane layout was checked on the GPU with a probe).
+typedef _Float16 lr_h8 __attribute__((ext_vector_type(8)));
+constexpr int F16_BM = 64, F16_BN = 64, F16_NT = 256;
+constexpr int F16_LD = kF16Blk + 8;  // LDS row stride in halves: 80 bytes, 16-byte aligned fragments
+static_assert(kF16Blk == 32, "one v_mfma_f32_16x16x32_f16 per block and plane pair");
+
+// exponent of a block row: the 32 lanes of a row are adjacent (a 5-step
+// butterfly inside each half of the wave)
+__device__ inline int f16_block_exp(double mx) {
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) mx = fmax(mx, __shfl_xor(mx, s, 64));
+  return mx > 0.0 ? ilogb(mx) - 14 : 0;
+}
+
+// the scaled value is rounded to FP32 first (24 bits, of which hi + lo keep
+// 22): the hardware converts FP32 to FP16 in one instruction, FP64 to FP16 only
+// through a long integer sequence
+__device__ inline void f16_split_store(double re, double im, int e, uint16_t *row, int l) {
+  _Float16 *h = reinterpret_cast<_Float16 *>(row);
+  const float xr = (float)ldexp(re, -e), xi = (float)ldexp(im, -e);
+  const _Float16 hr = (_Float16)xr, hm = (_Float16)xi;
+  h[l] = hr;
+  h[32 + l] = (_Float16)(xr - (float)hr);
+  h[64 + l] = hm;
+  h[96 + l] = (_Float16)(xi - (float)hm);
+}
+
+// A[P][q] (FP64 complex, row stride lda) -> Xa[b][P][4][32], Ea[b][P]; one
+// thread per (P, q) of the padded grid, 32-lane groups along q
+__global__ __launch_bounds__(256) void asplit_kernel(const double *__restrict__ A, int64_t lda, int naux, int nq,
+                                                     int nb, uint16_t *__restrict__ Xa, int32_t *__restrict__ Ea) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = (int)(gid & 31);
+  const int64_t t = gid >> 5;
+  const int b = (int)(t % nb);
+  const int64_t P = t / nb;
+  const int q = b * kF16Blk + l;
+  double re = 0.0, im = 0.0;
+  if (P < naux && q < nq) {
+    const int64_t o = P * lda + q;
+    re = A[2 * o];
+    im = A[2 * o + 1];
+  }
+  const int e = f16_block_exp(fmax(fabs(re), fabs(im)));
+  if (P < naux) {
+    f16_split_store(re, im, e, Xa + ((int64_t)b * naux + P) * 4 * kF16Blk, l);
+    if (l == 0) Ea[(int64_t)b * naux + P] = e;
+  }
+}
+
+hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, uint16_t *Xa, int32_t *Ea,
+                         hipStream_t stream) {
+  if (nq <= 0 || naux <= 0) return hipSuccess;
+  const int nb = (nq + kF16Blk - 1) / kF16Blk;
+  const int64_t n = (int64_t)naux * nb * kF16Blk;
+  hipLaunchKernelGGL(asplit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, A, lda, naux, nq, nb,
+                     Xa, Ea);
+  return hipGetLastError();
+}
+
+// kphase_kernel's Bloch sums written in the split format: Xb[kpi][b][mn][4][32],
+// Eb[kpi][b][mn], and the first nq_hi columns in FP64 into Bhi[kpi][mn][nq_hi].
+// One thread per (mn, q) of the padded grid, 32-lane groups along q.
+template <int KB>
+__global__ __launch_bounds__(256) void kphase_split_kernel(const double *__restrict__ I,
+                                                           const double *__restrict__ phase,
+                                                           uint16_t *__restrict__ Xb, int32_t *__restrict__ Eb,
+                                                           double *__restrict__ Bhi, int nq_hi, int nk, int nkpi,
+                                                           int nq, int nb, int64_t nmn) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = (int)(gid & 31);
+  const int64_t t = gid >> 5;
+  const int b = (int)(t % nb);
+  const int64_t mn = t / nb;
+  const int q = b * kF16Blk + l;
+  const bool row = mn < nmn, ok = row && q < nq;
+  const int64_t ne = (int64_t)nq * nmn, src = mn * nq + q;
+  for (int k0 = 0; k0 < nkpi; k0 += KB) {
+    double sr[KB], si[KB];
+    kphase_sums<KB>(I, ne, src, ok, phase, nk, k0, nkpi, sr, si);
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk)
+      if (k0 + kk < nkpi) {  // uniform over the wave
+        const int k = k0 + kk;
+        const int e = f16_block_exp(fmax(fabs(sr[kk]), fabs(si[kk])));
+        if (row) {
+          const int64_t rb = ((int64_t)k * nb + b) * nmn + mn;
+          f16_split_store(sr[kk], si[kk], e, Xb + rb * 4 * kF16Blk, l);
+          if (l == 0) Eb[rb] = e;
+        }
+        if (Bhi && ok && q < nq_hi) {
+          const int64_t oh = ((int64_t)k * nmn + mn) * nq_hi + q;
+          Bhi[2 * oh] = sr[kk];
+          Bhi[2 * oh + 1] = si[kk];
+        }
+      }
+  }
+}
+
+hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *Xb, int32_t *Eb, double *Bhi,
+                               int nq_hi, int nk, int nkpi, int nq, int64_t nmn, hipStream_t stream) {
+  if (nq <= 0 || nmn <= 0 || nkpi <= 0) return hipSuccess;
+  const int nb = (nq + kF16Blk - 1) / kF16Blk;
+  const int64_t n = nmn * nb * kF16Blk;
+  const dim3 grid((unsigned)((n + 255) / 256));
+#define KPH_SPLIT(kb) kphase_split_kernel<kb>
+  KPH_DISPATCH(KPH_SPLIT, I, phase, Xb, Eb, Bhi, nq_hi, nk, nkpi, nq, nb, nmn)
+#undef KPH_SPLIT
+  return hipGetLastError();
+}
+#undef KPH_DISPATCH
+
+// LDS stage of one block: the A and B tiles (64 rows x 256 bytes each, row r's
+// 16-byte chunk c = 4 plane + part stored at chunk position c ^ (r % 16), so
+// that the 16 rows a fragment read touches fall in distinct banks), then the
+// 64 + 64 block exponents.  The tiles are filled by global_load_lds_dwordx4:
+// one instruction writes 1 KB of LDS, lane l's 16 bytes at offset 16 l, so the
+// lane that fills slot u fetches the global chunk that belongs there.
+constexpr int F16_TILE = F16_BM * 4 * kF16Blk * 2;      // 16384 bytes
+constexpr int F16_STAGE = 2 * F16_TILE + 2 * 64 * 4;    // + exponents
+#ifndef RSGDF_F16_STAGES
+#define RSGDF_F16_STAGES 2  // 2: two workgroups per CU (66 KB of LDS each); 3: one, and
+                            // slower (measured on the 8-atom 3x3x3 workload, 1.90 s vs 2.65 s)
+#endif
+constexpr int F16_NS = RSGDF_F16_STAGES;                // stages in flight
+static_assert(F16_NS == 2 || F16_NS == 3, "the waits below cover two or three stages");
+
+// s_waitcnt with vmcnt <= n (expcnt and lgkmcnt not waited on), gfx9 encoding
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// s_waitcnt lgkmcnt(0) alone (this wave's LDS reads returned)
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
+// workgroup barrier without a memory fence; the empty asm statements keep the
+// compiler from moving memory accesses across it (the waits are explicit)
+__device__ __forceinline__ void bare_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__global__ __launch_bounds__(F16_NT) void lr_gemm_f16x3_kernel(const LRGemmParams gp, int q_lo) {
+  __shared__ __attribute__((aligned(16))) unsigned char S[F16_NS][F16_STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int kpi = blockIdx.z;
+  // XCD-aware tile order as in lr_gemm_tiled_kernel
+  const int mt = (gp.naux + F16_BM - 1) / F16_BM, ntile = mt * ((gp.nmn + F16_BN - 1) / F16_BN);
+  const int per = (ntile + 7) / 8;
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= ntile) return;
+  const int M0 = (t % mt) * F16_BM, N0 = (t / mt) * F16_BN;
+  const unsigned char *Xa8 = reinterpret_cast<const unsigned char *>(gp.Xa);
+  const unsigned char *Xb8 =
+      reinterpret_cast<const unsigned char *>(gp.Xb) + (size_t)kpi * gp.nb * gp.nmn * 4 * kF16Blk * 2;
+  const int32_t *Ebk = gp.Eb + (size_t)kpi * gp.nb * gp.nmn;
+  // slots u = (4 j + wave) 64 + lane, j < 4, of each tile: row u / 16, chunk
+  // (u % 16) ^ (row % 16); rows past the end are clamped to the last row
+  // (their results are not stored)
+  int64_t ga_off[4], gb_off[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int u = (4 * j + wave) * 64 + lane, r = u >> 4, c = (u & 15) ^ (r & 15);
+    ga_off[j] = (int64_t)min(M0 + r, gp.naux - 1) * 256 + 16 * c;
+    gb_off[j] = (int64_t)min(N0 + r, gp.nmn - 1) * 256 + 16 * c;
+  }
+  const int e_row = (wave == 0) ? min(M0 + lane, gp.naux - 1) : min(N0 + lane, gp.nmn - 1);
+  // loads of block b into stage st: 8 per wave, 9 for waves 0 and 1 (exponents)
+  auto issue = [&](int b, int st) {
+    const unsigned char *xa = Xa8 + (size_t)b * gp.naux * 256, *xb = Xb8 + (size_t)b * gp.nmn * 256;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      __builtin_amdgcn_global_load_lds(xa + ga_off[j], &S[st][(4 * j + wave) * 1024], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(xb + gb_off[j], &S[st][F16_TILE + (4 * j + wave) * 1024], 16, 0, 0);
+    }
+    if (wave == 0) __builtin_amdgcn_global_load_lds(gp.Ea + (size_t)b * gp.naux + e_row, &S[st][2 * F16_TILE], 4, 0, 0);
+    if (wave == 1)
+      __builtin_amdgcn_global_load_lds(Ebk + (size_t)b * gp.nmn + e_row, &S[st][2 * F16_TILE + 256], 4, 0, 0);
+  };
+
+  lr_f4 cre[2][2], cim[2][2];
+  double hre[2][2][4], him[2][2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cre[r][c][v] = cim[r][c][v] = 0.f;
+        hre[r][c][v] = him[r][c][v] = 0.0;
+      }
+  // blocks after the FP64 columns (nq_hi is a multiple of the block; when the
+  // launch is shorter than nq_hi there are none)
+  const int khi = gp.nq_hi < gp.nq ? gp.nq_hi : gp.nq;
+  const int b0 = (max(khi, q_lo) + kF16Blk - 1) / kF16Blk;
+  // the first stages' loads in flight during the FP64 columns
+#pragma unroll
+  for (int i = 0; i < F16_NS - 1; ++i)
+    if (b0 + i < gp.nb) issue(b0 + i, i);
+  // the innermost q in FP64 on the vector ALUs (rows in the f32 fragment order)
+  for (int k = q_lo; k < khi; ++k) {
+    double br[2], bi[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int n = N0 + wn * 32 + c * 16 + li;
+      const size_t o = ((size_t)kpi * gp.nmn + n) * gp.nq_hi + k;
+      br[c] = (n < gp.nmn) ? gp.Bhi[2 * o] : 0.0;
+      bi[c] = (n < gp.nmn) ? gp.Bhi[2 * o + 1] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
+        const size_t o = (size_t)m * gp.lda + k;
+        const double ar = (m < gp.naux) ? gp.A[2 * o] : 0.0, ai = (m < gp.naux) ? gp.A[2 * o + 1] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          hre[r][c][v] += ar * br[c] - ai * bi[c];
+          him[r][c][v] += ar * bi[c] + ai * br[c];
+        }
+      }
+  }
+  const int lpb = (wave < 2) ? 9 : 8;  // loads per block of this wave
+  int st = 0;
+  for (int b = b0; b < gp.nb; ++b) {
+    // stage of block b + NS - 1 was consumed in the previous iteration (barrier below)
+    const bool more = b + F16_NS - 1 < gp.nb;
+    if (more) issue(b + F16_NS - 1, (st + F16_NS - 1) % F16_NS);
+    // block b complete for this wave: the loads issued after it may stay outstanding
+    const int after = min(F16_NS - 1, gp.nb - 1 - b);
+    if (after == 2) {
+      if (lpb == 9) wait_vmcnt<18>();
+      else wait_vmcnt<16>();
+    } else if (after == 1) {
+      if (lpb == 9) wait_vmcnt<9>();
+      else wait_vmcnt<8>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    // every wave's part of block b in LDS (a bare barrier: a fence here would
+    // also wait for the later blocks' loads)
+    bare_barrier();
+    const unsigned char *SA = S[st], *SB = S[st] + F16_TILE;
+    const int *SE = reinterpret_cast<const int *>(S[st] + 2 * F16_TILE);
+    lr_h8 a[2][4], an[2][2], bf[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int row = wm * 32 + r * 16 + li;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        a[r][pl] = *reinterpret_cast<const lr_h8 *>(SA + row * 256 + (((4 * pl + lg) ^ li) << 4));
+      an[r][0] = -a[r][2];
+      an[r][1] = -a[r][3];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int row = wn * 32 + c * 16 + li;
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl)
+        bf[c][pl] = *reinterpret_cast<const lr_h8 *>(SB + row * 256 + (((4 * pl + lg) ^ li) << 4));
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        lr_f4 x = cre[r][c], y = cim[r][c];
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][0], bf[c][0], x, 0, 0, 0);  // re_a re_b
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][0], bf[c][1], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][1], bf[c][0], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(an[r][0], bf[c][2], x, 0, 0, 0);  // - im_a im_b
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(an[r][0], bf[c][3], x, 0, 0, 0);
+        x = __builtin_amdgcn_mfma_f32_16x16x32_f16(an[r][1], bf[c][2], x, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][0], bf[c][2], y, 0, 0, 0);  // re_a im_b
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][0], bf[c][3], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][1], bf[c][2], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][2], bf[c][0], y, 0, 0, 0);  // im_a re_b
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][2], bf[c][1], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[r][3], bf[c][0], y, 0, 0, 0);
+        cre[r][c] = x;
+        cim[r][c] = y;
+      }
+    // scale back by 2^(e_m + e_n) and promote to FP64
+    int ea[2][4], eb[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ea[r][v] = SE[wm * 32 + r * 16 + 4 * lg + v];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) eb[c] = SE[64 + wn * 32 + c * 16 + li];
+    wait_lgkm0();    // this wave's reads of stage st returned
+    bare_barrier();  // every wave's: the next iteration refills it
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double sc = ldexp(1.0, ea[r][v] + eb[c]);
+          hre[r][c][v] = fma((double)cre[r][c][v], sc, hre[r][c][v]);
+          him[r][c][v] = fma((double)cim[r][c][v], sc, him[r][c][v]);
+          cre[r][c][v] = 0.f;
+          cim[r][c][v] = 0.f;
+        }
+    st = (st + 1 == F16_NS) ? 0 : st + 1;
+  }
+  const size_t kp = gp.kp_of[kpi];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
+        const int n = N0 + wn * 32 + c * 16 + li;
+        if (m < gp.naux && n < gp.nmn) {
+          const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
+          gp.out[2 * o] += hre[r][c][v];
+          gp.out[2 * o + 1] += him[r][c][v];
+        }
+      }
+}
+
 hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream) {
   if (q_lo >= gp.nq) return hipSuccess;
   const int bm = tg_bm(mode);
@@ -785,7 +1095,13 @@ hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int 
   dim3 grid((unsigned)(8 * ((ntile + 7) / 8)), 1, nkpi);
   if (mode == 0) hipLaunchKernelGGL(lr_gemm_tiled_kernel<0>, grid, dim3(tg_threads(0)), 0, stream, gp, q_lo);
   else if (mode == 1) hipLaunchKernelGGL(lr_gemm_tiled_kernel<1>, grid, dim3(tg_threads(1)), 0, stream, gp, q_lo);
-  else hipLaunchKernelGGL(lr_gemm_tiled_kernel<2>, grid, dim3(tg_threads(2)), 0, stream, gp, q_lo);
+  else {
+    // the split format's blocks start at q = 0 and the FP64 columns end on a block boundary
+    if (q_lo != 0 || gp.nq_hi % kF16Blk != 0 || gp.nb != (gp.nq + kF16Blk - 1) / kF16Blk || !gp.Xa || !gp.Xb ||
+        !gp.Ea || !gp.Eb)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lr_gemm_f16x3_kernel, grid, dim3(F16_NT), 0, stream, gp, q_lo);
+  }
   return hipGetLastError();
 }
 

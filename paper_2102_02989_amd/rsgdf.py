@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(_HERE, "librsgdf.so")
 
 RSGDF_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ESIZE", -3: "ENOMEM", -4: "EHIP", -5: "EUNSUPPORTED"}
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, F16X3 = 0, 1, 2
 SCREEN_RIGOROUS, SCREEN_LEARNED = 0, 1
 PART_SR, PART_G0, PART_LR = 1, 2, 4
 PART_ALL = 7

@@ -1,4 +1,4 @@
-"""Reduced-precision G-space contraction (FP32 and split-BF16x3 operands on the
+"""Reduced-precision G-space contraction (FP32 and split-FP16x3 operands on the
 matrix cores, FP32 accumulation) against the FP64 oracle; the pair and aux
 transforms, the kernel weight and the Bloch sums stay FP64 in every form.
 Bar: <= 1e-8 au for the FP64 form, <= 1e-6 au for the reduced forms."""
@@ -13,7 +13,7 @@ from gpu_util import max_err, run_gpu
 
 pytestmark = pytest.mark.gpu
 
-FORMS = {"fp64": (0, 1e-8), "fp32": (1, 1e-6), "bf16x3": (2, 1e-6)}
+FORMS = {"fp64": (0, 1e-8), "fp32": (1, 1e-6), "f16x3": (2, 1e-6)}
 
 
 def _say(*a):
@@ -35,7 +35,7 @@ def test_lr_forms_tiny(form):
     assert err <= tol
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("form", ["fp32", "f16x3"])
 def test_lr_forms_tiny_full(form):
     """Whole j3c (SR - G0 + LR) in the reduced forms, same tiny cell."""
     prec, tol = FORMS[form]
