@@ -105,19 +105,6 @@ __device__ __forceinline__ void hermite_R_acc(double X, double Y, double Z, cons
   }
 }
 
-// Static FP64 operation count of the recursion of hermite_R_acc<L> (one multiply or add = 1).
-__host__ __device__ constexpr int hermite_R_flops(int L) {
-  int f = 0;
-  for (int n = L - 1; n >= 0; --n)
-    for (int s = L - n; s >= 1; --s)
-      for (int t = s; t >= 0; --t)
-        for (int u = s - t; u >= 0; --u) {
-          const int v = s - t - u;
-          int k = (t > 0) ? t : (u > 0 ? u : v);
-          f += (k > 1) ? 3 : 1;
-        }
-  return f;
-}
 
 // McMurchie-Davidson expansion coefficients of a 1-D Gaussian product
 // (x-A)^i (x-B)^j exp(...) = K sum_t E[i][j][t] Lambda_t:

@@ -123,9 +123,6 @@ struct J2Params {
   int32_t naux, pad;
 };
 
-int pair_class(int la, int lb);
-int sr_term_flops(int L);
-int sr_cells_per_wave(int nblk);
 hipError_t launch_sr3c(int lP, int pc, const SRParams *prms, const SRWork *works, long long *counts, int w0,
                        int nwork, hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);

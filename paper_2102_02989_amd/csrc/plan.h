@@ -31,6 +31,44 @@ __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 __host__ __device__ inline double pair_growth_c(double beta) { return sqrt(2.0 * beta); }
 __host__ __device__ constexpr int nherm(int l) { return (l + 1) * (l + 2) * (l + 3) / 6; }
 
+// Work layout of the short-range kernels, shared with the planner's work split.
+constexpr int kBlkCap = 1024;        // doubles of per-group Cartesian accumulators in LDS
+constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
+// cells per wave for which the Cartesian accumulators of a class fit in LDS
+__host__ __device__ constexpr int sr_max_cells(int nblk) {
+  return (kBlkCap / nblk) < 1 ? 1 : ((kBlkCap / nblk) > kMaxCellsPerWave ? kMaxCellsPerWave : kBlkCap / nblk);
+}
+inline int sr_cells_per_wave(int nblk) { return sr_max_cells(nblk); }
+// AO pair class of (l_a, l_b), l_a >= l_b: 0 ss, 1 ps, 2 pp, 3 ds, 4 dp, 5 dd
+inline int pair_class(int la, int lb) {
+  static const int t[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
+  return t[la][lb];
+}
+
+// Static FP64 operation count of the recursion of hermite_R_acc<L> (one multiply or add = 1).
+__host__ __device__ constexpr int hermite_R_flops(int L) {
+  int f = 0;
+  for (int n = L - 1; n >= 0; --n)
+    for (int s = L - n; s >= 1; --s)
+      for (int t = s; t >= 0; --t)
+        for (int u = s - t; u >= 0; --u) {
+          const int v = s - t - u;
+          int k = (t > 0) ? t : (u > 0 ? u : v);
+          f += (k > 1) ? 3 : 1;
+        }
+  return f;
+}
+
+// Static per-term FP64 operation count of the image loop for class L:
+// position and T (13) + attenuated Boys values (two degree-12 polynomials,
+// two downward recursions, theta scaling) + (-2 rho)^n scaling (2L) +
+// Hermite recursion + image accumulation (nherm(L)).  An exp counts as one.
+inline int sr_term_flops(int L) {
+  const int geo = 13;
+  const int boys = 2 * (2 * kBoysPolyDeg + 3 * L + 1) + 3 * (L + 1);
+  return geo + boys + 2 * L + hermite_R_flops(L) + nherm(L);
+}
+
 // Packed shell (AO or aux).  a_d, c_d: exponent and 1s-equivalent amplitude
 // of the most diffuse primitive (used by the screening bounds, which treat
 // every function as 1s and a contracted shell by its most diffuse primitive).

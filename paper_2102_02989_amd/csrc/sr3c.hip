@@ -38,9 +38,7 @@
 namespace rsgdf {
 
 constexpr int kCandCap = 1536;    // lattice-vector candidates held in LDS per wave
-constexpr int kBlkCap = 1024;     // doubles of per-group Cartesian accumulators in LDS
 constexpr int kSRWinCap = 256;    // screening windows held in LDS
-constexpr int kMaxCellsPerWave = 8;  // BvK cells (lane groups) per wave
 constexpr int kTripCap = 40;         // primitive triples whose constants are held in LDS
 constexpr int kTripC = 9;            // constants per primitive triple
 
@@ -80,11 +78,6 @@ __device__ __forceinline__ void triple_consts(double ga, double gb, double gc, d
   }
 }
 
-// cells per wave for which the Cartesian accumulators of a class fit in LDS
-__host__ __device__ constexpr int sr_max_cells(int nblk) {
-  return (kBlkCap / nblk) < 1 ? 1 : ((kBlkCap / nblk) > kMaxCellsPerWave ? kMaxCellsPerWave : kBlkCap / nblk);
-}
-int sr_cells_per_wave(int nblk) { return sr_max_cells(nblk); }
 
 // (t,u,v) of Hermite index h (inverse of hidx)
 __device__ __forceinline__ void herm_decode(int h, int &t, int &u, int &v) {
@@ -725,15 +718,6 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
   }
 }
 
-// Static per-term FP64 operation count of the image loop for class L:
-// position and T (13) + attenuated Boys values (two degree-12 polynomials,
-// two downward recursions, theta scaling) + (-2 rho)^n scaling (2L) +
-// Hermite recursion + image accumulation (nherm(L)).  An exp counts as one.
-int sr_term_flops(int L) {
-  const int geo = 13;
-  const int boys = 2 * (2 * kBoysPolyDeg + 3 * L + 1) + 3 * (L + 1);
-  return geo + boys + 2 * L + hermite_R_flops(L) + nherm(L);
-}
 
 // Sum the partial blocks of split work items (slice order) into X, direct and
 // transposed entries.  One thread per element of a (work item, cell range).
@@ -790,11 +774,6 @@ static const sr_kernel_t kSRTable[4][6] = {
 };
 
 // pair class index of (la, lb) with la >= lb
-int pair_class(int la, int lb) {
-  static const int t[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
-  return t[la][lb];
-}
-
 hipError_t launch_sr3c(int lP, int pc, const SRParams *prms, const SRWork *works, long long *counts, int w0,
                        int nwork, hipStream_t stream) {
   if (nwork <= 0) return hipSuccess;
