@@ -271,21 +271,24 @@ def main():
     t_sr = sum(s["t_sr_ms"] for s in stats) / len(stats)
     t_gemm = sum(s["t_lr_gemm_ms"] for s in stats) / len(stats)
     lr_name = args.lr if head == "chosen" else "fp64"
-    if t_gemm > t_sr:
-        flops = stats[-1]["lr_gemm_flops"]
-        achieved = flops / (t_gemm * 1e-3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[lr_name] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK[lr_name], "traffic": recorded_traffic("lr_gemm", problem.name),
-                "kernel": f"lr_gemm_tiled_kernel ({lr_name} complex G-space contraction, all k12 classes of one "
-                          f"build; flops = 8 per complex multiply-add)",
-                "flops_per_launch": flops, "avg_launch_ms": t_gemm}
-    else:
-        flops = stats[-1]["sr_flops"]
-        achieved = flops / (t_sr * 1e-3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VECTOR, "traffic": recorded_traffic("sr", problem.name),
-                "kernel": "sr3c_kernel (the 24 angular-momentum classes of one build, on 3 side streams)",
-                "flops_per_launch": flops, "avg_launch_ms": t_sr}
+    flops = stats[-1]["lr_gemm_flops"]
+    achieved = flops / (t_gemm * 1e-3) if t_gemm > 0 else 0.0
+    roof_gemm = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[lr_name] / 1e12, "unit": "TFLOP/s",
+                 "frac": achieved / PEAK[lr_name], "traffic": recorded_traffic("lr_gemm", problem.name),
+                 "kernel": (f"{'lr_gemm_f16x3_kernel' if lr_name == 'f16x3' else 'lr_gemm_tiled_kernel'} "
+                            f"({lr_name} complex G-space contraction, all k12 classes of one build; flops = 8 per "
+                            f"complex multiply-add" + (", the form issues 24 FP16 flops per complex multiply-add"
+                                                       if lr_name == "f16x3" else "") + ")"),
+                 "flops_per_launch": flops, "avg_launch_ms": t_gemm}
+    flops = stats[-1]["sr_flops"]
+    achieved = flops / (t_sr * 1e-3) if t_sr > 0 else 0.0
+    roof_sr = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
+               "frac": achieved / PEAK_FP64_VECTOR, "traffic": recorded_traffic("sr", problem.name),
+               "kernel": "sr3c_kernel (the 24 angular-momentum classes of one build, on 3 side streams; flops = "
+                         "image-loop terms plus the Hermite contractions)",
+               "flops_per_launch": flops, "avg_launch_ms": t_sr}
+    # the dominant kernel family by time; the other one is reported beside it
+    roof, roof2 = (roof_gemm, roof_sr) if t_gemm > t_sr else (roof_sr, roof_gemm)
     cfg = {"workload": describe(problem, shape[0]), "form": head,
            "chosen": {"lr_precision": args.lr, "screening": "learned", "mlp_margin": margin,
                       "mlp_margin_rule": "largest under-prediction on the held-out 20% of the training samples",
@@ -315,6 +318,7 @@ def main():
         "counts": {k: stats[-1][k] for k in ("n_sr_terms", "n_sr_shell_terms", "n_lr_terms", "n_g_total",
                                              "n_triplets", "n_screen_candidates", "n_screen_skipped")},
         "roofline": roof,
+        "roofline_second": roof2,
         "cpu_baseline": None,
     }
     del out_chosen, out_plain

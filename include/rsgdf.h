@@ -130,7 +130,10 @@ typedef struct rsgdf_stats {
   int64_t n_triplets;    /* (aux shell, AO shell pair) work items                           */
   int64_t n_aux_batches; /* aux-shell batches used to bound scratch memory                  */
   int64_t bytes_out;     /* output bytes written                                            */
-  double sr_flops;       /* algorithmic FP64 operations of the SR kernels (static counts)   */
+  double sr_flops;       /* algorithmic FP64 operations of the SR kernels (static counts):  the
+                            image loop's per-term count times the evaluated terms, plus the
+                            Hermite contraction's count per (pair image, primitive triple, BvK
+                            cell group) times the contractions performed                    */
   double t_lr_gemm_ms;   /* G-space contraction kernels alone                               */
   int64_t n_screen_candidates; /* (aux shell, AO pair, pair image) candidates (learned mode) */
   int64_t n_screen_skipped;    /* candidates the network dropped                            */

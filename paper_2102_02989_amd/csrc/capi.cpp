@@ -1692,13 +1692,14 @@ int Job::finish(hipStream_t st, const long long *cnt_host) {
           const int lP = g / 6, pc = g % 6;
           static const int la_of[6] = {0, 1, 1, 2, 2, 2}, lb_of[6] = {0, 0, 1, 0, 1, 2};
           const int Lt = lP + la_of[pc] + lb_of[pc];
-          long long nt = 0;
+          long long nt = 0, nc = 0;
           for (int t = tgrp_off[(size_t)b * 24 + g]; t < tgrp_off[(size_t)b * 24 + g + 1]; ++t) {
             nt += tterms[t];
+            nc += tcontr[t];
             s.n_sr_shell_terms += tshell[t];
           }
           s.n_sr_terms += nt;
-          flops += (double)nt * sr_term_flops(Lt);
+          flops += (double)nt * sr_term_flops(Lt) + (double)nc * sr_contr_flops(lP, la_of[pc], lb_of[pc]);
         }
       s.sr_flops = flops;
       // optional per-item dump (aux shell, pair, l_P, l_a, l_b, terms, contractions, shell terms,

@@ -69,6 +69,22 @@ inline int sr_term_flops(int L) {
   return geo + boys + 2 * L + hermite_R_flops(L) + nherm(L);
 }
 
+// Static FP64 operation count of the McMurchie-Davidson contraction of one
+// (pair image, primitive triple, BvK cell group): the aux pass
+// W[ic][tuv] = sum over the even aux Hermite orders of E^c_x E^c_y E^c_z R
+// (NW = ncart(lP) nherm(la + lb) entries, (KX + 1)^3 products each, KX =
+// lP / 2), then the pair pass, each Cartesian component (ncart of all three)
+// summing E^ab_x E^ab_y E^ab_z W over the nherm(la + lb) Hermite orders,
+// times the triple's prefactor.
+inline int sr_contr_flops(int lP, int la, int lb) {
+  const int lab = la + lb, kx = lP / 2 + 1;
+  const int nw = ncart(lP) * nherm(lab);
+  const int w = nw * (2 * kx * kx * kx + 3 * kx * kx);
+  const int nblk = ncart(lP) * ncart(la) * ncart(lb);
+  const int c = nblk * (2 * nherm(lab) + (lab + 1) * (lab + 2) + 2 * (lab + 1) + 1);
+  return w + c;
+}
+
 // Packed shell (AO or aux).  a_d, c_d: exponent and 1s-equivalent amplitude
 // of the most diffuse primitive (used by the screening bounds, which treat
 // every function as 1s and a contracted shell by its most diffuse primitive).

@@ -676,7 +676,7 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
               }
               }
               __syncthreads();
-              ++n_contr;
+              if (lane == 0) n_contr += __popcll(gnz);  // (image, triple, cell group) contractions
           }
         }
         // more candidates than one pass holds?
