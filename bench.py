@@ -44,14 +44,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VECTOR = 78.6e12  # 256 CU x 4 SIMD x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "f16x3": 2.5e15}  # dense matrix-core peaks per operand type
 LR_CHOICES = ("f16x3", "fp32", "fp64")
-TRAFFIC_FILES = {  # committed FETCH_SIZE / WRITE_SIZE summaries, keyed by kernel family
-    "sr": os.path.join(ROOT, "profiles", "sr3c_c2_traffic.json"),
-    "lr_gemm": os.path.join(ROOT, "profiles", "lr_gemm_c3_traffic.json"),
+TRAFFIC_FILES = {  # committed FETCH_SIZE / WRITE_SIZE summaries, by kernel family and workload
+    "sr": "sr3c_{}_traffic.json",
+    "lr_gemm": "lr_gemm_{}_traffic.json",
 }
 KERNEL_SOURCES = {
     "sr": ("paper_2102_02989_amd/csrc/sr3c.hip", "paper_2102_02989_amd/csrc/device_math.h",
-           "paper_2102_02989_amd/csrc/plan.h"),
-    "lr_gemm": ("paper_2102_02989_amd/csrc/lr.hip",),
+           "paper_2102_02989_amd/csrc/plan.h", "paper_2102_02989_amd/csrc/boys.h"),
+    "lr_gemm": ("paper_2102_02989_amd/csrc/lr.hip", "paper_2102_02989_amd/csrc/kernels.h"),
 }
 TABLE_S3 = ("paper Table S3 (J+K CPU time per SCF cycle including DF initialisation, one core of an Intel Xeon "
             "Gold 6126 at 2.6 GHz, 16 GB): diamond/cc-pVDZ N_k = 3^3: GDF 1441.77 s, RSGDF 205.25 s; "
@@ -72,7 +72,7 @@ def recorded_traffic(family, workload):
     the kernel sources changed since the counters were taken or they were
     taken on another workload."""
     try:
-        with open(TRAFFIC_FILES[family]) as fh:
+        with open(os.path.join(ROOT, "profiles", TRAFFIC_FILES[family].format(workload.lower()))) as fh:
             rec = json.load(fh)
     except (OSError, ValueError, KeyError):
         return None

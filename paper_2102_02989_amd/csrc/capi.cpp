@@ -1349,15 +1349,29 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     // the class's k-pairs (B), then the G-space contraction
     int max_kpi = 0;
     for (auto &v : cls_kp) max_kpi = std::max<int>(max_kpi, (int)v.size());
-    const double bbudget = std::min(0.5 * mem_frac * (double)free_b, 16e9);
-    qchunk = (int64_t)(bbudget / ((double)(nk + std::max(1, max_kpi)) * nao2 * 16.0));
+    // I and B per q chunk.  Every chunk's contraction reads and writes the
+    // class's output rows once more, so the chunks are long: a fixed 48 GB
+    // when half the memory share allows it (on the 3x3x3 workload 16 GB gave
+    // 16 chunks per class, 1.6 TB of output traffic per build), else the
+    // largest power of two of q that fits.  The chunk boundaries set the
+    // order in which the q sums are added, so they must not follow the free
+    // memory from call to call: this keeps builds bit-reproducible.
+    const double per_q = (double)(nk + std::max(1, max_kpi)) * nao2 * 16.0;
+    const double avail = 0.5 * mem_frac * (double)free_b, fixed = 48e9;
+    if (avail >= fixed) {
+      qchunk = (int64_t)(fixed / per_q);
+    } else {
+      const int64_t fit = (int64_t)(avail / per_q);
+      qchunk = 1;
+      while (qchunk * 2 <= fit) qchunk *= 2;
+    }
     qchunk = std::max<int64_t>(1, std::min<int64_t>(qchunk, 8192));
     int64_t max_nq = 0;
     for (auto &pt : lrp)
       for (int c = 0; c < nk; ++c) max_nq = std::max(max_nq, pt->qoff[c + 1] - pt->qoff[c]);
     qchunk = std::min(qchunk, std::max<int64_t>(max_nq, 1));
     if (o.lr_precision == RSGDF_F16X3)  // whole 32-q blocks per chunk (the split format's unit)
-      qchunk = std::max<int64_t>(kF16Blk, qchunk / kF16Blk * kF16Blk);
+      qchunk = std::max<int64_t>(kF16Blk * kF16Grp, qchunk / (kF16Blk * kF16Grp) * (kF16Blk * kF16Grp));
     HIPCHK(d_amax.alloc((size_t)qchunk * sizeof(double)));
     HIPCHK(d_I.alloc((size_t)nk * qchunk * nao2 * 2 * sizeof(double)));
     HIPCHK(d_B.alloc((size_t)max_kpi * qchunk * nao2 * 2 * sizeof(double)));
@@ -1562,13 +1576,14 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
         HIPCHK(launch_pairft_binned(pp, st));
         const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
         const bool split = o.lr_precision == RSGDF_F16X3;
-        const int nb = (nq + kF16Blk - 1) / kF16Blk;
+        const int nb = f16_nblk(nq);
         // split format: halves, then the exponents at a 256-byte boundary
         uint16_t *Xa = d_Asp.as<uint16_t>(), *Xb = d_B.as<uint16_t>();
         int32_t *Ea = reinterpret_cast<int32_t *>(d_Asp.as<char>() + f16_split_eoff(naux, nb));
         int32_t *Eb = reinterpret_cast<int32_t *>(d_B.as<char>() + f16_split_eoff((int64_t)nkpi * nao2, nb));
         if (split) {
-          HIPCHK(launch_asplit(pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0), pt.nq_tot, (int)naux, nq, Xa, Ea, st));
+          HIPCHK(launch_asplit(pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0), pt.nq_tot, (int)naux, nq, nq_hi, Xa, Ea,
+                               st));
           HIPCHK(launch_kphase_split(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, Xb, Eb,
                                      nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
         } else {

@@ -138,16 +138,22 @@ hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32
                          int nkpi, int nq, int64_t nmn, hipStream_t stream);
 hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t stream);
 // split FP16 operand formats of the mode-2 contraction (lr.hip)
-constexpr int kF16Blk = 32;  // q per block
+constexpr int kF16Blk = 32;  // q per block (one matrix-core K step)
+constexpr int kF16Grp = 2;   // blocks sharing one exponent (64 q: one wavefront of the producers)
 static_assert(kLrNqHi % kF16Blk == 0, "the FP64 columns end on a split block boundary");
+// blocks of the split format of nq columns: whole exponent groups (zero padded)
+inline int f16_nblk(int64_t nq) {
+  return (int)((nq + kF16Blk * kF16Grp - 1) / (kF16Blk * kF16Grp) * kF16Grp);
+}
 // byte offset of the exponents [nb][rows] behind the halves [nb][rows][4][32]
 inline int64_t f16_split_eoff(int64_t rows, int64_t nb) { return (rows * nb * 4 * kF16Blk * 2 + 255) / 256 * 256; }
-// bytes of the split format of rows x nq (nq a multiple of the block)
+// bytes of the split format of rows x nq
 inline int64_t f16_split_bytes(int64_t rows, int64_t nq) {
-  const int64_t nb = (nq + kF16Blk - 1) / kF16Blk;
+  const int64_t nb = f16_nblk(nq);
   return f16_split_eoff(rows, nb) + rows * nb * 4;
 }
-hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, uint16_t *Xa, int32_t *Ea,
+// q_excl: columns q < q_excl (contracted in FP64) do not enter the exponents
+hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, int q_excl, uint16_t *Xa, int32_t *Ea,
                          hipStream_t stream);
 hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *Xb, int32_t *Eb, double *Bhi,
                                int nq_hi, int nk, int nkpi, int nq, int64_t nmn, hipStream_t stream);

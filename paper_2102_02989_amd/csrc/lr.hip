@@ -742,21 +742,23 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
 }
 
 // ---- split-FP16 contraction (mode 2) ------------------------------------------
-// Operand format.  The q range of a launch is cut into blocks of 32 q.  In a
-// block every operand row (an aux function of A; a pair column of one k-pair's
-// B) is scaled by 2^-e, e chosen so that the row's largest |re|, |im| in the
-// block lies in [2^14, 2^15) (e = 0 for a zero row), and each scaled value x'
-// is split x' = hi + lo with hi = fp16(x'), lo = fp16(x' - hi): 22 significant
-// bits, always inside the FP16 range.  Storage per (block, row): 256 bytes, the
-// planes re_hi, re_lo, im_hi, im_lo of 32 halves, and the exponent e as an int;
-// q past the end of the launch are zero.  The producers write this format
+// Operand format.  The q range of a launch is cut into blocks of 32 q, and the
+// blocks into exponent groups of kF16Grp = 2 blocks (64 q).  In a group every
+// operand row (an aux function of A; a pair column of one k-pair's B) is
+// scaled by 2^-e, e chosen so that the row's largest |re|, |im| in the group
+// (over q >= q_excl: the columns contracted in FP64 do not count) lies in
+// [2^14, 2^15) (e = 0 for a zero row), and each scaled value x' is split
+// x' = hi + lo with hi = fp16(x'), lo = fp16(x' - hi): 22 significant bits,
+// always inside the FP16 range.  Storage per (block, row): 256 bytes, the
+// planes re_hi, re_lo, im_hi, im_lo of 32 halves, and the group's exponent e
+// as an int; q past the end of the launch are zero (whole groups are stored).  The producers write this format
 // from FP64 values (asplit_kernel from the aux transforms, kphase_split_kernel
 // from the Bloch sums), so the contraction only copies 16-byte pieces.
 //
 // Contraction: a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (the dropped lo_a lo_b
 // is 2^-22 of the product) on v_mfma_f32_16x16x32_f16, FP32 accumulation over
-// one block; after each block the FP32 sums are scaled back by 2^(e_m + e_n)
-// (exact) and added to FP64 registers.  The first nq_hi q of the class are
+// one exponent group; after each group the FP32 sums are scaled back by
+// 2^(e_m + e_n) (exact) and added to FP64 registers.  The first nq_hi q of the class are
 // taken in FP64 on the vector ALUs as in the FP32 form.  Workgroup tile 64 x
 // 64, 4 waves of 2 x 2 blocks of 16 x 16.  Fragments (li = lane % 16, lg =
 // lane / 16): A[li][8 lg + j], B[8 lg + j][li], j < 8; result D[4 lg + v][li]
@@ -766,11 +768,12 @@ constexpr int F16_BM = 64, F16_BN = 64, F16_NT = 256;
 constexpr int F16_LD = kF16Blk + 8;  // LDS row stride in halves: 80 bytes, 16-byte aligned fragments
 static_assert(kF16Blk == 32, "one v_mfma_f32_16x16x32_f16 per block and plane pair");
 
-// exponent of a block row: the 32 lanes of a row are adjacent (a 5-step
-// butterfly inside each half of the wave)
-__device__ inline int f16_block_exp(double mx) {
+// exponent of a group row: the 64 q of a row's exponent group are the 64
+// lanes of one wavefront (a 6-step butterfly)
+static_assert(kF16Blk * kF16Grp == 64, "one wavefront per exponent group");
+__device__ inline int f16_group_exp(double mx) {
 #pragma unroll
-  for (int s = 16; s >= 1; s >>= 1) mx = fmax(mx, __shfl_xor(mx, s, 64));
+  for (int s = 32; s >= 1; s >>= 1) mx = fmax(mx, __shfl_xor(mx, s, 64));
   return mx > 0.0 ? ilogb(mx) - 14 : 0;
 }
 
@@ -788,9 +791,11 @@ __device__ inline void f16_split_store(double re, double im, int e, uint16_t *ro
 }
 
 // A[P][q] (FP64 complex, row stride lda) -> Xa[b][P][4][32], Ea[b][P]; one
-// thread per (P, q) of the padded grid, 32-lane groups along q
+// thread per (P, q) of the padded grid, 32-lane blocks along q (nb is a whole
+// number of groups, so a wavefront holds the two blocks of one row's group)
 __global__ __launch_bounds__(256) void asplit_kernel(const double *__restrict__ A, int64_t lda, int naux, int nq,
-                                                     int nb, uint16_t *__restrict__ Xa, int32_t *__restrict__ Ea) {
+                                                     int q_excl, int nb, uint16_t *__restrict__ Xa,
+                                                     int32_t *__restrict__ Ea) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int l = (int)(gid & 31);
   const int64_t t = gid >> 5;
@@ -803,26 +808,27 @@ __global__ __launch_bounds__(256) void asplit_kernel(const double *__restrict__ 
     re = A[2 * o];
     im = A[2 * o + 1];
   }
-  const int e = f16_block_exp(fmax(fabs(re), fabs(im)));
+  const int e = f16_group_exp(q >= q_excl ? fmax(fabs(re), fabs(im)) : 0.0);
   if (P < naux) {
     f16_split_store(re, im, e, Xa + ((int64_t)b * naux + P) * 4 * kF16Blk, l);
     if (l == 0) Ea[(int64_t)b * naux + P] = e;
   }
 }
 
-hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, uint16_t *Xa, int32_t *Ea,
+hipError_t launch_asplit(const double *A, int64_t lda, int naux, int nq, int q_excl, uint16_t *Xa, int32_t *Ea,
                          hipStream_t stream) {
   if (nq <= 0 || naux <= 0) return hipSuccess;
-  const int nb = (nq + kF16Blk - 1) / kF16Blk;
+  const int nb = f16_nblk(nq);
   const int64_t n = (int64_t)naux * nb * kF16Blk;
-  hipLaunchKernelGGL(asplit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, A, lda, naux, nq, nb,
-                     Xa, Ea);
+  hipLaunchKernelGGL(asplit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, A, lda, naux, nq,
+                     q_excl, nb, Xa, Ea);
   return hipGetLastError();
 }
 
 // kphase_kernel's Bloch sums written in the split format: Xb[kpi][b][mn][4][32],
-// Eb[kpi][b][mn], and the first nq_hi columns in FP64 into Bhi[kpi][mn][nq_hi].
-// One thread per (mn, q) of the padded grid, 32-lane groups along q.
+// Eb[kpi][b][mn], and the first nq_hi columns in FP64 into Bhi[kpi][mn][nq_hi]
+// (those columns do not enter the exponents).  One thread per (mn, q) of the
+// padded grid, 32-lane blocks along q, a wavefront per row's exponent group.
 template <int KB>
 __global__ __launch_bounds__(256) void kphase_split_kernel(const double *__restrict__ I,
                                                            const double *__restrict__ phase,
@@ -844,7 +850,7 @@ __global__ __launch_bounds__(256) void kphase_split_kernel(const double *__restr
     for (int kk = 0; kk < KB; ++kk)
       if (k0 + kk < nkpi) {  // uniform over the wave
         const int k = k0 + kk;
-        const int e = f16_block_exp(fmax(fabs(sr[kk]), fabs(si[kk])));
+        const int e = f16_group_exp(q >= nq_hi ? fmax(fabs(sr[kk]), fabs(si[kk])) : 0.0);
         if (row) {
           const int64_t rb = ((int64_t)k * nb + b) * nmn + mn;
           f16_split_store(sr[kk], si[kk], e, Xb + rb * 4 * kF16Blk, l);
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(256) void kphase_split_kernel(const double *__restr
 hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *Xb, int32_t *Eb, double *Bhi,
                                int nq_hi, int nk, int nkpi, int nq, int64_t nmn, hipStream_t stream) {
   if (nq <= 0 || nmn <= 0 || nkpi <= 0) return hipSuccess;
-  const int nb = (nq + kF16Blk - 1) / kF16Blk;
+  const int nb = f16_nblk(nq);
   const int64_t n = nmn * nb * kF16Blk;
   const dim3 grid((unsigned)((n + 255) / 256));
 #define KPH_SPLIT(kb) kphase_split_kernel<kb>
@@ -1045,28 +1051,34 @@ __global__ __launch_bounds__(F16_NT) void lr_gemm_f16x3_kernel(const LRGemmParam
         cre[r][c] = x;
         cim[r][c] = y;
       }
-    // scale back by 2^(e_m + e_n) and promote to FP64
+    // at the end of an exponent group: scale back by 2^(e_m + e_n) and promote
+    // to FP64 (the blocks of a group carry the same exponents)
+    const bool promote = (b % kF16Grp == kF16Grp - 1) || b + 1 == gp.nb;
     int ea[2][4], eb[2];
+    if (promote) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) ea[r][v] = SE[wm * 32 + r * 16 + 4 * lg + v];
+        for (int v = 0; v < 4; ++v) ea[r][v] = SE[wm * 32 + r * 16 + 4 * lg + v];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) eb[c] = SE[64 + wn * 32 + c * 16 + li];
+      for (int c = 0; c < 2; ++c) eb[c] = SE[64 + wn * 32 + c * 16 + li];
+    }
     wait_lgkm0();    // this wave's reads of stage st returned
     bare_barrier();  // every wave's: the next iteration refills it
+    if (promote) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double sc = ldexp(1.0, ea[r][v] + eb[c]);
-          hre[r][c][v] = fma((double)cre[r][c][v], sc, hre[r][c][v]);
-          him[r][c][v] = fma((double)cim[r][c][v], sc, him[r][c][v]);
-          cre[r][c][v] = 0.f;
-          cim[r][c][v] = 0.f;
-        }
+          for (int v = 0; v < 4; ++v) {
+            const double sc = ldexp(1.0, ea[r][v] + eb[c]);
+            hre[r][c][v] = fma((double)cre[r][c][v], sc, hre[r][c][v]);
+            him[r][c][v] = fma((double)cim[r][c][v], sc, him[r][c][v]);
+            cre[r][c][v] = 0.f;
+            cim[r][c][v] = 0.f;
+          }
+    }
     st = (st + 1 == F16_NS) ? 0 : st + 1;
   }
   const size_t kp = gp.kp_of[kpi];
@@ -1097,7 +1109,7 @@ hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int 
   else if (mode == 1) hipLaunchKernelGGL(lr_gemm_tiled_kernel<1>, grid, dim3(tg_threads(1)), 0, stream, gp, q_lo);
   else {
     // the split format's blocks start at q = 0 and the FP64 columns end on a block boundary
-    if (q_lo != 0 || gp.nq_hi % kF16Blk != 0 || gp.nb != (gp.nq + kF16Blk - 1) / kF16Blk || !gp.Xa || !gp.Xb ||
+    if (q_lo != 0 || gp.nq_hi % kF16Blk != 0 || gp.nb != f16_nblk(gp.nq) || !gp.Xa || !gp.Xb ||
         !gp.Ea || !gp.Eb)
       return hipErrorInvalidValue;
     hipLaunchKernelGGL(lr_gemm_f16x3_kernel, grid, dim3(F16_NT), 0, stream, gp, q_lo);

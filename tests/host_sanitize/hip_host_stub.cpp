@@ -121,7 +121,7 @@ hipError_t launch_kphase(const double *, const double *, void *, bool, double *,
                          hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_asplit(const double *, int64_t, int, int, uint16_t *, int32_t *, hipStream_t) { return hipSuccess; }
+hipError_t launch_asplit(const double *, int64_t, int, int, int, uint16_t *, int32_t *, hipStream_t) { return hipSuccess; }
 hipError_t launch_kphase_split(const double *, const double *, uint16_t *, int32_t *, double *, int, int, int, int,
                                int64_t, hipStream_t) {
   return hipSuccess;
