@@ -870,6 +870,7 @@ struct Job {
   double acut = 0.0;
   std::vector<std::vector<int>> cls_kp;
   std::vector<int64_t> kpl_off{0};
+  std::vector<int64_t> ph_off;  // per class: offset (complex) of its phase table
   DBuf d_I, d_B, d_kp, d_ph, d_nterm, d_amax, d_Bhi;
   DBuf d_Asp;  // split-FP16 aux operand of one chunk (F16X3 form)
   // results
@@ -1380,21 +1381,27 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     if (o.lr_precision == RSGDF_F16X3)  // halves [nb][naux][4][32], then exponents [nb][naux]
       HIPCHK(d_Asp.alloc(f16_split_bytes(naux, qchunk)));
     HIPCHK(d_kp.alloc((size_t)std::max(nkp, 1) * sizeof(int32_t)));
-    HIPCHK(d_ph.alloc((size_t)std::max(nkp, 1) * nk * 2 * sizeof(double)));
     HIPCHK(d_nterm.alloc(sizeof(long long)));
-    // k-pair lists and e^{+i k2.L_c} rows of every class
+    // k-pair lists and the phases e^{+i k2.L_c} of every class, as a table
+    // [cell c][k-pair of the class] with the k-pairs contiguous and padded with
+    // zeros to whole passes of the k2-phase kernels
     for (int c = 0; c < nk; ++c) {
-      for (int t : cls_kp[c]) {
-        kpl.push_back(t);
-        const int k2 = hp.kp2[t];
-        phl.insert(phl.end(), kph.begin() + 2 * (size_t)k2 * nk, kph.begin() + 2 * (size_t)(k2 + 1) * nk);
-      }
+      const int nkpi = (int)cls_kp[c].size(), kpad = kphase_kpad(std::max(nkpi, 1));
+      for (int t : cls_kp[c]) kpl.push_back(t);
       kpl_off.push_back((int64_t)kpl.size());
+      ph_off.push_back((int64_t)(phl.size() / 2));
+      for (int cell = 0; cell < nk; ++cell)
+        for (int k = 0; k < kpad; ++k) {
+          const int k2 = k < nkpi ? hp.kp2[cls_kp[c][k]] : -1;
+          phl.push_back(k2 >= 0 ? kph[2 * ((size_t)k2 * nk + cell)] : 0.0);
+          phl.push_back(k2 >= 0 ? kph[2 * ((size_t)k2 * nk + cell) + 1] : 0.0);
+        }
     }
-    if (!kpl.empty()) {
+    HIPCHK(d_ph.alloc(std::max<size_t>(phl.size(), 2) * sizeof(double)));
+    if (!kpl.empty())
       HIPCHK(hipMemcpyAsync(d_kp.p, kpl.data(), kpl.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!phl.empty())
       HIPCHK(hipMemcpyAsync(d_ph.p, phl.data(), phl.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    }
   }
   // uploads read host vectors that live in this object; make them complete
   HIPCHK(hipStreamSynchronize(st));
@@ -1584,10 +1591,10 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
         if (split) {
           HIPCHK(launch_asplit(pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0), pt.nq_tot, (int)naux, nq, nq_hi, Xa, Ea,
                                st));
-          HIPCHK(launch_kphase_split(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, Xb, Eb,
+          HIPCHK(launch_kphase_split(d_I.as<double>(), d_ph.as<double>() + 2 * ph_off[c], Xb, Eb,
                                      nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
         } else {
-          HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * kpl_off[c] * nk, d_B.p, f32,
+          HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * ph_off[c], d_B.p, f32,
                                nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
         }
         LRGemmParams gp{};

@@ -365,7 +365,7 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
   return hipGetLastError();
 }
 
-// B[kpi][mn][q] = sum_c phase[kpi][c] I[c][mn][q], phase = e^{+i k2.L_c}; one
+// B[kpi][mn][q] = sum_c phase[c][kpi] I[c][mn][q], phase = e^{+i k2.L_c}; one
 // thread per (mn, q) element.  The k-pairs of the class are taken KB at a time
 // with their sums in registers, KB chosen per launch so that one pass covers
 // up to 28 k-pairs and the passes are even (each pass reads I once); the
@@ -375,17 +375,10 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 // first nq_hi columns also in FP64 into Bhi[kpi][mn][nq_hi] (the columns the
 // reduced-precision forms contract in FP64).
 constexpr int KPH_CB = 3;
-constexpr int KPH_KBMAX = 28;
-// KB of a class with nkpi k-pairs: the pass width rounded up to 4
-inline int kphase_kb(int nkpi) {
-  const int npass = (nkpi + KPH_KBMAX - 1) / KPH_KBMAX;
-  const int per = (nkpi + npass - 1) / npass;
-  return (per + 3) / 4 * 4;
-}
 
 template <int KB>
 __device__ __forceinline__ void kphase_sums(const double *__restrict__ I, int64_t ne, int64_t src, bool ok,
-                                            const double *__restrict__ phase, int nk, int k0, int nkpi,
+                                            const double *__restrict__ phase, int nk, int kpad, int k0,
                                             double (&sr)[KB], double (&si)[KB]) {
 #pragma unroll
   for (int kk = 0; kk < KB; ++kk) sr[kk] = si[kk] = 0.0;
@@ -402,10 +395,11 @@ __device__ __forceinline__ void kphase_sums(const double *__restrict__ I, int64_
     for (int j = 0; j < KPH_CB; ++j) {
       if (c0 + j >= nk) break;
       const int c = c0 + j;
+      // the pass's KB phases of cell c are contiguous (zero past nkpi)
+      const double *ph = phase + 2 * ((int64_t)c * kpad + k0);
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
-        const int k = (k0 + kk < nkpi) ? k0 + kk : nkpi - 1;  // clamped: in-bounds, result unused
-        const double pr = phase[2 * (k * nk + c)], pi = phase[2 * (k * nk + c) + 1];
+        const double pr = ph[2 * kk], pi = ph[2 * kk + 1];
         sr[kk] += pr * ir[j] - pi * ii[j];
         si[kk] += pr * ii[j] + pi * ir[j];
       }
@@ -424,7 +418,7 @@ __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ 
   const int64_t mn = gid / nq;
   for (int k0 = 0; k0 < nkpi; k0 += KB) {
     double sr[KB], si[KB];
-    kphase_sums<KB>(I, ne, gid, true, phase, nk, k0, nkpi, sr, si);
+    kphase_sums<KB>(I, ne, gid, true, phase, nk, kphase_kpad(nkpi), k0, sr, si);
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk)
       if (k0 + kk < nkpi) {
@@ -843,9 +837,10 @@ __global__ __launch_bounds__(256) void kphase_split_kernel(const double *__restr
   const int q = b * kF16Blk + l;
   const bool row = mn < nmn, ok = row && q < nq;
   const int64_t ne = (int64_t)nq * nmn, src = mn * nq + q;
+  const int kpad = kphase_kpad(nkpi);
   for (int k0 = 0; k0 < nkpi; k0 += KB) {
     double sr[KB], si[KB];
-    kphase_sums<KB>(I, ne, src, ok, phase, nk, k0, nkpi, sr, si);
+    kphase_sums<KB>(I, ne, src, ok, phase, nk, kpad, k0, sr, si);
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk)
       if (k0 + kk < nkpi) {  // uniform over the wave
