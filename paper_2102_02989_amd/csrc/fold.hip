@@ -8,9 +8,10 @@
 //     Y[c1][k2][e]  = sum_c2 e^{+i k2.L_c2} X[c1][c2][e]          (real input)
 //     out[kp][e]    = sum_c1 e^{-i k1.L_c1} Y[c1][k2][e],  kp = (k1, k2), k1 <= k2
 // over the output elements e = (P, mu, nu) of one aux batch, taken in chunks of
-// E elements (Y holds Nk^2 complex values per element).  Both stages are tiled
-// through LDS: 64 elements x 16 transform outputs per workgroup, 32 cells per
-// stage.  Per element this is 2 Nk^3 + 4 Nk Nkp multiply-adds instead of
+// E elements (Y holds Nk^2 complex values per element).  Both stages take 64
+// elements x 16 transform outputs per workgroup (4 outputs per wavefront), the
+// element values staged through LDS 32 cells at a time, the phases read by
+// scalar loads.  Per element this is 2 Nk^3 + 4 Nk Nkp multiply-adds instead of
 // 2 Nk^2 Nkp.  The second stage's epilogue subtracts pi/(Omega w^2) S_P S_{mu nu}(k)
 // on the k1 == k2 pairs.
 #include <hip/hip_runtime.h>
@@ -25,13 +26,23 @@ constexpr int FD_TE = 64;  // elements per tile
 constexpr int FD_TK = 16;  // transform outputs (k2, or k-pairs of one k2) per tile
 constexpr int FD_TC = 32;  // cells per LDS stage
 
-// stage 1: grid (element tiles of the chunk, k2 tiles, c1)
+// stage 1: grid (element tiles of the chunk, k2 tiles, c1).  The four
+// transform outputs of a wavefront are the same for its 64 lanes, so their
+// phases are read with scalar loads (the wave index is made uniform), and LDS
+// holds only the X tile: one LDS read per eight multiply-adds.
 __global__ __launch_bounds__(256) void fold_k2_kernel(const FoldParams fp, int64_t e0, int64_t E) {
   __shared__ double sX[FD_TC][FD_TE];
-  __shared__ double sPr[FD_TK][FD_TC], sPi[FD_TK][FD_TC];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // ty in [0,4): 4 outputs each
+  const int tx = threadIdx.x & 63;
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // 4 outputs per wave
   const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
   const int k20 = blockIdx.y * FD_TK, c1 = blockIdx.z, nk = fp.nk;
+  // phase rows of the wave's outputs (a row past nk repeats a valid one; its sums are not stored)
+  const double *ph[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k2 = k20 + ty * 4 + j;
+    ph[j] = fp.kph + 2 * (size_t)(k2 < nk ? k2 : nk - 1) * nk;
+  }
   double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
   for (int c0 = 0; c0 < nk; c0 += FD_TC) {
     for (int i = threadIdx.x; i < FD_TC * FD_TE; i += 256) {
@@ -39,20 +50,15 @@ __global__ __launch_bounds__(256) void fold_k2_kernel(const FoldParams fp, int64
       const int64_t eg = (int64_t)blockIdx.x * FD_TE + ee;
       sX[cc][ee] = (c0 + cc < nk && eg < E) ? fp.X[(int64_t)(c1 * nk + c0 + cc) * fp.ne + e0 + eg] : 0.0;
     }
-    for (int i = threadIdx.x; i < FD_TK * FD_TC; i += 256) {
-      const int kk = i / FD_TC, cc = i % FD_TC;
-      const bool ok = (k20 + kk < nk) && (c0 + cc < nk);
-      sPr[kk][cc] = ok ? fp.kph[2 * ((k20 + kk) * nk + c0 + cc)] : 0.0;
-      sPi[kk][cc] = ok ? fp.kph[2 * ((k20 + kk) * nk + c0 + cc) + 1] : 0.0;
-    }
     __syncthreads();
-#pragma unroll 8
-    for (int cc = 0; cc < FD_TC; ++cc) {
+    const int nc = nk - c0 < FD_TC ? nk - c0 : FD_TC;
+#pragma unroll 4
+    for (int cc = 0; cc < nc; ++cc) {
       const double x = sX[cc][tx];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        ar[j] += sPr[ty * 4 + j][cc] * x;
-        ai[j] += sPi[ty * 4 + j][cc] * x;
+        ar[j] += ph[j][2 * (c0 + cc)] * x;
+        ai[j] += ph[j][2 * (c0 + cc) + 1] * x;
       }
     }
     __syncthreads();
@@ -69,20 +75,23 @@ __global__ __launch_bounds__(256) void fold_k2_kernel(const FoldParams fp, int64
 }
 
 // stage 2: grid (element tiles of the chunk, k-pair tiles); a tile holds up to
-// 16 k-pairs (k1, k2) sharing k2, so the staged Y rows serve all of them
+// 16 k-pairs (k1, k2) sharing k2, so the staged Y rows serve all of them; the
+// phases e^{-i k1.L_c1} of a wavefront's four k-pairs by scalar loads
 __global__ __launch_bounds__(256) void fold_k1_kernel(const FoldParams fp, int64_t e0, int64_t E) {
   __shared__ double sYr[FD_TC][FD_TE], sYi[FD_TC][FD_TE];
-  __shared__ double sPr[FD_TK][FD_TC], sPi[FD_TK][FD_TC];
-  __shared__ int sK1[FD_TK];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 63;
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
   const int tile = blockIdx.y, nk = fp.nk;
   const int k2 = fp.tile_k2[tile];
-  if (threadIdx.x < FD_TK) {
-    const int kp = fp.tile_kp[tile * FD_TK + threadIdx.x];
-    sK1[threadIdx.x] = kp >= 0 ? fp.kp1[kp] : -1;
+  const double *ph[4];
+  bool on[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kp = fp.tile_kp[tile * FD_TK + ty * 4 + j];
+    on[j] = kp >= 0;
+    ph[j] = fp.kph + 2 * (size_t)(on[j] ? fp.kp1[kp] : 0) * nk;  // an unused slot reads row 0
   }
-  __syncthreads();
   double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
   if (fp.Y) {
     for (int c0 = 0; c0 < nk; c0 += FD_TC) {
@@ -94,20 +103,15 @@ __global__ __launch_bounds__(256) void fold_k1_kernel(const FoldParams fp, int64
         sYr[cc][ee] = ok ? fp.Y[2 * o] : 0.0;
         sYi[cc][ee] = ok ? fp.Y[2 * o + 1] : 0.0;
       }
-      for (int i = threadIdx.x; i < FD_TK * FD_TC; i += 256) {
-        const int kk = i / FD_TC, cc = i % FD_TC;
-        const int k1 = sK1[kk];
-        const bool ok = k1 >= 0 && c0 + cc < nk;  // e^{-i k1.L_c1} = conj of the table entry
-        sPr[kk][cc] = ok ? fp.kph[2 * (k1 * nk + c0 + cc)] : 0.0;
-        sPi[kk][cc] = ok ? -fp.kph[2 * (k1 * nk + c0 + cc) + 1] : 0.0;
-      }
       __syncthreads();
-#pragma unroll 8
-      for (int cc = 0; cc < FD_TC; ++cc) {
+      const int nc = nk - c0 < FD_TC ? nk - c0 : FD_TC;
+#pragma unroll 4
+      for (int cc = 0; cc < nc; ++cc) {
         const double yr = sYr[cc][tx], yi = sYi[cc][tx];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const double pr = sPr[ty * 4 + j][cc], pi = sPi[ty * 4 + j][cc];
+          // e^{-i k1.L_c1} = conjugate of the table entry
+          const double pr = ph[j][2 * (c0 + cc)], pi = -ph[j][2 * (c0 + cc) + 1];
           ar[j] += pr * yr - pi * yi;
           ai[j] += pr * yi + pi * yr;
         }
@@ -119,8 +123,8 @@ __global__ __launch_bounds__(256) void fold_k1_kernel(const FoldParams fp, int64
   const int64_t eb = e0 + e;  // element index within the aux batch
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
+    if (!on[j]) continue;
     const int kp = fp.tile_kp[tile * FD_TK + ty * 4 + j];
-    if (kp < 0) continue;
     double vr = ar[j], vi = ai[j];
     const int k = fp.kdiag[kp];
     if (k >= 0 && fp.g0fac != 0.0) {
