@@ -297,10 +297,12 @@ double solve_r12_grow(double NF, double beta, double eps, int L, double c) {
   return hi;
 }
 
+// f(i) for i < n on up to 16 host threads, in chunks of `grain` indices
 template <class F>
-void parallel_for(int64_t n, F f) {
+void parallel_for(int64_t n, F f, int64_t grain = 64) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (n < 64 || nt == 1) {
+  nt = (unsigned)std::min<int64_t>(nt, (n + grain - 1) / grain);
+  if (nt <= 1) {
     for (int64_t i = 0; i < n; ++i) f(i);
     return;
   }
@@ -309,9 +311,9 @@ void parallel_for(int64_t n, F f) {
   for (unsigned t = 0; t < nt; ++t)
     th.emplace_back([&]() {
       for (;;) {
-        const int64_t i0 = next.fetch_add(64);
+        const int64_t i0 = next.fetch_add(grain);
         if (i0 >= n) break;
-        for (int64_t i = i0; i < std::min(n, i0 + 64); ++i) f(i);
+        for (int64_t i = i0; i < std::min(n, i0 + grain); ++i) f(i);
       }
     });
   for (auto &t : th) t.join();
@@ -1144,14 +1146,16 @@ int Job::prepare(hipStream_t st, double mem_frac) {
   // factors `split` (autotuner output) scale the target work per wave.
   pgrp_off.assign(1, 0);
   {
+    // pair images inside R12 (all classes) per pair
+    std::vector<int64_t> nimg_pair(npair, 0);
+    for (int ip = 0; ip < npair; ++ip)
+      for (int c = 0; c < nk; ++c) nimg_pair[ip] += hp.nsr[(size_t)ip * nk + c];
     std::vector<double> est(ntrip);
-    double tot = 0.0;
-    for (int64_t t = 0; t < ntrip; ++t) {
+    parallel_for(ntrip, [&](int64_t t) {
       const Triplet &tr = trips[t];
       const Pair &pp = hp.pairs[tr.pair];
       const Shell &sA = hp.ao[pp.sa], &sB = hp.ao[pp.sb], &sP = hp.ax[tr.aux];
-      int64_t nimg = 0;
-      for (int c = 0; c < nk; ++c) nimg += hp.nsr[(size_t)tr.pair * nk + c];
+      const int64_t nimg = nimg_pair[tr.pair];
       const double nm = 4.18879020478639098 * tr.rc_cut * tr.rc_cut * tr.rc_cut / L.vol + 1.0;
       const int Lt = sP.l + sA.l + sB.l;
       // per (primitive triple, pair image, cell range): the group reduction, the
@@ -1163,14 +1167,18 @@ int Job::prepare(hipStream_t st, double mem_frac) {
       const double ev = 2.0 * nherm(Lt) + 2.0 * ncart_h(sP.l) * nherm(lab) * nkx + 2.0 * nblk * nherm(lab);
       const double nranges = std::ceil((double)nk / std::min(nk, sr_cells_per_wave(nblk)));
       est[t] = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg * (nm * sr_term_flops(Lt) + 13.6 * nranges * ev);
-      tot += est[t];
-    }
+    }, 1024);
+    double tot = 0.0;
+    for (int64_t t = 0; t < ntrip; ++t) tot += est[t];
     // target cost per wave: 8 waves per SIMD over the build
     const double target0 = std::max(tot / (8.0 * 1024.0), 1.0);
     const double part_budget = std::min(1.0e9, 0.05 * (double)free_b);  // bytes of partial blocks
     double part_bytes = 0.0;
-    std::vector<std::vector<SRWork>> grp((size_t)nbatch * 24);
-    std::vector<std::vector<double>> gcost((size_t)nbatch * 24);
+    // per triplet: cell ranges of ncbw cells, nsl slices each, the first
+    // partial group (if sliced) and the cost of each of its waves
+    std::vector<int32_t> t_ncbw(ntrip), t_nsl(ntrip);
+    std::vector<int64_t> t_pbase(ntrip, -1);
+    std::vector<double> t_cost(ntrip);
     for (int b = 0; b < nbatch; ++b) {
       for (int g = 0; g < 24; ++g) {
         const double target = target0 * (split.empty() ? 1.0 : (double)split[g]);
@@ -1185,10 +1193,13 @@ int Job::prepare(hipStream_t st, double mem_frac) {
           const int nranges = (nk + ncbw - 1) / ncbw;
           int nsl = (int)std::min<int64_t>(64, (want + nranges - 1) / nranges);
           if (nsl > 1 && part_bytes + (double)nsl * nk * nk * nblk * 8.0 > part_budget) nsl = 1;
-          for (int r = 0; r < nranges; ++r) {
-            const int cb0 = r * ncbw, ncb = std::min(ncbw, nk - cb0);
-            int64_t pbase = -1;
-            if (nsl > 1) {
+          t_ncbw[t] = ncbw;
+          t_nsl[t] = nsl;
+          t_cost[t] = est[t] / ((double)nranges * nsl);
+          if (nsl > 1) {
+            t_pbase[t] = part_total;
+            for (int r = 0; r < nranges; ++r) {
+              const int cb0 = r * ncbw, ncb = std::min(ncbw, nk - cb0);
               SRPartGroup pg{};
               pg.trip = t;
               pg.cb0 = cb0;
@@ -1196,41 +1207,57 @@ int Job::prepare(hipStream_t st, double mem_frac) {
               pg.nslice = nsl;
               pg.part = part_total;
               pgroups.push_back(pg);
-              pbase = part_total;
               part_total += (int64_t)nsl * ncb * nk * nblk;
               part_bytes += (double)nsl * ncb * nk * nblk * 8.0;
-            }
-            for (int sl = 0; sl < nsl; ++sl) {
-              SRWork w{};
-              w.trip = t;
-              w.cb0 = (int16_t)cb0;
-              w.ncb = (int16_t)ncb;
-              w.slice = (int16_t)sl;
-              w.nslice = (int16_t)nsl;
-              w.cell = 0;
-              w.part = (nsl > 1) ? pbase + (int64_t)sl * ncb * nk * nblk : -1;
-              grp[(size_t)b * 24 + g].push_back(w);
-              gcost[(size_t)b * 24 + g].push_back(est[t] / ((double)nranges * nsl));
             }
           }
         }
       }
       pgrp_off.push_back((int)pgroups.size());
     }
-    // heaviest waves first inside each class launch
-    wgrp_off.assign(1, 0);
-    for (size_t g = 0; g < grp.size(); ++g) {
-      std::vector<int> idx(grp[g].size());
-      for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return gcost[g][x] > gcost[g][y]; });
-      double c = 0.0;
-      for (int i : idx) {
-        work.push_back(grp[g][i]);
-        c += gcost[g][i];
-      }
-      wgrp_off.push_back((int)work.size());
-      wgrp_cost.push_back(c);
+    // the waves of a class launch, heaviest first (a triplet's waves share one
+    // cost, so the triplets are sorted and their waves kept in range, slice
+    // order); the class groups are independent and filled in parallel
+    const int ngrp = (int)tgrp_off.size() - 1;
+    wgrp_off.assign(ngrp + 1, 0);
+    for (int g = 0; g < ngrp; ++g) {
+      int64_t n = 0;
+      for (int t = tgrp_off[g]; t < tgrp_off[g + 1]; ++t) n += (int64_t)((nk + t_ncbw[t] - 1) / t_ncbw[t]) * t_nsl[t];
+      wgrp_off[g + 1] = (int)(wgrp_off[g] + n);
     }
+    work.resize(wgrp_off[ngrp]);
+    wgrp_cost.assign(ngrp, 0.0);
+    parallel_for(ngrp, [&](int64_t g) {
+      std::vector<int> idx;
+      idx.reserve(tgrp_off[g + 1] - tgrp_off[g]);
+      for (int t = tgrp_off[g]; t < tgrp_off[g + 1]; ++t) idx.push_back(t);
+      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return t_cost[x] > t_cost[y]; });
+      double c = 0.0;
+      SRWork *w = work.data() + wgrp_off[g];
+      for (int t : idx) {
+        const Triplet &tr = trips[t];
+        const Pair &pp = hp.pairs[tr.pair];
+        const int nblk = ncart_h(hp.ax[tr.aux].l) * ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+        const int ncbw = t_ncbw[t], nsl = t_nsl[t], nranges = (nk + ncbw - 1) / ncbw;
+        int64_t pbase = t_pbase[t];
+        for (int r = 0; r < nranges; ++r) {
+          const int cb0 = r * ncbw, ncb = std::min(ncbw, nk - cb0);
+          for (int sl = 0; sl < nsl; ++sl, ++w) {
+            *w = SRWork{};
+            w->trip = t;
+            w->cb0 = (int16_t)cb0;
+            w->ncb = (int16_t)ncb;
+            w->slice = (int16_t)sl;
+            w->nslice = (int16_t)nsl;
+            w->cell = 0;
+            w->part = (nsl > 1) ? pbase + (int64_t)sl * ncb * nk * nblk : -1;
+            c += t_cost[t];
+          }
+          if (nsl > 1) pbase += (int64_t)nsl * ncb * nk * nblk;
+        }
+      }
+      wgrp_cost[g] = c;
+    }, 1);
     // element prefix sums of the partial groups (per batch)
     for (int b = 0; b < nbatch; ++b) {
       int64_t off = 0;

@@ -485,16 +485,18 @@ hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t strea
 // ---- G-space contraction on the matrix cores ---------------------------------
 // out[kp][m][n] += sum_q A[m][q] B[kpi][n][q], complex, as real products on
 // 16x16 MFMA blocks: C_re += A_re B_re - A_im B_im, C_im += A_re B_im + A_im B_re.
-//   mode 0: FP64 operands, v_mfma_f64_16x16x4 (FP64 accumulation)
+//   mode 0: FP64 operands, v_mfma_f64_16x16x4 (FP64 accumulation;
+//           lr_gemm_f64_kernel)
 //   mode 1: FP32 operands (rounded from FP64), v_mfma_f32_16x16x4
-//   mode 2: split FP16 (lr_gemm_f16x3_kernel below): each FP32 operand of a
-//           32-q step scaled by a power of two per row and split x = hi + lo
-//           into two FP16 numbers; a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//           (lr_gemm_f32_kernel)
+//   mode 2: split FP16 (lr_gemm_f16x3_kernel): each operand row scaled by a
+//           power of two per 64-q group and split x = hi + lo into two FP16
+//           numbers; a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
 //           v_mfma_f32_16x16x32_f16
-// In modes 1 and 2 the matrix cores accumulate one step (16 q, resp. 32 q) in
-// FP32; each step's partial is then added to FP64 registers, and the first nq_hi columns
-// (the smallest |q|, whose kernel weights 1/q^2 dominate) are taken in FP64
-// on the vector ALUs.
+// In modes 1 and 2 the matrix cores accumulate in FP32 over one step (16 q)
+// resp. one exponent group (64 q); each partial is then added to FP64
+// registers, and the first nq_hi columns (the smallest |q|, whose kernel
+// weights 1/q^2 dominate) are taken in FP64 on the vector ALUs.
 // Operand fragments (li = lane % 16, lg = lane / 16):
 //   16x16x4 (f64, f32): A[li][lg], B[lg][li]
 //   16x16x32 f16:       A[li][8 lg + j], B[8 lg + j][li], j = 0..7 packed
@@ -503,41 +505,22 @@ hipError_t launch_to_f32(const double *x, float *y, int64_t n, hipStream_t strea
 typedef double lr_d4 __attribute__((ext_vector_type(4)));
 typedef float lr_f4 __attribute__((ext_vector_type(4)));
 
-// ---- tiled G-space contraction ----------------------------------------------
-// Workgroup output tile BM (aux rows) x BN (pair columns): 2 x (BM/32)
-// wavefronts, wave (wm, wn) owning rows 32 wm .. +32 and columns (BN/2) wn ..
-// + BN/2 (2 x BN/32 MFMA blocks).  Per step of 16 q the A and B tiles are read once,
-// converted to the form's operand format and staged in LDS (rows padded
-// against bank conflicts); the next step's tiles are loaded into registers
-// while the matrix cores work on the current one.  Modes 1 and 2 promote the
-// FP32 block sums to FP64 registers after every step, which needs twice the
-// registers: they run 4 waves per workgroup (BM = 64, BN = 64), mode 0 runs 8
-// (BM = 128, BN = 128).  Columns q in [q_lo, nq) of the launch.
-constexpr int TG_BK = 16;
-// pair columns per workgroup: 64 in the reduced-precision forms (a wave holds
-// 2 x 2 blocks, so its FP32 and FP64 accumulators leave room for three waves
-// per SIMD; with 2 x 4 blocks it was one), 128 for FP64 operands
-__host__ __device__ constexpr int tg_bn(int mode) { return mode == 0 ? 128 : 64; }
-__host__ __device__ constexpr int tg_bm(int mode) { return mode == 0 ? 128 : 64; }
-__host__ __device__ constexpr int tg_threads(int mode) { return 2 * (tg_bm(mode) / 32) * 64; }
-
-template <int MODE>
-struct TgTile;
-template <>
-struct TgTile<0> {  // FP64 re / im planes
-  double ar[128][TG_BK + 1], ai[128][TG_BK + 1], br[tg_bn(0)][TG_BK + 1], bi[tg_bn(0)][TG_BK + 1];
-};
-template <>
-struct TgTile<1> {  // FP32 re / im planes
-  float ar[64][TG_BK + 1], ai[64][TG_BK + 1], br[tg_bn(1)][TG_BK + 1], bi[tg_bn(1)][TG_BK + 1];
+// ---- FP32 contraction (mode 1) ----------------------------------------------
+// Workgroup output tile 64 (aux rows) x 64 (pair columns), 4 waves; wave (wm,
+// wn) = (wave / 2, wave % 2) owns rows 32 wm .. +32 and columns 32 wn .. +32
+// (2 x 2 MFMA blocks).  Per step of 16 q the A and B tiles are read once,
+// rounded to FP32 and staged in LDS (rows padded against bank conflicts); the
+// next step's tiles are loaded into registers while the matrix cores work on
+// the current one.  The FP32 block sums are promoted to FP64 registers after
+// every step.  Columns q in [q_lo, nq) of the launch.
+constexpr int F32_BM = 64, F32_BN = 64, F32_NT = 256, F32_BK = 16;
+struct F32Tile {  // FP32 re / im planes
+  float ar[F32_BM][F32_BK + 1], ai[F32_BM][F32_BK + 1], br[F32_BN][F32_BK + 1], bi[F32_BN][F32_BK + 1];
 };
 
-template <int MODE>
-__global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const LRGemmParams gp, int q_lo) {
-  constexpr int BM = tg_bm(MODE), NT = tg_threads(MODE), BN = tg_bn(MODE);
-  constexpr int NB = BN / 32;   // 16-column blocks per wave (a wave takes half the columns)
-  constexpr int RA = BM * 4 / NT, RB = BN * 4 / NT;  // staged rows per thread (4 threads x 4 q per row)
-  __shared__ TgTile<MODE> S;
+__global__ __launch_bounds__(F32_NT) void lr_gemm_f32_kernel(const LRGemmParams gp, int q_lo) {
+  constexpr int RA = F32_BM * 4 / F32_NT, RB = F32_BN * 4 / F32_NT;  // staged rows per thread (4 threads x 4 q per row)
+  __shared__ F32Tile S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int wm = wave >> 1, wn = wave & 1;
@@ -547,17 +530,14 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
   // b + 16, ... are renumbered consecutively, and consecutive tile numbers
   // walk the aux rows first, so the row tiles that share one B tile (and
   // stream the same q columns of A) run together on one XCD.
-  const int mt = (gp.naux + BM - 1) / BM, ntile = mt * ((gp.nmn + BN - 1) / BN);
+  const int mt = (gp.naux + F32_BM - 1) / F32_BM, ntile = mt * ((gp.nmn + F32_BN - 1) / F32_BN);
   const int per = (ntile + 7) / 8;  // the grid holds 8 per workgroups
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (t >= ntile) return;
-  const int M0 = (t % mt) * BM, N0 = (t / mt) * BN;
-  const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
+  const int M0 = (t % mt) * F32_BM, N0 = (t / mt) * F32_BN;
   const float *Bk32 = gp.B32 + 2 * (size_t)kpi * gp.nq * gp.nmn;
   const int sr0 = tid >> 2, sq = (tid & 3) * 4;
-  // staged operands in their storage format: FP64 (mode 0) or FP32 (modes 1, 2)
-  typedef typename std::conditional<MODE == 0, double, float>::type ld_t;
-  ld_t ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
+  float ga[RA][8], gb[RB][8];  // re, im of 4 q per staged row
   auto gload = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -565,32 +545,22 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
       const bool okk = k < gp.nq;
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
-        const int m = M0 + sr0 + r * (NT / 4);
+        const int m = M0 + sr0 + r * (F32_NT / 4);
         if (okk && m < gp.naux) {
           const size_t o = (size_t)m * gp.lda + k;
-          if constexpr (MODE == 0) {
-            ga[r][2 * j] = gp.A[2 * o];
-            ga[r][2 * j + 1] = gp.A[2 * o + 1];
-          } else {
-            ga[r][2 * j] = gp.A32[2 * o];
-            ga[r][2 * j + 1] = gp.A32[2 * o + 1];
-          }
+          ga[r][2 * j] = gp.A32[2 * o];
+          ga[r][2 * j + 1] = gp.A32[2 * o + 1];
         } else {
           ga[r][2 * j] = ga[r][2 * j + 1] = 0;
         }
       }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int n = N0 + sr0 + r * (NT / 4);
+        const int n = N0 + sr0 + r * (F32_NT / 4);
         if (okk && n < gp.nmn) {
           const size_t o = (size_t)n * gp.nq + k;
-          if constexpr (MODE == 0) {
-            gb[r][2 * j] = Bk[2 * o];
-            gb[r][2 * j + 1] = Bk[2 * o + 1];
-          } else {
-            gb[r][2 * j] = Bk32[2 * o];
-            gb[r][2 * j + 1] = Bk32[2 * o + 1];
-          }
+          gb[r][2 * j] = Bk32[2 * o];
+          gb[r][2 * j + 1] = Bk32[2 * o + 1];
         } else {
           gb[r][2 * j] = gb[r][2 * j + 1] = 0;
         }
@@ -602,135 +572,114 @@ __global__ __launch_bounds__(tg_threads(MODE)) void lr_gemm_tiled_kernel(const L
     for (int j = 0; j < 4; ++j) {
 #pragma unroll
       for (int r = 0; r < RA; ++r) {
-        const int row = sr0 + r * (NT / 4);
+        const int row = sr0 + r * (F32_NT / 4);
         S.ar[row][sq + j] = ga[r][2 * j];
         S.ai[row][sq + j] = ga[r][2 * j + 1];
       }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int row = sr0 + r * (NT / 4);
+        const int row = sr0 + r * (F32_NT / 4);
         S.br[row][sq + j] = gb[r][2 * j];
         S.bi[row][sq + j] = gb[r][2 * j + 1];
       }
     }
   };
 
-  typedef typename std::conditional<MODE == 0, lr_d4, lr_f4>::type acc_t;
-  acc_t cre[2][NB], cim[2][NB];
-  double hre[2][NB][4], him[2][NB][4];  // FP64 sums of modes 1 and 2 (f32 fragment order)
+  lr_f4 cre[2][2], cim[2][2];
+  double hre[2][2][4], him[2][2][4];  // FP64 sums (f32 fragment order)
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         cre[r][c][v] = cim[r][c][v] = 0;
         hre[r][c][v] = him[r][c][v] = 0.0;
       }
 
-  // modes 1 and 2: the innermost q shell (first nq_hi columns) in FP64 on the
-  // vector ALUs, rows in the f32 fragment order
-  int kstart = q_lo;
-  if constexpr (MODE != 0) {
-    const int khi = gp.nq_hi < gp.nq ? gp.nq_hi : gp.nq;
-    for (int k = q_lo; k < khi; ++k) {
-      double br[NB], bi[NB];
+  // the innermost q shell (first nq_hi columns) in FP64 on the vector ALUs,
+  // rows in the f32 fragment order
+  const int khi = gp.nq_hi < gp.nq ? gp.nq_hi : gp.nq;
+  for (int k = q_lo; k < khi; ++k) {
+    double br[2], bi[2];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const int n = N0 + wn * (BN / 2) + c * 16 + li;
-        const size_t o = ((size_t)kpi * gp.nmn + n) * gp.nq_hi + k;
-        br[c] = (n < gp.nmn) ? gp.Bhi[2 * o] : 0.0;
-        bi[c] = (n < gp.nmn) ? gp.Bhi[2 * o + 1] : 0.0;
-      }
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
-          const size_t o = (size_t)m * gp.lda + k;
-          const double ar = (m < gp.naux) ? gp.A[2 * o] : 0.0, ai = (m < gp.naux) ? gp.A[2 * o + 1] : 0.0;
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            hre[r][c][v] += ar * br[c] - ai * bi[c];
-            him[r][c][v] += ar * bi[c] + ai * br[c];
-          }
-        }
+    for (int c = 0; c < 2; ++c) {
+      const int n = N0 + wn * 32 + c * 16 + li;
+      const size_t o = ((size_t)kpi * gp.nmn + n) * gp.nq_hi + k;
+      br[c] = (n < gp.nmn) ? gp.Bhi[2 * o] : 0.0;
+      bi[c] = (n < gp.nmn) ? gp.Bhi[2 * o + 1] : 0.0;
     }
-    kstart = khi > q_lo ? khi : q_lo;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
+        const size_t o = (size_t)m * gp.lda + k;
+        const double ar = (m < gp.naux) ? gp.A[2 * o] : 0.0, ai = (m < gp.naux) ? gp.A[2 * o + 1] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          hre[r][c][v] += ar * br[c] - ai * bi[c];
+          him[r][c][v] += ar * bi[c] + ai * br[c];
+        }
+      }
   }
+  const int kstart = khi > q_lo ? khi : q_lo;
   gload(kstart);
-  for (int k0 = kstart; k0 < gp.nq; k0 += TG_BK) {
+  for (int k0 = kstart; k0 < gp.nq; k0 += F32_BK) {
     __syncthreads();  // previous step's fragments consumed
     sstore();
     __syncthreads();
-    if (k0 + TG_BK < gp.nq) gload(k0 + TG_BK);  // in flight during the MFMAs
-    {
+    if (k0 + F32_BK < gp.nq) gload(k0 + F32_BK);  // in flight during the MFMAs
 #pragma unroll
-      for (int ks = 0; ks < TG_BK / 4; ++ks) {
-        const int k = ks * 4 + lg;
-        typedef typename std::conditional<MODE == 0, double, float>::type op_t;
-        op_t ar[2], ai[2], br[NB], bi[NB];
+    for (int ks = 0; ks < F32_BK / 4; ++ks) {
+      const int k = ks * 4 + lg;
+      float ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          ar[r] = S.ar[wm * 32 + r * 16 + li][k];
-          ai[r] = S.ai[wm * 32 + r * 16 + li][k];
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          br[c] = S.br[wn * (BN / 2) + c * 16 + li][k];
-          bi[c] = S.bi[wn * (BN / 2) + c * 16 + li][k];
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            if constexpr (MODE == 0) {
-              cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], br[c], cre[r][c], 0, 0, 0);
-              cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[r], bi[c], cre[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[r], bi[c], cim[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[r], br[c], cim[r][c], 0, 0, 0);
-            } else {
-              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], br[c], cre[r][c], 0, 0, 0);
-              cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[r], bi[c], cre[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], bi[c], cim[r][c], 0, 0, 0);
-              cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[r], br[c], cim[r][c], 0, 0, 0);
-            }
-          }
+      for (int r = 0; r < 2; ++r) {
+        ar[r] = S.ar[wm * 32 + r * 16 + li][k];
+        ai[r] = S.ai[wm * 32 + r * 16 + li][k];
       }
-    }
-    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        br[c] = S.br[wn * 32 + c * 16 + li][k];
+        bi[c] = S.bi[wn * 32 + c * 16 + li][k];
+      }
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            hre[r][c][v] += (double)cre[r][c][v];
-            him[r][c][v] += (double)cim[r][c][v];
-            cre[r][c][v] = 0.f;
-            cim[r][c][v] = 0.f;
-          }
+        for (int c = 0; c < 2; ++c) {
+          cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], br[c], cre[r][c], 0, 0, 0);
+          cre[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[r], bi[c], cre[r][c], 0, 0, 0);
+          cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[r], bi[c], cim[r][c], 0, 0, 0);
+          cim[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[r], br[c], cim[r][c], 0, 0, 0);
+        }
     }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          hre[r][c][v] += (double)cre[r][c][v];
+          him[r][c][v] += (double)cim[r][c][v];
+          cre[r][c][v] = 0.f;
+          cim[r][c][v] = 0.f;
+        }
   }
-  // epilogue: f64 fragment row = lg + 4 v, f32 fragment row = 4 lg + v
+  // epilogue: f32 fragment row = 4 lg + v
   const size_t kp = gp.kp_of[kpi];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = M0 + wm * 32 + r * 16 + ((MODE == 0) ? (lg + 4 * v) : (4 * lg + v));
-        const int n = N0 + wn * (BN / 2) + c * 16 + li;
+        const int m = M0 + wm * 32 + r * 16 + 4 * lg + v;
+        const int n = N0 + wn * 32 + c * 16 + li;
         if (m < gp.naux && n < gp.nmn) {
           const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
-          if constexpr (MODE == 0) {
-            gp.out[2 * o] += cre[r][c][v];
-            gp.out[2 * o + 1] += cim[r][c][v];
-          } else {
-            gp.out[2 * o] += hre[r][c][v];
-            gp.out[2 * o + 1] += him[r][c][v];
-          }
+          gp.out[2 * o] += hre[r][c][v];
+          gp.out[2 * o + 1] += him[r][c][v];
         }
       }
 }
@@ -910,7 +859,7 @@ __global__ __launch_bounds__(F16_NT) void lr_gemm_f16x3_kernel(const LRGemmParam
   const int li = lane & 15, lg = lane >> 4;
   const int wm = wave >> 1, wn = wave & 1;
   const int kpi = blockIdx.z;
-  // XCD-aware tile order as in lr_gemm_tiled_kernel
+  // XCD-aware tile order as in lr_gemm_f32_kernel
   const int mt = (gp.naux + F16_BM - 1) / F16_BM, ntile = mt * ((gp.nmn + F16_BN - 1) / F16_BN);
   const int per = (ntile + 7) / 8;
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -1093,15 +1042,153 @@ __global__ __launch_bounds__(F16_NT) void lr_gemm_f16x3_kernel(const LRGemmParam
       }
 }
 
+// ---- FP64 contraction (mode 0) ------------------------------------------------
+// Workgroup tile 128 x 128, 8 waves; wave (wm, wn) = (wave / 2, wave % 2) owns
+// rows 32 wm .. +32 and columns 64 wn .. +64 (2 x 4 blocks of 16 x 16).  A step
+// is 16 q.  Its A and B tiles (128 rows x 16 complex numbers, 32 KB each) go
+// from global memory straight into LDS, one complex number (16 bytes) per lane
+// and load, with two stages in flight: no registers are spent on staging, and
+// the loads of step s + 1 run while the matrix cores work on step s.  Row r of
+// a tile keeps its q at chunk position q ^ (r % 16), so the 16 lanes of one
+// fragment read (rows li, one q) fall on 16 different groups of four banks.
+// Rows past the end are clamped to the last row (their results are not
+// stored) and q past the end of the launch to the last q; there the A
+// fragment is replaced by zero.
+constexpr int F64_BM = 128, F64_BN = 128, F64_NT = 512, F64_BK = 16;
+constexpr int F64_TILE = F64_BM * F64_BK * 16;  // 32768 bytes
+static_assert(F64_BM * F64_BK * 16 == 4 * F64_NT * 16, "four loads per thread and tile");
+typedef double lr_d2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(F64_NT) void lr_gemm_f64_kernel(const LRGemmParams gp, int q_lo) {
+  __shared__ __attribute__((aligned(16))) unsigned char S[2][2 * F64_TILE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int kpi = blockIdx.z;
+  // XCD-aware tile order as in lr_gemm_f32_kernel
+  const int mt = (gp.naux + F64_BM - 1) / F64_BM, ntile = mt * ((gp.nmn + F64_BN - 1) / F64_BN);
+  const int per = (ntile + 7) / 8;
+  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (t >= ntile) return;
+  const int M0 = (t % mt) * F64_BM, N0 = (t / mt) * F64_BN;
+  const double *Bk = gp.B + 2 * (size_t)kpi * gp.nq * gp.nmn;
+  // slots u = (8 j + wave) 64 + lane, j < 4, of each tile: row u / 16, q
+  // offset (u % 16) ^ (row % 16)
+  const double *pa[4], *pb[4];
+  int qo[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int u = (8 * j + wave) * 64 + lane, r = u >> 4;
+    qo[j] = (u & 15) ^ (r & 15);
+    pa[j] = gp.A + 2 * (size_t)min(M0 + r, gp.naux - 1) * gp.lda;
+    pb[j] = Bk + 2 * (size_t)min(N0 + r, gp.nmn - 1) * gp.nq;
+  }
+  // loads of the step starting at k0 into stage st: 8 per thread
+  auto issue = [&](int k0, int st) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = min(k0 + qo[j], gp.nq - 1);
+      __builtin_amdgcn_global_load_lds(pa[j] + 2 * q, &S[st][(8 * j + wave) * 1024], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(pb[j] + 2 * q, &S[st][F64_TILE + (8 * j + wave) * 1024], 16, 0, 0);
+    }
+  };
+
+  lr_d4 cre[2][4], cim[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cre[r][c][v] = cim[r][c][v] = 0.0;
+  // 16-row blocks of this wave inside the aux range: in the last row tile the
+  // blocks past the end take no products, so a SIMD there has half the work
+  const int nr = min(max((gp.naux - (M0 + wm * 32) + 15) / 16, 0), 2);
+  // the products of one step (16 q) for the wave's first NR row blocks
+  auto step = [&](const unsigned char *SA, const unsigned char *SB, int k0, auto nrc) {
+    constexpr int NR = decltype(nrc)::value;
+#pragma unroll
+    for (int ks = 0; ks < F64_BK / 4; ++ks) {
+      const int k = 4 * ks + lg;
+      const bool kin = k0 + k < gp.nq;
+      lr_d2 a[NR], b[4];
+      double an[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        a[r] = *reinterpret_cast<const lr_d2 *>(SA + (wm * 32 + r * 16 + li) * 256 + ((k ^ li) << 4));
+        if (!kin) a[r] = lr_d2{0.0, 0.0};
+        an[r] = -a[r].y;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        b[c] = *reinterpret_cast<const lr_d2 *>(SB + (wn * 64 + c * 16 + li) * 256 + ((k ^ li) << 4));
+      // four independent rounds over the blocks, so that no product waits
+      // for the one just issued into the same accumulator
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, cre[r][c], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, cim[r][c], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cre[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[r], b[c].y, cre[r][c], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cim[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].y, b[c].x, cim[r][c], 0, 0, 0);
+    }
+  };
+  const int nst = (gp.nq - q_lo + F64_BK - 1) / F64_BK;  // >= 1 (the launcher skips empty launches)
+  issue(q_lo, 0);
+  int st = 0;
+  for (int s = 0; s < nst; ++s) {
+    const int k0 = q_lo + s * F64_BK;
+    // stage st ^ 1 was consumed in the previous step (barrier below)
+    if (s + 1 < nst) {
+      issue(k0 + F64_BK, st ^ 1);
+      wait_vmcnt<8>();  // this step's loads done, the next step's in flight
+    } else {
+      wait_vmcnt<0>();
+    }
+    bare_barrier();  // every wave's part of the step in LDS
+    const unsigned char *SA = S[st], *SB = S[st] + F64_TILE;
+    if (nr == 2) step(SA, SB, k0, std::integral_constant<int, 2>{});
+    else if (nr == 1) step(SA, SB, k0, std::integral_constant<int, 1>{});
+    wait_lgkm0();    // this wave's reads of stage st returned
+    bare_barrier();  // every wave's: the next step refills it
+    st ^= 1;
+  }
+  // f64 fragment row = lg + 4 v
+  const size_t kp = gp.kp_of[kpi];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = M0 + wm * 32 + r * 16 + lg + 4 * v;
+        const int n = N0 + wn * 64 + c * 16 + li;
+        if (m < gp.naux && n < gp.nmn) {
+          const size_t o = kp * gp.plane + (size_t)m * gp.nmn + n;
+          gp.out[2 * o] += cre[r][c][v];
+          gp.out[2 * o + 1] += cim[r][c][v];
+        }
+      }
+}
+
 hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int nkpi, hipStream_t stream) {
   if (q_lo >= gp.nq) return hipSuccess;
-  const int bm = tg_bm(mode);
-  const int bn = tg_bn(mode);
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+  const int bm = mode == 0 ? F64_BM : mode == 1 ? F32_BM : F16_BM;
+  const int bn = mode == 0 ? F64_BN : mode == 1 ? F32_BN : F16_BN;
   const int64_t ntile = (int64_t)((gp.nmn + bn - 1) / bn) * ((gp.naux + bm - 1) / bm);
   if (ntile * 8 > 0x7fffffff) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(8 * ((ntile + 7) / 8)), 1, nkpi);
-  if (mode == 0) hipLaunchKernelGGL(lr_gemm_tiled_kernel<0>, grid, dim3(tg_threads(0)), 0, stream, gp, q_lo);
-  else if (mode == 1) hipLaunchKernelGGL(lr_gemm_tiled_kernel<1>, grid, dim3(tg_threads(1)), 0, stream, gp, q_lo);
+  if (mode == 0) hipLaunchKernelGGL(lr_gemm_f64_kernel, grid, dim3(F64_NT), 0, stream, gp, q_lo);
+  else if (mode == 1) hipLaunchKernelGGL(lr_gemm_f32_kernel, grid, dim3(F32_NT), 0, stream, gp, q_lo);
   else {
     // the split format's blocks start at q = 0 and the FP64 columns end on a block boundary
     if (q_lo != 0 || gp.nq_hi % kF16Blk != 0 || gp.nb != f16_nblk(gp.nq) || !gp.Xa || !gp.Xb ||
