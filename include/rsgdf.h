@@ -346,6 +346,19 @@ int rsgdf_autotune_sr(const rsgdf_cell *cell, const rsgdf_basis *basis, const rs
                       const int32_t kmesh[3], double omega, double thresh, float *split, double *class_ms,
                       void *stream);
 
+/* Device memory cache (a project addition).  The large scratch buffers of a
+ * build (64 MB and more: the short-range bins, the fold intermediate, the
+ * long-range q-chunk operands) are not freed when it returns but kept idle
+ * for the next build on the same device, which reuses a block that holds its
+ * request and wastes at most a quarter of it; idle blocks beyond 40% of the
+ * device's memory are freed at once, and all idle blocks of a device when an
+ * allocation there fails.  The scratch budgets count idle blocks as free
+ * memory, so a build plans the same with or without them.  This call frees
+ * every idle block (blocks of builds still running are not affected; do not
+ * call it concurrently with a build that is returning).  Returns RSGDF_OK or
+ * RSGDF_EHIP. */
+int rsgdf_release_cache(void);
+
 /* Message of the last error on this thread ("" if none). */
 const char *rsgdf_last_error(void);
 

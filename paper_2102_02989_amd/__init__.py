@@ -20,6 +20,7 @@ from .rsgdf import (  # noqa: F401
     SCREEN_RIGOROUS,
     RsgdfError,
     build_j3c,
+    release_cache,
     build_j2c,
     j2c_nbytes,
     df_solve,

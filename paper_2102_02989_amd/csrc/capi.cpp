@@ -59,13 +59,118 @@ struct Arena {
 };
 thread_local Arena *t_arena = nullptr;
 
+// Cache of large device blocks across builds.  A hipMalloc or hipFree of a
+// buffer of tens of GB takes from under a millisecond to over a second (the
+// long ones measured right after a large free), so the blocks of a build from
+// kCacheMin bytes on go to an idle list when the build ends and the next
+// request that fits reuses them: the smallest idle block of the current
+// device that holds the request and wastes at most a quarter of itself.  Idle
+// blocks beyond 40% of the device's memory are freed at once (oldest first),
+// all of a device's when an allocation on it fails, and all by
+// rsgdf_release_cache().  The budgets that follow the free memory count the
+// idle blocks as free, and the part of a reused block beyond its request, so
+// the planning of a build does not depend on the cache.
+constexpr size_t kCacheMin = (size_t)64 << 20;
+constexpr int kCacheDevs = 64;
+struct CacheBlk {
+  int dev;
+  void *p;
+  size_t n;
+};
+std::mutex g_cache_mu;
+std::vector<CacheBlk> g_cache;          // idle blocks, oldest first
+size_t g_cache_slack[kCacheDevs] = {};  // bytes of live reused blocks beyond their requests
+
+size_t cache_idle_locked(int dev) {
+  size_t b = 0;
+  for (const CacheBlk &c : g_cache)
+    if (c.dev == dev) b += c.n;
+  return b;
+}
+// free the oldest idle blocks of dev until at most keep bytes stay idle
+void cache_trim_locked(int dev, size_t keep) {
+  size_t idle = cache_idle_locked(dev);
+  for (size_t i = 0; i < g_cache.size() && idle > keep;) {
+    if (g_cache[i].dev != dev) {
+      ++i;
+      continue;
+    }
+    (void)hipFree(g_cache[i].p);
+    idle -= g_cache[i].n;
+    g_cache.erase(g_cache.begin() + (std::ptrdiff_t)i);
+  }
+}
+// idle bytes plus the slack of live reused blocks of the current device
+size_t cache_free_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return cache_idle_locked(dev) + (dev >= 0 && dev < kCacheDevs ? g_cache_slack[dev] : 0);
+}
+// a block of at least bytes; *got = its size
+hipError_t dev_alloc(void **p, size_t bytes, size_t *got) {
+  *got = bytes;
+  if (bytes < kCacheMin) return hipMalloc(p, bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      const CacheBlk &c = g_cache[i];
+      if (c.dev == dev && c.n >= bytes && c.n - bytes <= c.n / 4 && (best < 0 || c.n < g_cache[best].n))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      *p = g_cache[best].p;
+      *got = g_cache[best].n;
+      if (dev >= 0 && dev < kCacheDevs) g_cache_slack[dev] += *got - bytes;
+      g_cache.erase(g_cache.begin() + best);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      cache_trim_locked(dev, 0);
+    }
+    e = hipMalloc(p, bytes);
+  }
+  return e;
+}
+// give a block back: small ones are freed, large ones kept idle.  Like
+// hipFree, this first waits for the device, so no kernel still uses the block
+// when the next request takes it.
+void dev_release(void *p, size_t n, size_t req) {
+  if (n < kCacheMin) {
+    (void)hipFree(p);
+    return;
+  }
+  int dev = 0;
+  size_t fr = 0, tot = 0;
+  const bool ok = hipGetDevice(&dev) == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
+                  hipMemGetInfo(&fr, &tot) == hipSuccess;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (dev >= 0 && dev < kCacheDevs) g_cache_slack[dev] -= std::min(g_cache_slack[dev], n - std::min(n, req));
+  if (!ok) {
+    (void)hipFree(p);
+    return;
+  }
+  g_cache.push_back({dev, p, n});
+  cache_trim_locked(dev, (size_t)(0.4 * (double)tot));
+}
+
 // RAII device buffer
 struct DBuf {
   void *p = nullptr;
   size_t n = 0;
+  size_t cap = 0;  // bytes of the block behind p (>= n)
   bool owned = false;
   ~DBuf() {
-    if (p && owned) (void)hipFree(p);
+    if (p && owned) dev_release(p, cap, n == 0 ? 16 : n);
   }
   hipError_t alloc(size_t bytes) {
     n = bytes;
@@ -83,7 +188,7 @@ struct DBuf {
       return hipSuccess;
     }
     owned = true;
-    return hipMalloc(&p, bytes);
+    return dev_alloc(&p, bytes, &cap);
   }
   template <class T>
   T *as() const {
@@ -131,14 +236,16 @@ int validate_basis(const rsgdf_basis *b, int natm, int lmax, const char *what) {
 }
 
 // free device memory for the scratch budgets: the remainder of the installed
-// arena, else what the runtime reports
+// arena, else what the runtime reports plus the idle cached blocks
 hipError_t mem_avail(size_t *free_b) {
   if (t_arena) {
     *free_b = t_arena->cap - std::min(t_arena->cap, t_arena->used);
     return hipSuccess;
   }
   size_t total_b = 0;
-  return hipMemGetInfo(free_b, &total_b);
+  const hipError_t e = hipMemGetInfo(free_b, &total_b);
+  if (e == hipSuccess) *free_b += cache_free_bytes();
+  return e;
 }
 
 int64_t nfunc(const rsgdf_basis *b) {
@@ -232,24 +339,75 @@ double f_sr(double R, double eta1, double eta2) {  // Eq. S7
   return (std::erf(eta1 * R) - std::erf(eta2 * R)) / R;
 }
 
+// The cut x* of a bracket [lo, hi] with g(lo) > 0 >= g(hi), g having one sign
+// change there and falling through it: Newton steps with g' from the newest
+// point, a bisection whenever g' is not negative there or the step leaves the
+// bracket.  Ends when a step is below 1e-14 of x (Newton converges
+// quadratically, so x is then within far less of x*) and returns x (1 + 1e-12),
+// at or beyond the cut like the upper end of a bisection; or the bracket's
+// upper end once it is that narrow.
+template <class G, class D>
+double cut_root(G g, D dg, double lo, double hi) {
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double gx = g(x);
+    if (gx > 0) lo = x;
+    else hi = x;
+    if (hi - lo <= 1e-14 * hi) return hi;
+    const double d = dg(x);
+    double xn = (d < 0.0) ? x - gx / d : 0.5 * (lo + hi);
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (std::fabs(xn - x) <= 1e-14 * x) return std::min(hi, xn * (1.0 + 1e-12));
+    x = xn;
+  }
+  return hi;
+}
+
 // largest R > 0 with K (1 + 2 eta R)^L exp(-eta^2 R^2)/R >= eps: the bound of Eq. S14
 // with the growth of an angular momentum L = l_P + l_a + l_b term, whose
 // Gaussian tail carries a degree-L polynomial (the L-th Hermite derivative of
 // exp(-eta^2 R^2) is (2 eta^2 R)^L exp(-eta^2 R^2) times 1 + O(1/R^2)), which the
-// s-type model of Eq. S14 leaves out.  The left side rises at most once and
-// then decreases, so bisection from a point where it holds finds the cut.
+// s-type model of Eq. S14 leaves out.  With t = eta R the logarithm g of the
+// left side over eps has g' > 0 exactly where q(t) = 4t^3 + 2t^2 - 2(L-1)t + 1
+// < 0: for L < 3 never (g falls), for larger L on the interval (t1, t2) between
+// the positive roots of q when its minimum is negative (g falls, rises, falls).
+// The largest cut lies beyond the local maximum t2 / eta if g is positive
+// there, else before the local minimum t1 / eta; each bracket holds one.
 double solve_rc(double K, double eta, double eps, int L) {
   const double c0 = std::log(K) - std::log(eps);
   auto g = [&](double R) { return c0 + L * std::log1p(2.0 * eta * R) - eta * eta * R * R - std::log(R); };
+  auto dg = [&](double R) { return 2.0 * L * eta / (1.0 + 2.0 * eta * R) - 2.0 * eta * eta * R - 1.0 / R; };
+  double t1 = 0.0, t2 = 0.0;
+  if (L >= 3) {
+    auto q = [&](double t) { return ((4.0 * t + 2.0) * t - 2.0 * (L - 1)) * t + 1.0; };
+    auto dq = [&](double t) { return (12.0 * t + 4.0) * t - 2.0 * (L - 1); };
+    const double ts = (-4.0 + std::sqrt(16.0 + 96.0 * (L - 1))) / 24.0;  // minimum of q on t > 0
+    if (q(ts) < 0.0) {
+      t1 = cut_root(q, dq, 0.0, ts);  // q falls from q(0) = 1 through zero
+      double th = std::max(1.0, 2.0 * ts);
+      while (q(th) <= 0.0) th *= 2.0;
+      auto mq = [&](double t) { return -q(t); };
+      auto dmq = [&](double t) { return -dq(t); };
+      t2 = cut_root(mq, dmq, ts, th);  // q rises through zero
+    }
+  }
+  if (t2 > 0.0 && g(t2 / eta) > 0.0) {
+    const double lo = t2 / eta;
+    double hi = 2.0 * lo;
+    while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
+    if (g(hi) > 0) return hi;
+    return cut_root(g, dg, lo, hi);
+  }
   double lo = 1e-8, hi = 1.0;
   if (g(lo) < 0) return lo;
-  while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 52; ++it) {  // the bracket shrinks to 2^-52 of its width
-    const double mid = 0.5 * (lo + hi);
-    if (g(mid) > 0) lo = mid;
-    else hi = mid;
+  if (t1 > 0.0) {
+    hi = t1 / eta;  // g(hi) <= g(t2 / eta) <= 0
+    if (hi <= lo) return lo;
+  } else {
+    while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
+    if (g(hi) > 0) return hi;
   }
-  return hi;
+  return cut_root(g, dg, lo, hi);
 }
 
 // largest x with NF * x exp(-beta x^2) >= eps, or 0 (Eq. S23)
@@ -258,46 +416,35 @@ double solve_r12(double NF, double beta, double eps) {
   if (!(NF > 0.0) || NF * xs * std::exp(-0.5) < eps) return 0.0;
   const double c0 = std::log(NF) - std::log(eps);
   auto g = [&](double x) { return c0 + std::log(x) - beta * x * x; };
+  auto dg = [&](double x) { return 1.0 / x - 2.0 * beta * x; };
   double lo = xs, hi = 2.0 * xs;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 52; ++it) {  // the bracket shrinks to 2^-52 of its width
-    const double mid = 0.5 * (lo + hi);
-    if (g(mid) > 0) lo = mid;
-    else hi = mid;
-  }
-  return hi;
+  if (g(hi) > 0) return hi;
+  return cut_root(g, dg, lo, hi);
 }
 
 // largest x with NF x exp(-beta x^2) (1 + c x)^L >= eps, or 0 (Eq. S23 with the
 // angular growth of an l_a + l_b = L pair factor); the left side has one
-// maximum on x > 0, found by bisection on its logarithmic derivative
+// maximum on x > 0, where its logarithmic derivative (a falling function)
+// changes sign
 double solve_r12_grow(double NF, double beta, double eps, int L, double c) {
   if (L == 0) return solve_r12(NF, beta, eps);
   if (!(NF > 0.0)) return 0.0;
   auto dlog = [&](double x) { return 1.0 / x - 2.0 * beta * x + L * c / (1.0 + c * x); };
+  auto ddlog = [&](double x) { return -1.0 / (x * x) - 2.0 * beta - L * c * c / ((1.0 + c * x) * (1.0 + c * x)); };
   double lo = 1e-12, hi = 1.0;
   while (dlog(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 60; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (dlog(mid) > 0) lo = mid;
-    else hi = mid;
-  }
-  const double xm = hi;
+  const double xm = dlog(hi) > 0 ? hi : cut_root(dlog, ddlog, lo, hi);
   const double c0 = std::log(NF) - std::log(eps);
   auto g = [&](double x) { return c0 + std::log(x) - beta * x * x + L * std::log1p(c * x); };
   if (g(xm) < 0) return 0.0;
   lo = xm;
   hi = 2.0 * xm;
   while (g(hi) > 0 && hi < 1e6) hi *= 2.0;
-  for (int it = 0; it < 52; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (g(mid) > 0) lo = mid;
-    else hi = mid;
-  }
-  return hi;
+  if (g(hi) > 0) return hi;
+  return cut_root(g, dlog, lo, hi);
 }
 
-// f(i) for i < n on up to 16 host threads, in chunks of `grain` indices
 template <class F>
 void parallel_for(int64_t n, F f, int64_t grain = 64) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -739,6 +886,19 @@ const char *rsgdf_last_error(void) { return g_err.c_str(); }
 
 const char *rsgdf_version(void) { return "rsgdf-mi355x 0.1 (gfx950)"; }
 
+int rsgdf_release_cache(void) {
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  while (!g_cache.empty()) {
+    const int dev = g_cache.front().dev;
+    HIPCHK(hipSetDevice(dev));
+    cache_trim_locked(dev, 0);
+  }
+  HIPCHK(hipSetDevice(cur));
+  return RSGDF_OK;
+}
+
 int64_t rsgdf_j3c_nbytes(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                          const int32_t kmesh[3]) {
   if (!cell || !basis || !auxbasis || !kmesh || cell->natm < 1 || !cell->coords) {
@@ -837,6 +997,7 @@ struct Job {
   std::vector<double> kph;
   DBuf d_kph, d_kdiag, d_SP, d_O, d_Smn, d_kp1, d_tk2, d_tkp, d_Y;
   int ftiles = 0;         // k-pair tiles of the fold's second transform
+  int ftk = 4;            // k-pair slots per tile
   int64_t fchunk = 1;     // output elements per fold pass
   double *ybuf = nullptr; // the fold's intermediate: d_Y, or a batch's shared buffer
   bool own_y = true;      // false: the batch allocates one Y for all its cells (their folds run in turn)
@@ -997,17 +1158,21 @@ int Job::prepare(hipStream_t st, double mem_frac) {
     d_out = d_outbuf.as<double>();
   }
 
-  // phase table kphase[k][c] = e^{+i k.L_c}; the fold's k-pair tiles: up to 16
-  // k-pairs (k1, k2) of one k2 each
+  // phase table kphase[k][c] = e^{+i k.L_c}; the fold's k-pair tiles: up to
+  // ftk (a multiple of 4, at most 64) k-pairs (k1, k2) of one k2 each, as many
+  // as the k2 with the most k-pairs has
   kph = mesh_phases(L);
   {
     std::vector<std::vector<int32_t>> by_k2(nk);
     for (int t = 0; t < nkp; ++t) by_k2[hp.kp2[t]].push_back(t);
+    size_t most = 1;
+    for (auto &v : by_k2) most = std::max(most, v.size());
+    ftk = (int)std::min<size_t>(64, (most + 3) / 4 * 4);
     std::vector<int32_t> tk2, tkp;
     for (int k2 = 0; k2 < nk; ++k2)
-      for (size_t i = 0; i < by_k2[k2].size(); i += 16) {
+      for (size_t i = 0; i < by_k2[k2].size(); i += ftk) {
         tk2.push_back(k2);
-        for (size_t j = i; j < i + 16; ++j) tkp.push_back(j < by_k2[k2].size() ? by_k2[k2][j] : -1);
+        for (size_t j = i; j < i + ftk; ++j) tkp.push_back(j < by_k2[k2].size() ? by_k2[k2][j] : -1);
       }
     ftiles = (int)tk2.size();
     std::vector<int32_t> kp1(hp.kp1.begin(), hp.kp1.end());
@@ -1552,6 +1717,7 @@ int Job::enqueue_fold(int b, hipStream_t st) {
   fp.nk = nk;
   fp.nao2 = (int32_t)nao2;
   fp.ntile = ftiles;
+  fp.tk = ftk;
   HIPCHK(launch_fold(fp, st));
   return RSGDF_OK;
 }
@@ -2036,8 +2202,8 @@ int rsgdf_batch_create(int32_t ncell, const rsgdf_cell *cells, const rsgdf_basis
     for (auto &j : B->jobs)
       if (j->do_sr) ymax = std::max(ymax, (double)j->max_bf_el * j->nk * j->nk * 16.0);
     if (ymax > 0.0) {
-      size_t fr = 0, tt = 0;
-      HIPCHK(hipMemGetInfo(&fr, &tt));
+      size_t fr = 0;
+      HIPCHK(mem_avail(&fr));
       const double ybytes = std::min({ymax, 0.25 * 0.9 * (double)fr, 8e9});
       size_t need_b = 0;
       for (auto &j : B->jobs)

@@ -8,11 +8,10 @@
 //     Y[c1][k2][e]  = sum_c2 e^{+i k2.L_c2} X[c1][c2][e]          (real input)
 //     out[kp][e]    = sum_c1 e^{-i k1.L_c1} Y[c1][k2][e],  kp = (k1, k2), k1 <= k2
 // over the output elements e = (P, mu, nu) of one aux batch, taken in chunks of
-// E elements (Y holds Nk^2 complex values per element).  Both stages take 64
-// elements x 16 transform outputs per workgroup (4 outputs per wavefront), the
-// element values staged through LDS 32 cells at a time, the phases read by
-// scalar loads.  Per element this is 2 Nk^3 + 4 Nk Nkp multiply-adds instead of
-// 2 Nk^2 Nkp.  The second stage's epilogue subtracts pi/(Omega w^2) S_P S_{mu nu}(k)
+// E elements (Y holds Nk^2 complex values per element).  Both stages run on
+// the FP64 matrix cores, 64 elements x up to 64 transform outputs per
+// workgroup, so that each reads its input about once.  Per element this is
+// 2 Nk^3 + 4 Nk Nkp multiply-adds instead of 2 Nk^2 Nkp.  The second stage's epilogue subtracts pi/(Omega w^2) S_P S_{mu nu}(k)
 // on the k1 == k2 pairs.
 #include <hip/hip_runtime.h>
 
@@ -22,136 +21,186 @@
 
 namespace rsgdf {
 
-constexpr int FD_TE = 64;  // elements per tile
-constexpr int FD_TK = 16;  // transform outputs (k2, or k-pairs of one k2) per tile
-constexpr int FD_TC = 32;  // cells per LDS stage
+typedef double fd_d4 __attribute__((ext_vector_type(4)));
+typedef double fd_d2 __attribute__((ext_vector_type(2)));
+constexpr int FD_TE = 64;     // elements per workgroup: 4 column blocks of 16
+constexpr int FD_TKMAX = 64;  // k-pair slots per stage-2 tile at most (4 wavefronts of 16)
 
-// stage 1: grid (element tiles of the chunk, k2 tiles, c1).  The four
-// transform outputs of a wavefront are the same for its 64 lanes, so their
-// phases are read with scalar loads (the wave index is made uniform), and LDS
-// holds only the X tile: one LDS read per eight multiply-adds.
+// Both stages are products with the phase table on the FP64 matrix cores
+// (v_mfma_f64_16x16x4): a wavefront owns 16 transform outputs (rows) x 64
+// elements (4 column blocks), four cells per step.  Fragments (li = lane % 16,
+// lg = lane / 16): A[li][lg] = the phase of row li at cell 4 s + lg, B[lg][li]
+// = the input of that cell at element li of the block, result D[lg + 4 v][li].
+// The phases of a lane's row are one 16-byte load per step, the inputs are
+// read straight from memory (the wavefronts of a workgroup share them in the
+// caches).  Rows past the end read a valid phase row and are not stored; cells
+// past nk get zero phases; elements past the chunk read the last element and
+// are not stored.
+
+// stage 1: grid (element tiles of the chunk, k2 groups of 16 W, c1), W
+// wavefronts per workgroup, wavefront w taking k2 = 16 (W y + w) .. + 16:
+//   Yr[k2][e] = sum_c2 cos(k2.L_c2) X[c1][c2][e],  Yi likewise with sin
 __global__ __launch_bounds__(256) void fold_k2_kernel(const FoldParams fp, int64_t e0, int64_t E) {
-  __shared__ double sX[FD_TC][FD_TE];
-  const int tx = threadIdx.x & 63;
-  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // 4 outputs per wave
-  const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
-  const int k20 = blockIdx.y * FD_TK, c1 = blockIdx.z, nk = fp.nk;
-  // phase rows of the wave's outputs (a row past nk repeats a valid one; its sums are not stored)
-  const double *ph[4];
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int nk = fp.nk, c1 = blockIdx.z;
+  const int kb = blockIdx.y * (blockDim.x >> 6) + (threadIdx.x >> 6);  // 16-row block of k2
+  if (kb * 16 >= nk) return;  // no barriers below
+  const double *pha = fp.kph + 2 * (size_t)min(kb * 16 + li, nk - 1) * nk;
+  const int64_t eb = (int64_t)blockIdx.x * FD_TE;
+  const double *xc = fp.X + (int64_t)c1 * nk * fp.ne + e0;  // X[c1][c][e0 + e] at xc[c ne + e]
+  int64_t ecol[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int k2 = k20 + ty * 4 + j;
-    ph[j] = fp.kph + 2 * (size_t)(k2 < nk ? k2 : nk - 1) * nk;
-  }
-  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-  for (int c0 = 0; c0 < nk; c0 += FD_TC) {
-    for (int i = threadIdx.x; i < FD_TC * FD_TE; i += 256) {
-      const int cc = i / FD_TE, ee = i % FD_TE;
-      const int64_t eg = (int64_t)blockIdx.x * FD_TE + ee;
-      sX[cc][ee] = (c0 + cc < nk && eg < E) ? fp.X[(int64_t)(c1 * nk + c0 + cc) * fp.ne + e0 + eg] : 0.0;
+  for (int cb = 0; cb < 4; ++cb) ecol[cb] = min(eb + cb * 16 + li, E - 1);
+  fd_d4 yc[4], ys[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) yc[cb][v] = ys[cb][v] = 0.0;
+  // two register sets in turn: the operands of one step are loaded while the
+  // matrix cores work on the other (a load's cell is clamped into range; the
+  // products of cells past nk take zero phases)
+  struct Ops {
+    double ac, as, x[4];
+  };
+  auto load = [&](int c0, Ops &o) {
+    const int c = c0 + lg, cr = min(c, nk - 1);
+    const fd_d2 p = *reinterpret_cast<const fd_d2 *>(pha + 2 * cr);
+    o.ac = c < nk ? p.x : 0.0;
+    o.as = c < nk ? p.y : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) o.x[cb] = xc[(int64_t)cr * fp.ne + ecol[cb]];
+  };
+  auto step = [&](const Ops &o) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      yc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.ac, o.x[cb], yc[cb], 0, 0, 0);
+      ys[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.as, o.x[cb], ys[cb], 0, 0, 0);
     }
-    __syncthreads();
-    const int nc = nk - c0 < FD_TC ? nk - c0 : FD_TC;
-#pragma unroll 4
-    for (int cc = 0; cc < nc; ++cc) {
-      const double x = sX[cc][tx];
+  };
+  Ops oa, ob;
+  load(0, oa);
+  for (int c0 = 0; c0 < nk; c0 += 8) {
+    load(c0 + 4, ob);
+    step(oa);
+    load(c0 + 8, oa);
+    if (c0 + 4 < nk) step(ob);
+  }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ar[j] += ph[j][2 * (c0 + cc)] * x;
-        ai[j] += ph[j][2 * (c0 + cc) + 1] * x;
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k2 = kb * 16 + lg + 4 * v;
+      const int64_t e = eb + cb * 16 + li;
+      if (k2 < nk && e < E) {
+        const int64_t o = ((int64_t)c1 * nk + k2) * E + e;
+        fp.Y[2 * o] = yc[cb][v];
+        fp.Y[2 * o + 1] = ys[cb][v];
       }
     }
-    __syncthreads();
-  }
-  if (e >= E) return;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int k2 = k20 + ty * 4 + j;
-    if (k2 >= nk) continue;
-    const int64_t o = ((int64_t)c1 * nk + k2) * E + e;
-    fp.Y[2 * o] = ar[j];
-    fp.Y[2 * o + 1] = ai[j];
-  }
 }
 
 // stage 2: grid (element tiles of the chunk, k-pair tiles); a tile holds up to
-// 16 k-pairs (k1, k2) sharing k2, so the staged Y rows serve all of them; the
-// phases e^{-i k1.L_c1} of a wavefront's four k-pairs by scalar loads
+// fp.tk (<= 64) k-pairs (k1, k2) sharing k2, one tile per k2 when they fit,
+// wavefront w its slots 16 w .. + 16 (a wavefront whose first slot is empty has
+// none and returns).  With the table entry (c, s) of k1 at c1:
+//   out_re += c Yr + s Yi,  out_im += c Yi - s Yr     (e^{-i k1.L_c1} = c - i s)
+// and on the k1 == k2 pairs the G = 0 term is subtracted.
 __global__ __launch_bounds__(256) void fold_k1_kernel(const FoldParams fp, int64_t e0, int64_t E) {
-  __shared__ double sYr[FD_TC][FD_TE], sYi[FD_TC][FD_TE];
-  const int tx = threadIdx.x & 63;
-  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t e = (int64_t)blockIdx.x * FD_TE + tx;
-  const int tile = blockIdx.y, nk = fp.nk;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4, w = threadIdx.x >> 6;
+  const int tile = blockIdx.y, nk = fp.nk, tk = fp.tk;
+  const int32_t *slots = fp.tile_kp + (size_t)tile * tk;
+  if (w * 16 >= tk || slots[w * 16] < 0) return;  // slots are filled in order; no barriers below
   const int k2 = fp.tile_k2[tile];
-  const double *ph[4];
-  bool on[4];
+  const int sa = w * 16 + li;
+  const int kpa = sa < tk ? slots[sa] : -1;
+  const double *pha = fp.kph + 2 * (size_t)(kpa >= 0 ? fp.kp1[kpa] : 0) * nk;
+  const int64_t eb = (int64_t)blockIdx.x * FD_TE;
+  int64_t ecol[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int kp = fp.tile_kp[tile * FD_TK + ty * 4 + j];
-    on[j] = kp >= 0;
-    ph[j] = fp.kph + 2 * (size_t)(on[j] ? fp.kp1[kp] : 0) * nk;  // an unused slot reads row 0
-  }
-  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  for (int cb = 0; cb < 4; ++cb) ecol[cb] = min(eb + cb * 16 + li, E - 1);
+  fd_d4 orr[4], oi[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) orr[cb][v] = oi[cb][v] = 0.0;
   if (fp.Y) {
-    for (int c0 = 0; c0 < nk; c0 += FD_TC) {
-      for (int i = threadIdx.x; i < FD_TC * FD_TE; i += 256) {
-        const int cc = i / FD_TE, ee = i % FD_TE;
-        const int64_t eg = (int64_t)blockIdx.x * FD_TE + ee;
-        const bool ok = c0 + cc < nk && eg < E;
-        const int64_t o = ((int64_t)(c0 + cc) * nk + k2) * E + eg;
-        sYr[cc][ee] = ok ? fp.Y[2 * o] : 0.0;
-        sYi[cc][ee] = ok ? fp.Y[2 * o + 1] : 0.0;
-      }
-      __syncthreads();
-      const int nc = nk - c0 < FD_TC ? nk - c0 : FD_TC;
-#pragma unroll 4
-      for (int cc = 0; cc < nc; ++cc) {
-        const double yr = sYr[cc][tx], yi = sYi[cc][tx];
+    // two register sets in turn, as in stage 1
+    const double *yk = fp.Y + 2 * (int64_t)k2 * E;  // Y[c1][k2][e] at yk[2 (c1 nk E + e)]
+    struct Ops {
+      double ac, as;
+      fd_d2 y[4];
+    };
+    auto load = [&](int c0, Ops &o) {
+      const int c = c0 + lg, cr = min(c, nk - 1);
+      const fd_d2 p = *reinterpret_cast<const fd_d2 *>(pha + 2 * cr);
+      o.ac = c < nk ? p.x : 0.0;
+      o.as = c < nk ? p.y : 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          // e^{-i k1.L_c1} = conjugate of the table entry
-          const double pr = ph[j][2 * (c0 + cc)], pi = -ph[j][2 * (c0 + cc) + 1];
-          ar[j] += pr * yr - pi * yi;
-          ai[j] += pr * yi + pi * yr;
-        }
+      for (int cb = 0; cb < 4; ++cb)
+        o.y[cb] = *reinterpret_cast<const fd_d2 *>(yk + 2 * ((int64_t)cr * nk * E + ecol[cb]));
+    };
+    auto step = [&](const Ops &o) {
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        orr[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.ac, o.y[cb].x, orr[cb], 0, 0, 0);
+        oi[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.ac, o.y[cb].y, oi[cb], 0, 0, 0);
       }
-      __syncthreads();
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        orr[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.as, o.y[cb].y, orr[cb], 0, 0, 0);
+        oi[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-o.as, o.y[cb].x, oi[cb], 0, 0, 0);
+      }
+    };
+    Ops oa, ob;
+    load(0, oa);
+    for (int c0 = 0; c0 < nk; c0 += 8) {
+      load(c0 + 4, ob);
+      step(oa);
+      load(c0 + 8, oa);
+      if (c0 + 4 < nk) step(ob);
     }
   }
-  if (e >= E) return;
-  const int64_t eb = e0 + e;  // element index within the aux batch
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (!on[j]) continue;
-    const int kp = fp.tile_kp[tile * FD_TK + ty * 4 + j];
-    double vr = ar[j], vi = ai[j];
+  for (int v = 0; v < 4; ++v) {
+    const int sl = w * 16 + lg + 4 * v;
+    const int kp = sl < tk ? slots[sl] : -1;
+    if (kp < 0) continue;
     const int k = fp.kdiag[kp];
-    if (k >= 0 && fp.g0fac != 0.0) {
-      const int64_t P = eb / fp.nao2, mn = eb - P * fp.nao2;
-      const double s = fp.g0fac * fp.SP[P];
-      vr -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn)];
-      vi -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn) + 1];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int64_t e = eb + cb * 16 + li;
+      if (e >= E) continue;
+      const int64_t ebat = e0 + e;  // element index within the aux batch
+      double vr = orr[cb][v], vi = oi[cb][v];
+      if (k >= 0 && fp.g0fac != 0.0) {
+        const int64_t P = ebat / fp.nao2, mn = ebat - P * fp.nao2;
+        const double s = fp.g0fac * fp.SP[P];
+        vr -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn)];
+        vi -= s * fp.Smn[2 * ((int64_t)k * fp.nao2 + mn) + 1];
+      }
+      const int64_t o = (int64_t)kp * fp.plane + fp.out_off + ebat;
+      fp.out[2 * o] = vr;
+      fp.out[2 * o + 1] = vi;
     }
-    const int64_t o = (int64_t)kp * fp.plane + fp.out_off + eb;
-    fp.out[2 * o] = vr;
-    fp.out[2 * o + 1] = vi;
   }
 }
 
 hipError_t launch_fold(const FoldParams &fp, hipStream_t stream) {
   if (fp.ne == 0 || fp.ntile == 0) return hipSuccess;
   if (fp.echunk < 1 || (fp.X && !fp.Y)) return hipErrorInvalidValue;
+  if (fp.tk < 4 || fp.tk > FD_TKMAX || fp.tk % 4 != 0 || fp.nk < 1) return hipErrorInvalidValue;
+  // stage 1: up to 4 wavefronts (64 k2) per workgroup; stage 2: one per 16 slots
+  const int nkb = (fp.nk + 15) / 16, w1 = nkb < 4 ? nkb : 4, w2 = (fp.tk + 15) / 16;
   for (int64_t e0 = 0; e0 < fp.ne; e0 += fp.echunk) {
     const int64_t E = fp.ne - e0 < fp.echunk ? fp.ne - e0 : fp.echunk;
     const int64_t nt = (E + FD_TE - 1) / FD_TE;
     if (nt > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (fp.X)
-      hipLaunchKernelGGL(fold_k2_kernel, dim3((unsigned)nt, (unsigned)((fp.nk + FD_TK - 1) / FD_TK), (unsigned)fp.nk),
-                         dim3(256), 0, stream, fp, e0, E);
+      hipLaunchKernelGGL(fold_k2_kernel, dim3((unsigned)nt, (unsigned)((nkb + w1 - 1) / w1), (unsigned)fp.nk),
+                         dim3(64 * w1), 0, stream, fp, e0, E);
     FoldParams f2 = fp;
     if (!fp.X) f2.Y = nullptr;  // no short-range part: zeros plus the G = 0 term
-    hipLaunchKernelGGL(fold_k1_kernel, dim3((unsigned)nt, (unsigned)fp.ntile), dim3(256), 0, stream, f2, e0, E);
+    hipLaunchKernelGGL(fold_k1_kernel, dim3((unsigned)nt, (unsigned)fp.ntile), dim3(64 * w2), 0, stream, f2, e0, E);
   }
   return hipGetLastError();
 }

@@ -16,7 +16,7 @@ struct FoldParams {
   const int32_t *kdiag;   // [nkp]: k index if k1 == k2 else -1
   const int32_t *kp1;     // [nkp]: k1 of each k-pair
   const int32_t *tile_k2; // [ntile]: k2 of the tile's k-pairs
-  const int32_t *tile_kp; // [ntile][16]: k-pair indices of the tile, -1 padded
+  const int32_t *tile_kp; // [ntile][tk]: k-pair indices of the tile, -1 padded
   const double *SP;       // [naux_b] lattice-free aux integrals int chi_P
   const double *Smn;      // complex [nk][nao*nao]
   double g0fac;           // pi / (Omega w^2), 0 disables the G = 0 term
@@ -25,6 +25,7 @@ struct FoldParams {
   int64_t out_off;        // aux_f0 * nao * nao
   int64_t plane;          // naux * nao * nao
   int32_t nkp, nk, nao2, ntile;
+  int32_t tk;             // k-pair slots per tile: a multiple of 4, at most 64
 };
 
 struct OvlParams {

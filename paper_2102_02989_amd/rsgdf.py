@@ -143,6 +143,8 @@ def library():
         L.rsgdf_autotune_sr.restype = ctypes.c_int
         L.rsgdf_autotune_sr.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                         ctypes.c_double, ctypes.c_double, P, P, P]
+        L.rsgdf_release_cache.restype = ctypes.c_int
+        L.rsgdf_release_cache.argtypes = []
         L.rsgdf_last_error.restype = ctypes.c_char_p
         L.rsgdf_version.restype = ctypes.c_char_p
         _lib = L
@@ -151,6 +153,14 @@ def library():
 
 def version() -> str:
     return library().rsgdf_version().decode()
+
+
+def release_cache() -> None:
+    """Free the library's idle cached device blocks (rsgdf_release_cache).
+
+    The large scratch buffers of a build are kept for the next one; call this
+    to give their memory back to the device."""
+    _check(library().rsgdf_release_cache())
 
 
 class _Marshal:

@@ -147,6 +147,12 @@ def main():
             raise SystemExit(f"batch run: {L.rsgdf_last_error()}")
     L.rsgdf_batch_destroy(h)
 
+    # the idle cached blocks of the builds above are freed
+    rc = L.rsgdf_release_cache()
+    say("case release cache rc", rc)
+    if rc != 0:
+        raise SystemExit(f"release cache: {L.rsgdf_last_error()}")
+
     # error paths: each is refused with a negative code and no access out of bounds
     say("case error paths")
     p = synth.config1()

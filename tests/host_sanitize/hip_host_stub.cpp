@@ -81,6 +81,9 @@ hipError_t hipGetDevice(int *d) {
   *d = 0;
   return hipSuccess;
 }
+hipError_t hipSetDevice(int) { return hipSuccess; }
+hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipDeviceSynchronize() { return hipSuccess; }
 const char *hipGetErrorString(hipError_t) { return "host stub error"; }
 hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
   *p = const_cast<void *>(symbol);

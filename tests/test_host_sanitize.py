@@ -54,6 +54,7 @@ def test_host_driver_under_asan_ubsan(sanitized_lib):
     assert "ERROR: AddressSanitizer" not in log and "runtime error:" not in log, log[-6000:]
     assert log.rstrip().endswith("done"), log[-3000:]
     # every input was planned and built, the batch ran twice, each malformed input was refused
-    for case in ("case tiny 2x1x1", "case tiny 1x2x2", "case C1", "case C2", "batch run rc 0", "case error paths"):
+    for case in ("case tiny 2x1x1", "case tiny 1x2x2", "case C1", "case C2", "batch run rc 0",
+                 "case release cache rc 0", "case error paths"):
         assert case in log, case
     assert log.count("error path ") == 16
