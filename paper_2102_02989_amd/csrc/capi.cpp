@@ -1774,8 +1774,13 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
         pp.acut = acut;
         pp.pmode = pt.pmode;
         HIPCHK(launch_pairft_binned(pp, st));
-        const int nq_hi = (q0 == 0 && f32) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
-        const bool split = o.lr_precision == RSGDF_F16X3;
+        // A class of at most 4 nq_hi q is contracted in FP64 in every form: the
+        // reduced-precision kernels would take its first nq_hi q (or all of them)
+        // in FP64 on the vector ALUs, slower than the FP64 matrix-core kernel,
+        // and FP64 is the more accurate.
+        const int prec = (f32 && q0 == 0 && nqc <= 4 * lr_nq_hi) ? RSGDF_FP64 : o.lr_precision;
+        const int nq_hi = (q0 == 0 && prec != RSGDF_FP64) ? lr_nq_hi : 0;  // q sorted by |q|: the class's innermost shell
+        const bool split = prec == RSGDF_F16X3;
         const int nb = f16_nblk(nq);
         // split format: halves, then the exponents at a 256-byte boundary
         uint16_t *Xa = d_Asp.as<uint16_t>(), *Xb = d_B.as<uint16_t>();
@@ -1787,15 +1792,15 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
           HIPCHK(launch_kphase_split(d_I.as<double>(), d_ph.as<double>() + 2 * ph_off[c], Xb, Eb,
                                      nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
         } else {
-          HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * ph_off[c], d_B.p, f32,
+          HIPCHK(launch_kphase(d_I.as<double>(), d_ph.as<double>() + 2 * ph_off[c], d_B.p, prec == RSGDF_FP32,
                                nq_hi ? d_Bhi.as<double>() : nullptr, nq_hi, nk, nkpi, nq, nao2, st));
         }
         LRGemmParams gp{};
         gp.A = pt.d_A.as<double>() + 2 * (pt.qoff[c] + q0);
         gp.lda = pt.nq_tot;
         gp.B = d_B.as<double>();
-        gp.A32 = o.lr_precision == RSGDF_FP32 ? pt.d_A32.as<float>() + 2 * (pt.qoff[c] + q0) : nullptr;
-        gp.B32 = o.lr_precision == RSGDF_FP32 ? d_B.as<float>() : nullptr;
+        gp.A32 = prec == RSGDF_FP32 ? pt.d_A32.as<float>() + 2 * (pt.qoff[c] + q0) : nullptr;
+        gp.B32 = prec == RSGDF_FP32 ? d_B.as<float>() : nullptr;
         if (split) {
           gp.Xa = Xa;
           gp.Ea = Ea;
@@ -1819,7 +1824,7 @@ int Job::enqueue_lr(hipStream_t st, std::vector<hipEvent_t> *gev) {
           gev->push_back(e1);
           HIPCHK(hipEventRecord(e0, st));
         }
-        HIPCHK(launch_lr_gemm_tiled(o.lr_precision, gp, 0, nkpi, st));
+        HIPCHK(launch_lr_gemm_tiled(prec, gp, 0, nkpi, st));
         if (gev) HIPCHK(hipEventRecord(e1, st));
         lr_flops += 8.0 * (double)naux * nq * (double)nao2 * nkpi;
       }

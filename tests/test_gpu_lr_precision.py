@@ -46,3 +46,28 @@ def test_lr_forms_tiny_full(form):
     err = max_err(got, ref)
     _say("  max err", err)
     assert err <= tol
+
+
+def test_small_classes_contracted_in_fp64():
+    """A k12 class of at most 4 x 32 q is contracted in FP64 in every form (the
+    reduced-precision kernels would take its innermost 32 q in FP64 on the
+    vector ALUs anyway): on the 2x2x2 mesh at omega = 0.1 (56 q in 8 classes)
+    the FP32 and split-FP16 forms give the FP64 form's long-range part bit for
+    bit."""
+    import torch
+
+    import paper_2102_02989_amd as P
+    p = synth.config2()
+    shape = (P.nkpairs(p.kmesh), p.aux.nfunc, p.basis.nfunc, p.basis.nfunc)
+    outs = {}
+    for name, prec in (("fp64", P.FP64), ("fp32", P.FP32), ("f16x3", P.F16X3)):
+        _say("case C2 LR form", name)
+        out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        _, st = P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, p.omega, p.thresh, out, g_thresh=p.g_thr,
+                            lr_precision=prec, parts=P.PART_LR)
+        torch.cuda.synchronize()
+        _say("  N_G", st["n_g_total"])
+        assert st["n_g_total"] <= 8 * 4 * 32
+        outs[name] = out
+    assert torch.equal(outs["fp32"], outs["fp64"])
+    assert torch.equal(outs["f16x3"], outs["fp64"])
