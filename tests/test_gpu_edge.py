@@ -89,9 +89,9 @@ def test_c2_diagonal_kpairs_hermitian():
 
 
 def test_large_mesh_sampled_kpairs():
-    """A 4x3x3 mesh (36 k-points, 666 k-pairs): more cells than one LDS stage of
-    the fold's transforms holds, several k2 tiles, and k2 values with more than
-    16 k-pairs; the oracle checks a spread of k-pairs, at thresh 1e-10 and 1e-11;
+    """A 4x3x3 mesh (36 k-points, 666 k-pairs): the fold's transforms take 36
+    rows in three 16-row blocks (the last one partial) and k-pair tiles of 36
+    slots; the oracle checks a spread of k-pairs, at thresh 1e-10 and 1e-11;
     the deviation must fall with thresh (it is the screening's; a fault in the
     fold would not scale)."""
     p = synth.tiny_problem(kmesh=(4, 3, 3), omega=0.8, diffuse=False)
@@ -107,3 +107,21 @@ def test_large_mesh_sampled_kpairs():
         _say("  thresh", thresh, "max err", errs[thresh], "max |ref|", np.abs(ref[sel]).max())
     assert errs[1e-10] <= TOL
     assert errs[1e-11] < errs[1e-10] / 3
+
+
+def test_mesh_beyond_one_fold_workgroup():
+    """A 5x5x3 mesh (75 k-points, 2850 k-pairs): more k2 than one workgroup of
+    the fold's first transform takes (64), and k2 values with more k-pairs
+    (up to 75) than one tile of the second (64), so both stages run several
+    workgroups per output row set; the oracle checks k-pairs from the first and
+    the split tiles."""
+    p = synth.tiny_problem(kmesh=(5, 5, 3), omega=0.8, diffuse=False)
+    nkp = oracle.nkpairs(p.kmesh)
+    sel = [0, 1, 63, 64, 74, 75, 2000, nkp - 2, nkp - 1]
+    _say("case tiny cell 5x5x3 mesh, k-pairs", sel)
+    ref = oracle.j3c(p, kpairs=sel)
+    got, _ = run_gpu(p)
+    assert got.shape[0] == nkp == 2850
+    err = max_err(got[sel], ref[sel])
+    _say("  max err", err, "max |ref|", np.abs(ref[sel]).max())
+    assert err <= TOL
