@@ -246,6 +246,24 @@ int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const 
 int rsgdf_choose_omega(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
                        const int32_t kmesh[3], double thresh, double g_thresh, const double *omegas, int32_t nomega,
                        const double coef[RSGDF_NFEATURES], double *best_omega, double *predicted_ms);
+/* The same with the compact/diffuse split (Fig. 1, Eq. M15; options.alpha_cut):
+ * rsgdf_plan_features_acut fills feat for one (omega, alpha_cut), alpha_cut = 0
+ * meaning no split (then it equals rsgdf_plan_features).  With the split the
+ * short-range features count only compact aux primitives and primitive pairs
+ * not both diffuse, and the long-range ones add the two Eq. M15 parts on their
+ * q spheres (q^2 <= 4 alpha_cut ln(1/g_thresh) for the diffuse aux primitives,
+ * twice that for the diffuse-diffuse pairs).  The split changes no result
+ * beyond the screening thresholds, so rsgdf_choose_params returns the grid point
+ * (omegas[i], acuts[j]) with the smallest predicted time, and the predictions
+ * predicted_ms[i * nacut + j] if not NULL.  RSGDF_EINVAL for null arguments,
+ * empty grids, omega <= 0 or alpha_cut < 0. */
+int rsgdf_plan_features_acut(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                             const int32_t kmesh[3], double omega, double alpha_cut, double thresh, double g_thresh,
+                             double feat[RSGDF_NFEATURES]);
+int rsgdf_choose_params(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                        const int32_t kmesh[3], double thresh, double g_thresh, const double *omegas, int32_t nomega,
+                        const double *acuts, int32_t nacut, const double coef[RSGDF_NFEATURES], double *best_omega,
+                        double *best_acut, double *predicted_ms);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

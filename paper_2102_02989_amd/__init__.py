@@ -27,6 +27,7 @@ from .rsgdf import (  # noqa: F401
     coulomb_direct,
     plan_features,
     choose_omega,
+    choose_params,
     build_j3c_noalloc,
     NOALLOC_SCRATCH_MB,
     j3c_nbytes,

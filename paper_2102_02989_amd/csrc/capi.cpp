@@ -2998,30 +2998,43 @@ int rsgdf_coulomb_direct(const rsgdf_cell *cell, const rsgdf_basis *basis, const
 // ---------------------------------------------------------------------------
 extern "C" {
 
-int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
-                        const int32_t kmesh[3], double omega, double thresh, double g_thresh,
-                        double feat[RSGDF_NFEATURES]) {
+int rsgdf_plan_features_acut(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                             const int32_t kmesh[3], double omega, double alpha_cut, double thresh, double g_thresh,
+                             double feat[RSGDF_NFEATURES]) {
   g_err.clear();
   if (!feat) return fail(RSGDF_EINVAL, "null feature array");
   const int64_t need = rsgdf_j3c_nbytes(cell, basis, auxbasis, kmesh);
   if (need < 0) return (int)need;
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(RSGDF_EINVAL, "omega must be > 0");
   if (!(thresh > 0.0) || !std::isfinite(thresh)) return fail(RSGDF_EINVAL, "thresh must be > 0");
+  if (!(alpha_cut >= 0.0) || !std::isfinite(alpha_cut)) return fail(RSGDF_EINVAL, "alpha_cut must be >= 0");
   const double g_thr = g_thresh > 0.0 ? g_thresh : 1e-2 * thresh;
+  const double acut = alpha_cut;
   HostPlan hp;
+  hp.acut = acut;
   int rc = build_plan(cell, basis, auxbasis, kmesh, omega, thresh, hp);
   if (rc) return rc;
   const Lattice &L = hp.lt.L;
   const int nk = L.nk, npair = (int)hp.pairs.size(), nxs = (int)hp.ax.size();
+  // primitives below the cut (the diffuse ones of the split, R28)
+  auto ndiff = [&](const Shell &s_, const std::vector<double> &ex) {
+    int n = 0;
+    if (acut > 0.0)
+      for (int k = 0; k < s_.nprim; ++k) n += ex[s_.pptr + k] < acut;
+    return n;
+  };
   // short range: the planner's per-item cost (primitive triples x pair images
   // x lattice vectors in the R_c ball x per-term operations, plus the
-  // per-(triple, image) contraction), summed over every (aux shell, pair)
+  // per-(triple, image) contraction), summed over every (aux shell, pair);
+  // with the split only compact aux primitives and pairs of primitives not
+  // both diffuse
   double sr = 0.0, sr_terms = 0.0;
   for (int P = 0; P < nxs; ++P)
     for (int ip = 0; ip < npair; ++ip) {
       const size_t t = (size_t)P * npair + ip;
       const Pair &pp = hp.pairs[ip];
       const Shell &sA = hp.ao[pp.sa], &sB = hp.ao[pp.sb], &sP = hp.ax[P];
+      if (acut > 0.0 && sP.a_d <= 0.0) continue;  // no compact primitive
       int64_t nimg = 0;
       for (int c = 0; c < nk; ++c) nimg += hp.nsr[(size_t)ip * nk + c];
       const double rc_cut = hp.rc_t[t];
@@ -3031,14 +3044,14 @@ int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const 
       const int nblk = ncart_h(sP.l) * ncart_h(sA.l) * ncart_h(sB.l);
       const double ev = 2.0 * nherm(Lt) + 2.0 * ncart_h(sP.l) * nherm(lab) * nkx + 2.0 * nblk * nherm(lab);
       const double nranges = std::ceil((double)nk / std::min(nk, sr_cells_per_wave(nblk)));
-      const double np3 = (double)sA.nprim * sB.nprim * sP.nprim * (double)nimg;
+      const double npp = (double)sA.nprim * sB.nprim - (double)ndiff(sA, hp.ao_exp) * ndiff(sB, hp.ao_exp);
+      const double np3 = npp * (sP.nprim - ndiff(sP, hp.ax_exp)) * (double)nimg;
       sr += np3 * (nm * sr_term_flops(Lt) + 13.6 * nranges * ev);
       sr_terms += np3 * nm;
     }
-  // long range: q vectors, pair-transform candidates, contraction flops
-  std::vector<double> qv;
-  std::vector<int64_t> qoff;
-  make_qsets(hp.lt, hp.kvec, omega, g_thr, qv, qoff);
+  // long range: q vectors, pair-transform candidates, contraction flops, per
+  // part (one part without the split; with it the range-separated part and
+  // the two Eq. M15 parts on their q spheres, R28)
   std::vector<int> kp_of_cls(nk, 0);
   for (size_t t = 0; t < hp.kp1.size(); ++t) {
     const int k1 = hp.kp1[t], k2 = hp.kp2[t];
@@ -3048,22 +3061,51 @@ int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const 
     for (int d = 0; d < 3; ++d) c = c * L.n[d] + ((j2[d] - j1[d]) % L.n[d] + L.n[d]) % L.n[d];
     kp_of_cls[c]++;
   }
-  double img_pp = 0.0;  // (primitive pair, image) units of the pair transforms, per q
+  // (primitive pair, image, component) units of the pair transforms per q:
+  // every pair (pmode 0), not both diffuse (1), both diffuse (2)
+  double img_pp[3] = {0.0, 0.0, 0.0};
   for (int ip = 0; ip < npair; ++ip) {
     const Pair &pp = hp.pairs[ip];
-    img_pp += (double)hp.ao[pp.sa].nprim * hp.ao[pp.sb].nprim * hp.cls_off[(size_t)ip * (nk + 1) + nk] *
-              ncart_h(hp.ao[pp.sa].l) * ncart_h(hp.ao[pp.sb].l);
+    const Shell &sA = hp.ao[pp.sa], &sB = hp.ao[pp.sb];
+    const double w = (double)hp.cls_off[(size_t)ip * (nk + 1) + nk] * ncart_h(sA.l) * ncart_h(sB.l);
+    const double all = (double)sA.nprim * sB.nprim, dd = (double)ndiff(sA, hp.ao_exp) * ndiff(sB, hp.ao_exp);
+    img_pp[0] += all * w;
+    img_pp[1] += (all - dd) * w;
+    img_pp[2] += dd * w;
   }
-  double nq = 0.0, gemm = 0.0, kphase = 0.0;
-  for (int c = 0; c < nk; ++c) {
-    const double nqc = (double)(qoff[c + 1] - qoff[c]);
-    if (kp_of_cls[c] == 0) continue;
-    nq += nqc;
-    gemm += 8.0 * (double)hp.naux * nqc * (double)hp.nao * hp.nao * kp_of_cls[c];
-    kphase += nqc * (double)hp.nao * hp.nao * (nk + kp_of_cls[c]);
+  struct Part {
+    std::vector<int64_t> qoff;
+    int pmode;
+  };
+  std::vector<Part> parts;
+  {
+    std::vector<double> qv;
+    Part rs;
+    make_qsets(hp.lt, hp.kvec, omega, g_thr, qv, rs.qoff);
+    rs.pmode = acut > 0.0 ? 1 : 0;
+    parts.push_back(rs);
+    if (acut > 0.0) {
+      Part d, c;
+      make_qsets_sphere(hp.lt, hp.kvec, 4.0 * acut * std::log(1.0 / g_thr), qv, d.qoff);
+      d.pmode = 0;
+      make_qsets_sphere(hp.lt, hp.kvec, 8.0 * acut * std::log(1.0 / g_thr), qv, c.qoff);
+      c.pmode = 2;
+      parts.push_back(d);
+      parts.push_back(c);
+    }
   }
+  double nq = 0.0, gemm = 0.0, kphase = 0.0, cand = 0.0;
+  for (const Part &pt : parts)
+    for (int c = 0; c < nk; ++c) {
+      const double nqc = (double)(pt.qoff[c + 1] - pt.qoff[c]);
+      if (kp_of_cls[c] == 0) continue;
+      nq += nqc;
+      cand += nqc * img_pp[pt.pmode];
+      gemm += 8.0 * (double)hp.naux * nqc * (double)hp.nao * hp.nao * kp_of_cls[c];
+      kphase += nqc * (double)hp.nao * hp.nao * (nk + kp_of_cls[c]);
+    }
   feat[0] = sr;                                              // SR operations (cost estimate)
-  feat[1] = nq * img_pp;                                     // pair-transform candidate components
+  feat[1] = cand;                                            // pair-transform candidate components
   feat[2] = gemm;                                            // contraction flops
   feat[3] = kphase;                                          // k2-phase elements read + written
   feat[4] = (double)hp.kp1.size() * hp.naux * hp.nao * hp.nao;  // output elements (fold, write-out)
@@ -3071,6 +3113,40 @@ int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const 
   feat[6] = nq;                                              // q vectors summed over the classes
   feat[7] = sr_terms;                                        // SR primitive terms (estimate)
   feat[8] = 1.0;                                             // per-build fixed cost
+  return RSGDF_OK;
+}
+
+int rsgdf_plan_features(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                        const int32_t kmesh[3], double omega, double thresh, double g_thresh,
+                        double feat[RSGDF_NFEATURES]) {
+  return rsgdf_plan_features_acut(cell, basis, auxbasis, kmesh, omega, 0.0, thresh, g_thresh, feat);
+}
+
+// argmin over the (omega, alpha_cut) grid of the predicted time sum_i coef[i] feat[i]
+int rsgdf_choose_params(const rsgdf_cell *cell, const rsgdf_basis *basis, const rsgdf_basis *auxbasis,
+                        const int32_t kmesh[3], double thresh, double g_thresh, const double *omegas, int32_t nomega,
+                        const double *acuts, int32_t nacut, const double coef[RSGDF_NFEATURES], double *best_omega,
+                        double *best_acut, double *predicted_ms) {
+  g_err.clear();
+  if (!omegas || nomega < 1 || !acuts || nacut < 1 || !coef || !best_omega || !best_acut)
+    return fail(RSGDF_EINVAL, "null argument or no candidates");
+  double best = 1e300;
+  int ib = -1;
+  for (int i = 0; i < nomega; ++i)
+    for (int j = 0; j < nacut; ++j) {
+      double f[RSGDF_NFEATURES];
+      const int rc = rsgdf_plan_features_acut(cell, basis, auxbasis, kmesh, omegas[i], acuts[j], thresh, g_thresh, f);
+      if (rc) return rc;
+      double t = 0.0;
+      for (int k = 0; k < RSGDF_NFEATURES; ++k) t += coef[k] * f[k];
+      if (predicted_ms) predicted_ms[(size_t)i * nacut + j] = t;
+      if (t < best) {
+        best = t;
+        ib = i * nacut + j;
+      }
+    }
+  *best_omega = omegas[ib / nacut];
+  *best_acut = acuts[ib % nacut];
   return RSGDF_OK;
 }
 

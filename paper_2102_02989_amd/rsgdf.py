@@ -110,6 +110,14 @@ def library():
         L.rsgdf_plan_features.restype = ctypes.c_int
         L.rsgdf_plan_features.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.rsgdf_plan_features_acut.restype = ctypes.c_int
+        L.rsgdf_plan_features_acut.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT),
+                                               P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               P]
+        L.rsgdf_choose_params.restype = ctypes.c_int
+        L.rsgdf_choose_params.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
+                                          ctypes.c_double, ctypes.c_double, P, ctypes.c_int32, P, ctypes.c_int32, P,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P]
         L.rsgdf_choose_omega.restype = ctypes.c_int
         L.rsgdf_choose_omega.argtypes = [ctypes.POINTER(Cell), ctypes.POINTER(BasisT), ctypes.POINTER(BasisT), P,
                                          ctypes.c_double, ctypes.c_double, P, ctypes.c_int32, P,
@@ -350,14 +358,33 @@ def coulomb_direct(cell, basis, aux, kmesh, omega, thresh, dm, vj=None, *, aux_g
 NFEATURES = 9
 
 
-def plan_features(cell, basis, aux, kmesh, omega, thresh, g_thresh=None) -> np.ndarray:
-    """rsgdf_plan_features: the cost-model features of one build (host only)."""
+def plan_features(cell, basis, aux, kmesh, omega, thresh, g_thresh=None, alpha_cut=0.0) -> np.ndarray:
+    """rsgdf_plan_features_acut: the cost-model features of one build (host only);
+    alpha_cut = 0 means no compact/diffuse split."""
     m = _Marshal(cell, basis, aux, kmesh)
     f = np.zeros(NFEATURES, np.float64)
-    _check(library().rsgdf_plan_features(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
-                                         m.kmesh.ctypes.data, float(omega), float(thresh),
-                                         -1.0 if g_thresh is None else float(g_thresh), f.ctypes.data))
+    _check(library().rsgdf_plan_features_acut(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                              m.kmesh.ctypes.data, float(omega), float(alpha_cut), float(thresh),
+                                              -1.0 if g_thresh is None else float(g_thresh), f.ctypes.data))
     return f
+
+
+def choose_params(cell, basis, aux, kmesh, thresh, coef, omegas, acuts, g_thresh=None):
+    """rsgdf_choose_params: (best omega, best alpha_cut, predicted ms [len(omegas)][len(acuts)])."""
+    m = _Marshal(cell, basis, aux, kmesh)
+    om = np.ascontiguousarray(omegas, np.float64)
+    ac = np.ascontiguousarray(acuts, np.float64)
+    cf = np.ascontiguousarray(coef, np.float64)
+    if cf.size != NFEATURES:
+        raise ValueError(f"expected {NFEATURES} coefficients")
+    pred = np.zeros((len(om), len(ac)), np.float64)
+    bo, ba = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(library().rsgdf_choose_params(ctypes.byref(m.cell), ctypes.byref(m.basis), ctypes.byref(m.aux),
+                                         m.kmesh.ctypes.data, float(thresh),
+                                         -1.0 if g_thresh is None else float(g_thresh), om.ctypes.data, len(om),
+                                         ac.ctypes.data, len(ac), cf.ctypes.data, ctypes.byref(bo), ctypes.byref(ba),
+                                         pred.ctypes.data))
+    return bo.value, ba.value, pred
 
 
 def choose_omega(cell, basis, aux, kmesh, thresh, coef, omegas, g_thresh=None):

@@ -1,8 +1,9 @@
-"""The automatic choice of omega on the GPU: the omega the committed cost
-model picks for the 8-atom cell on the 2x2x2 and 3x3x3 meshes gives
-integrals within the FP64 bar (1e-8 au) of the stored oracle blocks (the
-j3c does not depend on omega: Eq. M9 splits 1/r exactly), and a build at
-that omega is faster than at the configuration's own omega."""
+"""The automatic choice of omega (and of the compact/diffuse cut alpha_cut)
+on the GPU: the parameters the committed cost model picks for the 8-atom
+cell on the 2x2x2 and 3x3x3 meshes give integrals within the FP64 bar
+(1e-8 au) of the stored oracle blocks (the j3c depends on neither: Eq. M9
+splits 1/r exactly, Eq. M15 takes the diffuse triples without the split),
+and a build with them is faster than at the configuration's own omega."""
 import json
 import os
 import sys
@@ -17,6 +18,7 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 MODEL = os.path.join(os.path.dirname(HERE), "paper_2102_02989_amd", "data", "cost_model.json")
 OMEGAS = [0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0, 1.5]
+ACUTS = [0.0, 0.1, 0.3, 1.0]
 
 
 def _say(*a):
@@ -24,10 +26,10 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _build(P, p, omega, out):
+def _build(P, p, omega, out, acut=0.0):
     import torch
     t0 = time.perf_counter()
-    P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, omega, p.thresh, out, g_thresh=p.g_thr)
+    P.build_j3c(p.cell, p.basis, p.aux, p.kmesh, omega, p.thresh, out, g_thresh=p.g_thr, alpha_cut=acut)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3
 
@@ -56,5 +58,34 @@ def test_chosen_omega_parity_and_speed(name, golden):
     t_cfg = _build(P, p, p.omega, out)
     _say(f"  max err {err:.3e}; build {t_best:.0f} ms at omega {best} vs {t_cfg:.0f} ms at omega {p.omega} "
          f"({t_cfg / t_best:.2f}x)")
+    assert err <= 1e-8
+    assert t_best <= 1.1 * t_cfg
+
+
+def test_chosen_params_with_split_c2():
+    """The joint (omega, alpha_cut) choice on the 2x2x2 mesh: parity with the
+    stored oracle blocks and not slower than 1.1x the configuration's omega
+    without the split."""
+    import torch
+
+    import paper_2102_02989_amd as P
+    p = synth.config2()
+    coef = np.array(json.load(open(MODEL))["coef_fp64"])
+    bo, ba, pred = P.choose_params(p.cell, p.basis, p.aux, p.kmesh, p.thresh, coef, OMEGAS, ACUTS, g_thresh=p.g_thr)
+    _say(f"case auto omega and alpha_cut C2: chosen omega {bo}, alpha_cut {ba}; predicted best "
+         f"{float(pred.min()):.0f} ms")
+    out = torch.empty((P.nkpairs(p.kmesh), p.aux.nfunc, p.basis.nfunc, p.basis.nfunc), dtype=torch.complex128,
+                      device="cuda")
+    _build(P, p, bo, out, ba)  # warm-up
+    t_best = _build(P, p, bo, out, ba)
+    g = np.load(os.path.join(HERE, "golden", "c2_blocks_dd.npz"))
+    kp = torch.as_tensor(g["kpairs"], device="cuda")
+    rows = torch.as_tensor(g["rows"], device="cuda")
+    bo_ = p.basis.offsets()
+    sub = out.index_select(0, kp).index_select(1, rows)
+    err = max(float(np.abs(sub[:, :, bo_[mu]:bo_[mu + 1], bo_[nu]:bo_[nu + 1]].cpu().numpy()
+                           - g[f"pair_{mu}_{nu}"]).max()) for mu, nu in g["pairs"])
+    t_cfg = _build(P, p, p.omega, out)
+    _say(f"  max err {err:.3e}; build {t_best:.0f} ms vs {t_cfg:.0f} ms at omega {p.omega} ({t_cfg / t_best:.2f}x)")
     assert err <= 1e-8
     assert t_best <= 1.1 * t_cfg
