@@ -297,8 +297,19 @@ void sr3c_kernel(const SRParams *__restrict__ prms, const SRWork *__restrict__ w
           }
           const int ic = comp / (NCA * NCB), ia = (comp / NCB) % NCA, ib = comp % NCB;
           const size_t rowP = (size_t)(pf0 + ic) * prm.nao;
-          X12[(rowP + shA.foff + ia) * prm.nao + shB.foff + ib] += v;
-          if (!pr.diag) X21[(rowP + shB.foff + ib) * prm.nao + shA.foff + ia] += v;
+          double *x12 = X12 + (rowP + shA.foff + ia) * prm.nao + shB.foff + ib;
+          double *x21 = X21 + (rowP + shB.foff + ib) * prm.nao + shA.foff + ia;
+          // Outside logging runs each element is flushed once: the class's
+          // images are contiguous in the list, the item's cell range is its
+          // own, and the transposed block lies in the other shell's rows.  X
+          // starts at zero, so a store replaces the read-modify-write.
+          if (logging) {
+            *x12 += v;
+            if (!pr.diag) *x21 += v;
+          } else {
+            *x12 = v;
+            if (!pr.diag) *x21 = v;
+          }
         }
       }
     };
