@@ -115,8 +115,13 @@ hipError_t launch_auxft(const AuxFTParams &ap, hipStream_t stream) {
 // q values per lane: the image-dependent work of a term (Gaussian factor,
 // bound, pair centre, E coefficients) is the same for every q, so the lanes of
 // the lighter classes take several q each and do it once for all of them (s-s
-// four, up to l_a + l_b = 3 two; the d-d accumulators leave no registers for more)
-__host__ __device__ constexpr int pairft_qpl(int la, int lb) { return la + lb == 0 ? 4 : (la + lb <= 3 ? 2 : 1); }
+// eight, p-s four, up to l_a + l_b = 3 two; the d-d accumulators leave no
+// registers for more).  Measured on the 8-atom 3x3x3 workload: s-s 4 -> 8 and
+// p-s 2 -> 4 took the long-range phase from 5.39 to 5.10 s; p-s 6 or
+// l_a + l_b = 2 at four were slower.
+__host__ __device__ constexpr int pairft_qpl(int la, int lb) {
+  return la + lb == 0 ? 8 : (la + lb == 1 ? 4 : (la + lb <= 3 ? 2 : 1));
+}
 
 template <int LA, int LB>
 __device__ long long pairft_binned_one(const PairFTParams &pp, int ip, int c, int iq0) {
