@@ -136,13 +136,13 @@ hipError_t launch_lr_gemm_tiled(int mode, const LRGemmParams &gp, int q_lo, int 
 hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream);
 hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *amax, hipStream_t stream);
 // k-pairs summed per pass of the k2-phase kernels for a class of nkpi k-pairs
-// (up to 28, even passes, rounded up to 4), and the k-pair stride of their
-// phase table: phase[c][k] = e^{+i k2(k).L_c}, zero for k >= nkpi
+// (passes of equal width, at most 28; a class of up to 28 takes one pass of
+// exactly nkpi), and the k-pair stride of their phase table:
+// phase[c][k] = e^{+i k2(k).L_c}, zero for k >= nkpi
 constexpr int kKphKbMax = 28;
 __host__ __device__ inline int kphase_kb(int nkpi) {
   const int npass = (nkpi + kKphKbMax - 1) / kKphKbMax;
-  const int per = (nkpi + npass - 1) / npass;
-  return (per + 3) / 4 * 4;
+  return (nkpi + npass - 1) / npass;
 }
 __host__ __device__ inline int kphase_kpad(int nkpi) {
   const int kb = kphase_kb(nkpi);

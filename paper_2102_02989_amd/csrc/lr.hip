@@ -446,31 +446,24 @@ __global__ __launch_bounds__(256) void kphase_kernel(const double *__restrict__ 
   }
 }
 
-#define KPH_DISPATCH(KERNEL, ...)                                                                   \
-  switch (kphase_kb(nkpi)) {                                                                        \
-    case 4: hipLaunchKernelGGL(KERNEL(4), grid, dim3(256), 0, stream, __VA_ARGS__); break;          \
-    case 8: hipLaunchKernelGGL(KERNEL(8), grid, dim3(256), 0, stream, __VA_ARGS__); break;          \
-    case 12: hipLaunchKernelGGL(KERNEL(12), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
-    case 16: hipLaunchKernelGGL(KERNEL(16), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
-    case 20: hipLaunchKernelGGL(KERNEL(20), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
-    case 24: hipLaunchKernelGGL(KERNEL(24), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
-    default: hipLaunchKernelGGL(KERNEL(28), grid, dim3(256), 0, stream, __VA_ARGS__); break;        \
-  }
+// calls launch(std::integral_constant<int, KB>) for KB = kb, 1 <= kb <= KBT:
+// one kernel instance per pass width
+template <int KBT, class F>
+void kph_dispatch(int kb, F &&launch) {
+  if (kb == KBT) launch(std::integral_constant<int, KBT>{});
+  else if constexpr (KBT > 1) kph_dispatch<KBT - 1>(kb, launch);
+}
 
 hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32, double *Bhi, int nq_hi, int nk,
                          int nkpi, int nq, int64_t nmn, hipStream_t stream) {
   const int64_t ne = (int64_t)nq * nmn;
   if (ne == 0 || nkpi == 0) return hipSuccess;
   const dim3 grid((unsigned)((ne + 255) / 256));
-#define KPH_F32(kb) kphase_kernel<true, kb>
-#define KPH_F64(kb) kphase_kernel<false, kb>
-  if (f32) {
-    KPH_DISPATCH(KPH_F32, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn)
-  } else {
-    KPH_DISPATCH(KPH_F64, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn)
-  }
-#undef KPH_F32
-#undef KPH_F64
+  kph_dispatch<kKphKbMax>(kphase_kb(nkpi), [&](auto kbc) {
+    constexpr int KB = decltype(kbc)::value;
+    if (f32) hipLaunchKernelGGL(kphase_kernel<true, KB>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+    else hipLaunchKernelGGL(kphase_kernel<false, KB>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+  });
   return hipGetLastError();
 }
 
@@ -820,12 +813,13 @@ hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *X
   const int nb = f16_nblk(nq);
   const int64_t n = nmn * nb * kF16Blk;
   const dim3 grid((unsigned)((n + 255) / 256));
-#define KPH_SPLIT(kb) kphase_split_kernel<kb>
-  KPH_DISPATCH(KPH_SPLIT, I, phase, Xb, Eb, Bhi, nq_hi, nk, nkpi, nq, nb, nmn)
-#undef KPH_SPLIT
+  kph_dispatch<kKphKbMax>(kphase_kb(nkpi), [&](auto kbc) {
+    constexpr int KB = decltype(kbc)::value;
+    hipLaunchKernelGGL(kphase_split_kernel<KB>, grid, dim3(256), 0, stream, I, phase, Xb, Eb, Bhi, nq_hi, nk, nkpi, nq,
+                       nb, nmn);
+  });
   return hipGetLastError();
 }
-#undef KPH_DISPATCH
 
 // LDS stage of one block: the A and B tiles (64 rows x 256 bytes each, row r's
 // 16-byte chunk c = 4 plane + part stored at chunk position c ^ (r % 16), so
