@@ -461,8 +461,8 @@ hipError_t launch_kphase(const double *I, const double *phase, void *B, bool f32
   const dim3 grid((unsigned)((ne + 255) / 256));
   kph_dispatch<kKphKbMax>(kphase_kb(nkpi), [&](auto kbc) {
     constexpr int KB = decltype(kbc)::value;
-    if (f32) hipLaunchKernelGGL(kphase_kernel<true, KB>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
-    else hipLaunchKernelGGL(kphase_kernel<false, KB>, grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+    if (f32) hipLaunchKernelGGL((kphase_kernel<true, KB>), grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
+    else hipLaunchKernelGGL((kphase_kernel<false, KB>), grid, dim3(256), 0, stream, I, phase, B, Bhi, nq_hi, nk, nkpi, nq, nmn);
   });
   return hipGetLastError();
 }
@@ -815,7 +815,7 @@ hipError_t launch_kphase_split(const double *I, const double *phase, uint16_t *X
   const dim3 grid((unsigned)((n + 255) / 256));
   kph_dispatch<kKphKbMax>(kphase_kb(nkpi), [&](auto kbc) {
     constexpr int KB = decltype(kbc)::value;
-    hipLaunchKernelGGL(kphase_split_kernel<KB>, grid, dim3(256), 0, stream, I, phase, Xb, Eb, Bhi, nq_hi, nk, nkpi, nq,
+    hipLaunchKernelGGL((kphase_split_kernel<KB>), grid, dim3(256), 0, stream, I, phase, Xb, Eb, Bhi, nq_hi, nk, nkpi, nq,
                        nb, nmn);
   });
   return hipGetLastError();
