@@ -383,6 +383,13 @@ const char *rsgdf_last_error(void);
 /* Library version string. */
 const char *rsgdf_version(void);
 
+/* Hash of the sources the library was built from (16 hex digits: SHA-256
+ * over the files of csrc/ and include/, by name and content), or "unknown"
+ * for a build outside the package's build script.  The Python binding
+ * compares it with the sources on disk and refuses a stale library.  Static
+ * string, owned by the library. */
+const char *rsgdf_source_hash(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import concurrent.futures
+import hashlib
 import os
 import shutil
 import subprocess
@@ -14,6 +15,21 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librsgdf.so")
 SOURCES = ["sr3c.hip", "fold.hip", "lr.hip", "learned.hip", "j2c.hip", "df.hip", "coulomb.hip", "capi.cpp"]
 ARCH = os.environ.get("RSGDF_ARCH", "gfx950")
+
+
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) over the library's sources: every file of
+    csrc/ and the public headers, by name and content.  The build bakes it into
+    the library (rsgdf_source_hash) and the binding compares it on load."""
+    h = hashlib.sha256()
+    inc = os.path.join(ROOT, "include")
+    for d in (CSRC, inc):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".cpp", ".h")):
+                h.update(f.encode() + b"\0")
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def hipcc() -> str:
@@ -29,9 +45,9 @@ def flags():
             "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, defs=()) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *flags(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *flags(), *defs, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -40,8 +56,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    defs = [f'-DRSGDF_SOURCE_HASH="{source_hash()}"']
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, defs), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -886,6 +886,12 @@ const char *rsgdf_last_error(void) { return g_err.c_str(); }
 
 const char *rsgdf_version(void) { return "rsgdf-mi355x 0.1 (gfx950)"; }
 
+// set by the build script from the sources it compiled
+#ifndef RSGDF_SOURCE_HASH
+#define RSGDF_SOURCE_HASH "unknown"
+#endif
+const char *rsgdf_source_hash(void) { return RSGDF_SOURCE_HASH; }
+
 int rsgdf_release_cache(void) {
   int cur = 0;
   HIPCHK(hipGetDevice(&cur));

@@ -155,8 +155,22 @@ def library():
         L.rsgdf_release_cache.argtypes = []
         L.rsgdf_last_error.restype = ctypes.c_char_p
         L.rsgdf_version.restype = ctypes.c_char_p
+        L.rsgdf_source_hash.restype = ctypes.c_char_p
+        _check_fresh(L)
         _lib = L
     return _lib
+
+
+def _check_fresh(L) -> None:
+    """Refuse a library built from other sources than the ones in the tree:
+    a stale build would test code that is not the committed one."""
+    from . import build as _build
+    if not os.path.isdir(_build.CSRC):
+        return
+    built, now = L.rsgdf_source_hash().decode(), _build.source_hash()
+    if built != now:
+        raise RsgdfError(-5, f"{_LIB_PATH} was built from other sources (library {built}, "
+                             f"tree {now}); rebuild it with __graft_entry__.build()")
 
 
 def version() -> str:

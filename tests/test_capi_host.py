@@ -82,3 +82,21 @@ def test_product_path_has_no_fallback(monkeypatch):
     monkeypatch.setattr(R, "_lib", None)
     with pytest.raises(R.RsgdfError):
         R.library()
+
+
+def test_library_matches_tree_sources():
+    """The library records the hash of the sources it was built from; the
+    loaded one is the tree's, and a library built from other sources is
+    refused rather than run."""
+    import paper_2102_02989_amd.build as B
+    import paper_2102_02989_amd.rsgdf as R
+    assert P.library().rsgdf_source_hash().decode() == B.source_hash()
+
+
+def test_stale_library_is_refused(monkeypatch):
+    import paper_2102_02989_amd.build as B
+    import paper_2102_02989_amd.rsgdf as R
+    monkeypatch.setattr(R, "_lib", None)
+    monkeypatch.setattr(B, "source_hash", lambda: "0000000000000000")
+    with pytest.raises(R.RsgdfError, match="other sources"):
+        R.library()

@@ -29,8 +29,12 @@ def _runtime(name):
 def sanitized_lib(tmp_path_factory):
     if not _runtime("libasan.so") or not os.path.isdir("/opt/rocm/include/hip"):
         pytest.skip("g++ with libasan and the HIP headers are needed for the host sanitizer build")
+    from paper_2102_02989_amd.build import source_hash
     out = str(tmp_path_factory.mktemp("hostsan") / "librsgdf_hostsan.so")
+    # built from the tree's capi.cpp, so it carries the tree's source hash
+    # (the binding checks it on load)
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__",
+           f'-DRSGDF_SOURCE_HASH="{source_hash()}"',
            "-I/opt/rocm/include",
            # the two HIP-compiler spellings the host driver uses, for a plain C++ compiler
            "-D__align__(n)=__attribute__((aligned(n)))", "-DHIP_SYMBOL(x)=x",
