@@ -374,8 +374,12 @@ hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *a
 // thread per (mn, q) element.  The k-pairs of the class are taken KB at a time
 // with their sums in registers, KB chosen per launch so that one pass covers
 // up to 28 k-pairs and the passes are even (each pass reads I once); the
-// phases are uniform over the wave (scalar loads), and KPH_CB image classes'
-// loads are in flight before their multiply-adds.  F32: B is written as FP32
+// phases are uniform over the wave (scalar loads).  The cells are taken
+// KPH_CB at a time, and the next group's I loads are issued before the
+// current group's multiply-adds (two register sets in turn), so a wave always
+// has loads in flight; the loop body has no branch (cell indices are clamped
+// into range, which keeps every load in bounds, and the values of cells past
+// nk are zeroed), so the compiler cannot sink a load next to its first use.  F32: B is written as FP32
 // pairs (the operand format of the FP32 contraction, half the bytes), and the
 // first nq_hi columns also in FP64 into Bhi[kpi][mn][nq_hi] (the columns the
 // reduced-precision forms contract in FP64).
@@ -388,28 +392,45 @@ __device__ __forceinline__ void kphase_sums(const double *__restrict__ I, int64_
 #pragma unroll
   for (int kk = 0; kk < KB; ++kk) sr[kk] = si[kk] = 0.0;
   if (!ok) return;
-  for (int c0 = 0; c0 < nk; c0 += KPH_CB) {
-    double ir[KPH_CB], ii[KPH_CB];
+  // group g = cells [KPH_CB g, KPH_CB (g + 1)); two register sets in turn
+  auto load = [&](int g, double (&xr)[KPH_CB], double (&xi)[KPH_CB]) {
 #pragma unroll
     for (int j = 0; j < KPH_CB; ++j) {
-      const int c = (c0 + j < nk) ? c0 + j : c0;  // clamped: in-bounds, unused below
-      ir[j] = I[2 * ((int64_t)c * ne + src)];
-      ii[j] = I[2 * ((int64_t)c * ne + src) + 1];
+      const int64_t o = 2 * ((int64_t)min(KPH_CB * g + j, nk - 1) * ne + src);
+      xr[j] = I[o];
+      xi[j] = I[o + 1];
     }
+  };
+  auto madd = [&](int g, const double (&xr)[KPH_CB], const double (&xi)[KPH_CB]) {
 #pragma unroll
     for (int j = 0; j < KPH_CB; ++j) {
-      if (c0 + j >= nk) break;
-      const int c = c0 + j;
+      const int c = KPH_CB * g + j;
+      const double vr = c < nk ? xr[j] : 0.0, vi = c < nk ? xi[j] : 0.0;
       // the pass's KB phases of cell c are contiguous (zero past nkpi)
-      const double *ph = phase + 2 * ((int64_t)c * kpad + k0);
+      const double *ph = phase + 2 * ((int64_t)min(c, nk - 1) * kpad + k0);
 #pragma unroll
       for (int kk = 0; kk < KB; ++kk) {
         const double pr = ph[2 * kk], pi = ph[2 * kk + 1];
-        sr[kk] += pr * ir[j] - pi * ii[j];
-        si[kk] += pr * ii[j] + pi * ir[j];
+        // two fused multiply-adds per real sum (the written form compiles to
+        // a multiply, a fused multiply-add and an add)
+        sr[kk] = fma(pr, vr, sr[kk]);
+        sr[kk] = fma(-pi, vi, sr[kk]);
+        si[kk] = fma(pr, vi, si[kk]);
+        si[kk] = fma(pi, vr, si[kk]);
       }
     }
+  };
+  const int ng = (nk + KPH_CB - 1) / KPH_CB;
+  double ar[KPH_CB], ai[KPH_CB], br[KPH_CB], bi[KPH_CB];
+  load(0, ar, ai);
+  int g = 0;
+  for (; g + 1 < ng; g += 2) {
+    load(g + 1, br, bi);
+    madd(g, ar, ai);
+    load(g + 2, ar, ai);  // past the last group: clamped, in bounds, unused
+    madd(g + 1, br, bi);
   }
+  if (g < ng) madd(g, ar, ai);
 }
 
 template <bool F32, int KB>
