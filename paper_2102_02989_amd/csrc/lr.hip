@@ -352,21 +352,33 @@ hipError_t launch_pairft_binned(const PairFTParams &pp, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// amax[q] = max_P |A[P][q]| over the aux functions, one thread per q.
-__global__ void amax_kernel(const double *__restrict__ A, int64_t lda, int naux, int nq, double *__restrict__ amax) {
-  const int iq = blockIdx.x * blockDim.x + threadIdx.x;
-  if (iq >= nq) return;
+// amax[q] = max_P (|Re A[P][q]| + |Im A[P][q]|) over the aux functions.
+__global__ __launch_bounds__(1024) void amax_kernel(const double *__restrict__ A, int64_t lda, int naux, int nq,
+                                                  double *__restrict__ amax) {
+  // 64 columns per workgroup; wave w takes rows w, w + 16, ... (each load
+  // instruction reads 64 consecutive complex values), and the 16 partial
+  // maxima meet in LDS.  A maximum does not depend on the order.
+  __shared__ double part[16][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int iq = blockIdx.x * 64 + lane;
   double m = 0.0;
-  for (int P = 0; P < naux; ++P) {
-    const size_t o = (size_t)P * lda + iq;
-    m = fmax(m, fabs(A[2 * o]) + fabs(A[2 * o + 1]));
+  if (iq < nq)
+    for (int P = w; P < naux; P += 16) {
+      const size_t o = (size_t)P * lda + iq;
+      m = fmax(m, fabs(A[2 * o]) + fabs(A[2 * o + 1]));
+    }
+  part[w][lane] = m;
+  __syncthreads();
+  if (w == 0 && iq < nq) {
+#pragma unroll
+    for (int j = 1; j < 16; ++j) m = fmax(m, part[j][lane]);
+    amax[iq] = m;
   }
-  amax[iq] = m;
 }
 
 hipError_t launch_amax(const double *A, int64_t lda, int naux, int nq, double *amax, hipStream_t stream) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(amax_kernel, dim3((nq + 255) / 256), dim3(256), 0, stream, A, lda, naux, nq, amax);
+  hipLaunchKernelGGL(amax_kernel, dim3((nq + 63) / 64), dim3(1024), 0, stream, A, lda, naux, nq, amax);
   return hipGetLastError();
 }
 
