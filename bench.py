@@ -12,9 +12,9 @@ contraction.
 Two forms are timed on the same input:
   plain  : rsgdf_build_j3c, every stage FP64, rigorous screening;
   chosen : rsgdf_build_j3c_ex with the G-space contraction on reduced-
-           precision matrix cores (each operand scaled per 32-q block by a
+           precision matrix cores (each operand scaled per 64-q group by a
            power of two and split into two FP16 numbers, three FP16
-           products per real product accumulated in FP32 over the block and
+           products per real product accumulated in FP32 over the group and
            promoted to FP64; the 32 innermost q of each class in FP64) and
            learned screening with the committed network at its calibrated
            margin (the largest under-prediction on held-out samples).  Boys,
@@ -212,7 +212,7 @@ def main():
                          "reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus N > 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -64,7 +64,7 @@ extern "C" {
  * matrix product per k12 class).  In every form the transforms, the kernel
  * weight, the Bloch phases and the output are FP64; the reduced forms take
  * the 32 smallest-|q| vectors of each class in FP64 and add each 16-q FP32
- * partial (32 q in the F16X3 form) into FP64 registers. */
+ * partial (64 q in the F16X3 form) into FP64 registers. */
 #define RSGDF_FP64 0   /* plain: FP64 matrix-core products                          */
 #define RSGDF_FP32 1   /* operands rounded to FP32, FP32 matrix-core products        */
 #define RSGDF_F16X3 2  /* operands scaled per row by 2^e, split hi + lo in FP16,

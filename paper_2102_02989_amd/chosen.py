@@ -2,9 +2,9 @@
 tests check against the oracle (one definition for both).
 
   * G-space contraction on reduced-precision matrix cores (default: each
-    operand scaled per 32-q block by a power of two and split into two FP16
+    operand scaled per 64-q group by a power of two and split into two FP16
     numbers, three FP16 products per real product accumulated in FP32 over
-    the block and promoted to FP64; the 32 innermost q of each k12 class in
+    the group and promoted to FP64; the 32 innermost q of each k12 class in
     FP64);
   * learned screening with the committed network at its calibrated margin:
     the largest under-prediction (log10 units) on the held-out 20% of the
