@@ -33,7 +33,7 @@ def test_traffic_record_follows_the_sources(family, monkeypatch):
     assert rec["hbm_bytes_per_launch"] > rec["algorithmic_bytes_per_launch"] > 0
     monkeypatch.setattr(bench, "source_hash", lambda fam, h=rec["source_hash"]: h)
     assert bench.recorded_traffic(family, "C3") == rec["hbm_bytes_per_launch"]
-    assert bench.recorded_traffic(family, "C2") is None  # no record for that workload
+    assert bench.recorded_traffic(family, "C5") is None  # no record for that workload
     monkeypatch.setattr(bench, "source_hash", lambda fam: "0" * 16)
     assert bench.recorded_traffic(family, "C3") is None  # the kernel changed since
 
